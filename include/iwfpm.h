@@ -1,0 +1,188 @@
+/*
+ * iwfpm.h - C ABI of the irrational-window-filter projection method (IWFPM)
+ * Hamiltonian apply and block eigensolver for AMD gfx950 (MI355X).
+ *
+ * The operator (paper, Sec. 4.1): for the quasiperiodic Schroedinger problem
+ *     H u = -1/2 Laplace u + v u = E u,
+ * discretised on the irrational window W_{K,L} (Sec. 3.1, eq:non-tensor) and
+ * moved onto the lifted grid K*_{K,L} by the index-shift map (Sec. 3.2,
+ * eq:index mod, eq:inverse1-eq:inverse3), the matrix is
+ *     H~ = Lambda + F V F^{-1},   F = T F*   (Sec. 3.3, eq:F),
+ * with Lambda = 1/2 |2 pi P k|^2 on the true labels k = rho^{-1}(k*) and V the
+ * parent potential sampled on the dual grid G_{K,L} (eq:G_KL).  F* is the
+ * standard n-D DFT with the 1/N factor of the discrete inner product
+ * eq:new_inner_product.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - P is d x n, row-major, float64, in the convention where the kinetic
+ *    energy of mode k is 1/2 |2 pi P k|^2.  (The paper's examples carry the
+ *    factor 2 pi inside P; divide it out.)  Columns 1..d form P_I, which must
+ *    be invertible (Sec. 3.1); Q = P_I^{-1} P_II.
+ *  - K has d entries, L has n-d entries, all >= 1 (Remark after Fig. 1).
+ *  - Grid extents ext = (2L_1..2L_{n-d}, 2K_1..2K_d); N = prod(ext) is the
+ *    number of degrees of freedom (Sec. 4.2, DOF).
+ *  - Vectors are complex float64, interleaved (re, im), N entries each; a
+ *    block of nvec vectors is column-major (vector j starts at j*N).
+ *  - GRID order: entry i is the coefficient of k* where i is the row-major
+ *    index of an array of shape ext, i.e. the k_II axes are slow and the k_I
+ *    axes fast (k_d fastest).  WINDOW order: the same, except that along each
+ *    k_I axis the entries run over the true labels k_j ascending from the
+ *    slice's lower end -K_j - floor((Q k_II)_j), instead of over k*_j.
+ *  - The potential is given by its parent-function Fourier modes
+ *    (Sec. 4.1: V(y) = sum_m Vhat_m e^{i m.y}): n_modes integer n-vectors m
+ *    (paper order: m_1..m_n) and complex coefficients Vhat (re, im pairs).
+ *    V must be real: every m needs -m with the conjugate coefficient.
+ *  - Every function returns an iwfpm_status.  Arguments are checked before any
+ *    device work; on error nothing has been enqueued.  No function throws or
+ *    aborts across the ABI.
+ *  - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *  - The caller owns every vector buffer and the stream; the plan owns its
+ *    tables and device workspace until iwfpm_destroy.  A plan is not
+ *    re-entrant: calls on one plan must not overlap.
+ */
+#ifndef IWFPM_H
+#define IWFPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct iwfpm_plan_s* iwfpm_plan_t;
+
+typedef enum {
+    IWFPM_OK = 0,
+    IWFPM_ERR_ARG = -1,            /* bad argument (sizes, NULL pointers, ranges) */
+    IWFPM_ERR_SINGULAR_PI = -2,    /* P_I not invertible, or P has rank < d (Def. 2.1) */
+    IWFPM_ERR_NONHERMITIAN = -3,   /* potential modes do not describe a real V */
+    IWFPM_ERR_UNSUPPORTED = -4,    /* valid input outside what this build implements */
+    IWFPM_ERR_ALLOC = -5,          /* device or host allocation failed */
+    IWFPM_ERR_DEVICE = -6,         /* a HIP call failed */
+    IWFPM_ERR_NUMERIC = -7,        /* NaN/Inf or a breakdown the solver could not recover */
+    IWFPM_ERR_NOCONV = -8,         /* maxit reached; partial results are returned */
+    IWFPM_ERR_WEIGHTS = -9,        /* learned preconditioner weights missing or invalid */
+    IWFPM_ERR_NODEVICE = -10       /* the plan was created host-only (device = -1) */
+} iwfpm_status;
+
+enum { IWFPM_PREC_FP64 = 0, IWFPM_PREC_FP32 = 1 };
+/* How the sheared offset q = Q k_II enters the window:
+ * EXACT    k_I + q in [-K, K)               (Sec. 3.1, the method as defined)
+ * ROUNDED  k_I + floor(q + 1/2) in [-K, K)  (the reading that reproduces Table 1's cond(H))
+ * PM       k_I in [-K, K)                   (shear off: the projection method's rectangle) */
+enum { IWFPM_WINDOW_EXACT = 0, IWFPM_WINDOW_ROUNDED = 1, IWFPM_WINDOW_PM = 2 };
+enum { IWFPM_ORDER_GRID = 0, IWFPM_ORDER_WINDOW = 1 };
+enum { IWFPM_SCHED_AUTO = 0, IWFPM_SCHED_FUSED = 1, IWFPM_SCHED_THREEPASS = 2 };
+enum { IWFPM_PRECOND_NONE = 0, IWFPM_PRECOND_PLAIN = 1, IWFPM_PRECOND_LEARNED = 2 };
+
+typedef struct {
+    int precision;       /* IWFPM_PREC_*: arithmetic of the potential convolution.
+                            FP32 keeps the kinetic term, the boundary vectors and
+                            everything in the eigensolver in float64. */
+    int window_variant;  /* IWFPM_WINDOW_* */
+    int order;           /* IWFPM_ORDER_* */
+    int device;          /* HIP device ordinal; -1 = host-only plan (geometry queries only) */
+    int schedule;        /* IWFPM_SCHED_*; AUTO picks FUSED when the grid fits one workgroup */
+    int split;           /* THREEPASS: number of leading grid axes in the middle pass; 0 = auto */
+    int tile;            /* THREEPASS: middle-pass tile width (columns); 0 = auto */
+} iwfpm_opts;
+
+/* Fill *opts with the defaults: FP64, EXACT, GRID, device 0, AUTO, 0, 0. */
+void iwfpm_default_opts(iwfpm_opts* opts);
+
+/* Human-readable name of a status code (static storage). */
+const char* iwfpm_status_string(int status);
+
+/*
+ * iwfpm_plan - Alg. 1 steps 1-2 set-up: builds K_{K,L}, K*_{K,L} and the
+ * per-slice offsets of rho^{-1} (eq:inverse1-3), the kinetic tables, the
+ * potential on G_{K,L} (eq:G_KL) and the FFT schedule, and uploads them to
+ * the device.  Host inputs (P, K, L, modes, vhat) are copied; the caller may
+ * free them on return.  opts may be NULL (defaults).  Blocking.
+ * Errors: ERR_ARG (d < 1, n <= d, n > 8, K/L < 1, grid extent unsupported),
+ * ERR_SINGULAR_PI, ERR_NONHERMITIAN, ERR_DEVICE / ERR_ALLOC.
+ */
+int iwfpm_plan(int d, int n, const double* P, const int32_t* K, const int32_t* L,
+               int n_modes, const int32_t* modes, const double* vhat,
+               const iwfpm_opts* opts, iwfpm_plan_t* out);
+
+/* Release the plan and its device memory (synchronises its device first). */
+int iwfpm_destroy(iwfpm_plan_t plan);
+
+/* Number of degrees of freedom N = (2K)^d (2L)^{n-d} (Sec. 4.2). */
+int iwfpm_dof(iwfpm_plan_t plan, int64_t* N);
+
+/* Grid extents in storage-axis order (2L_1..2L_{n-d}, 2K_1..2K_d); ext has n entries. */
+int iwfpm_grid_shape(iwfpm_plan_t plan, int32_t* ext);
+
+/* True labels k = rho^{-1}(k*) (eq:inverse1-3), paper order k_1..k_n, for every
+ * vector entry in the plan's vector order.  k_out: host, N*n int32, row i = entry i. */
+int iwfpm_indices(iwfpm_plan_t plan, int32_t* k_out);
+
+/* Diagonal Lambda_i = 1/2 |2 pi P k_i|^2 (Sec. 4.1) in vector order; out: host, N float64. */
+int iwfpm_kinetic(iwfpm_plan_t plan, double* out);
+
+/* Upper bound of ||H~||_2: max Lambda + sum_m |Vhat_m|. */
+int iwfpm_norm_bound(iwfpm_plan_t plan, double* out);
+
+/*
+ * iwfpm_apply - Hpsi = Lambda psi + F V F^{-1} psi (Sec. 4.1) for nvec vectors.
+ * psi, hpsi: device pointers, complex float64, N x nvec column-major, in the
+ * plan's vector order; they must not overlap.  Runs the window gather (T^{-1}),
+ * the inverse lifted FFT, the product with V, the forward FFT and the scatter
+ * T fused with the kinetic term, all on `stream` (hipStream_t).  Asynchronous:
+ * returns after enqueueing.  nvec = 0 is a no-op.
+ * Errors: ERR_ARG (NULL pointers, nvec < 0), ERR_NODEVICE, ERR_DEVICE.
+ */
+int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* stream);
+
+/* As iwfpm_apply but forcing the convolution precision (IWFPM_PREC_*). */
+int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
+                     int precision, void* stream);
+
+typedef struct {
+    int nev;            /* eigenpairs wanted (lowest), >= 1 */
+    int block;          /* LOBPCG block size m >= nev; 0 = nev + max(2, nev/4) */
+    double tol;         /* target backward error eta (see iwfpm_eigs) */
+    int maxit;          /* iteration limit */
+    int precond;        /* IWFPM_PRECOND_* */
+    uint64_t seed;      /* start block seed when x0 == NULL */
+    int polish;         /* FP32 plans: 1 = finish with float64 applies once FP32 stalls */
+} iwfpm_eigs_opts;
+
+typedef struct {
+    int iterations;     /* LOBPCG iterations */
+    int64_t matvecs;    /* single-vector applies (all precisions) */
+    int converged;      /* pairs with eta <= tol at exit */
+    int restarts;       /* Rayleigh-Ritz restarts without the P block */
+    int fallback;       /* learned preconditioner replaced by the plain one */
+    int polished;       /* iterations done with float64 applies on an FP32 plan */
+    double t_total;     /* seconds, wall */
+    double t_apply;     /* seconds in applies (device events) */
+} iwfpm_stats;
+
+void iwfpm_default_eigs_opts(iwfpm_eigs_opts* opts);
+
+/*
+ * iwfpm_eigs - lowest nev eigenpairs of H~ by block LOBPCG (Sec. 4.1: the
+ * solver, with the diagonal preconditioner of eq:precond applied to
+ * H~ + sigma I, sigma = max(0, sum_{m != 0} |Vhat_m| - Vhat_0) so that the
+ * diagonal is positive).
+ * Convergence: eta_i = ||H~ x_i - theta_i x_i|| / ((||H~||_est + |theta_i|) ||x_i||)
+ * <= tol, with ||H~||_est from iwfpm_norm_bound; the final eta is always
+ * evaluated with float64 applies.
+ * x0: device, N x m start block (m = block size) or NULL for a seeded random start.
+ * evals, eta: host, nev float64 (eta may be NULL).  evecs: device, N x nev
+ * complex float64, or NULL.  stats may be NULL.  Blocking (synchronises stream).
+ * Errors: ERR_ARG, ERR_NODEVICE, ERR_NUMERIC, ERR_NOCONV (results of the last
+ * iterate are still written), ERR_WEIGHTS (LEARNED without loaded weights).
+ */
+int iwfpm_eigs(iwfpm_plan_t plan, const iwfpm_eigs_opts* opts, const void* x0,
+               double* evals, void* evecs, double* eta, iwfpm_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IWFPM_H */

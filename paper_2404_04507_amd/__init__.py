@@ -1,0 +1,269 @@
+"""Python binding of libiwfpm (the IWFPM Hamiltonian apply and eigensolver for gfx950).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Vectors are torch complex128 tensors on the plan's GPU, shaped (nvec, N)
+(each vector contiguous, i.e. the library's N x nvec column-major block) or (N,).
+torch supplies device memory and the stream; nothing here computes.
+
+The library is loaded on first use; if it has not been built the binding
+raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = ["Plan", "IwfpmError", "load_library", "library_path", "EXPORTED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_destroy", "iwfpm_dof",
+            "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
+            "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs"]
+
+PREC = {"fp64": 0, "fp32": 1}
+WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
+ORDER = {"grid": 0, "window": 1}
+SCHED = {"auto": 0, "fused": 1, "threepass": 2}
+PRECOND = {"none": 0, "plain": 1, "learned": 2}
+
+
+class IwfpmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib().iwfpm_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("window_variant", ctypes.c_int), ("order", ctypes.c_int),
+                ("device", ctypes.c_int), ("schedule", ctypes.c_int), ("split", ctypes.c_int),
+                ("tile", ctypes.c_int)]
+
+
+class _EigsOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("precond", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("polish", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("matvecs", ctypes.c_int64), ("converged", ctypes.c_int),
+                ("restarts", ctypes.c_int), ("fallback", ctypes.c_int), ("polished", ctypes.c_int),
+                ("t_total", ctypes.c_double), ("t_apply", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libiwfpm.so")
+
+
+def load_library():
+    """Load libiwfpm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2404_04507_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    lib.iwfpm_default_opts.argtypes = [ctypes.POINTER(_Opts)]
+    lib.iwfpm_default_opts.restype = None
+    lib.iwfpm_status_string.argtypes = [ctypes.c_int]
+    lib.iwfpm_status_string.restype = ctypes.c_char_p
+    lib.iwfpm_plan.argtypes = [ctypes.c_int, ctypes.c_int, dp, ip, ip, ctypes.c_int, ip, dp,
+                               ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
+    lib.iwfpm_destroy.argtypes = [vp]
+    lib.iwfpm_dof.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.iwfpm_grid_shape.argtypes = [vp, ip]
+    lib.iwfpm_indices.argtypes = [vp, ip]
+    lib.iwfpm_kinetic.argtypes = [vp, dp]
+    lib.iwfpm_norm_bound.argtypes = [vp, dp]
+    lib.iwfpm_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.iwfpm_apply_prec.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
+    lib.iwfpm_default_eigs_opts.restype = None
+    lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
+    for name in EXPORTED:
+        if name not in ("iwfpm_default_opts", "iwfpm_status_string", "iwfpm_default_eigs_opts"):
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _lib():
+    return load_library()
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise IwfpmError(status, where)
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+@dataclass
+class EigsResult:
+    evals: np.ndarray
+    evecs: object          # torch tensor (nev, N) complex128 or None
+    eta: np.ndarray
+    iterations: int
+    matvecs: int
+    converged: int
+    restarts: int
+    fallback: int
+    polished: int
+    t_total: float
+    t_apply: float
+    status: int
+
+
+class Plan:
+    """An IWFPM plan (wraps iwfpm_plan_t).
+
+    P: d x n (kinetic 1/2 |2 pi P k|^2), K: d ints, L: n-d ints,
+    modes: n_modes x n ints, vhat: n_modes complex.
+    """
+
+    def __init__(self, P, K, L, modes, vhat, *, precision="fp64", window="exact", order="grid",
+                 device=0, schedule="auto", split=0, tile=0):
+        lib = _lib()
+        P = _f64(np.atleast_2d(P))
+        d, n = P.shape
+        K = _i32(np.atleast_1d(K))
+        L = _i32(np.atleast_1d(L))
+        modes = _i32(np.asarray(modes).reshape(-1, n))
+        vh = np.asarray(vhat, dtype=np.complex128).reshape(-1)
+        vri = _f64(np.stack([vh.real, vh.imag], axis=1).reshape(-1)) if vh.size else _f64(np.zeros(2))
+        opts = _Opts()
+        lib.iwfpm_default_opts(ctypes.byref(opts))
+        opts.precision = PREC[precision]
+        opts.window_variant = WINDOW[window]
+        opts.order = ORDER[order]
+        opts.device = int(device)
+        opts.schedule = SCHED[schedule]
+        opts.split = int(split)
+        opts.tile = int(tile)
+        h = ctypes.c_void_p()
+        st = lib.iwfpm_plan(d, n, _ptr(P, ctypes.c_double), _ptr(K, ctypes.c_int32), _ptr(L, ctypes.c_int32),
+                            modes.shape[0], _ptr(modes, ctypes.c_int32), _ptr(vri, ctypes.c_double),
+                            ctypes.byref(opts), ctypes.byref(h))
+        _check(st, "iwfpm_plan")
+        self._h = h
+        self.d, self.n = d, n
+        self.device = int(device)
+        self.precision = precision
+        N = ctypes.c_int64()
+        _check(lib.iwfpm_dof(h, ctypes.byref(N)), "iwfpm_dof")
+        self.N = int(N.value)
+        ext = np.zeros(n, dtype=np.int32)
+        _check(lib.iwfpm_grid_shape(h, _ptr(ext, ctypes.c_int32)), "iwfpm_grid_shape")
+        self.ext = tuple(int(x) for x in ext)
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls(prob.P, prob.K, prob.L, prob.modes, prob.vhat, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().iwfpm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- host queries --------------------------------------------------------
+    def indices(self) -> np.ndarray:
+        out = np.zeros((self.N, self.n), dtype=np.int32)
+        _check(_lib().iwfpm_indices(self._h, _ptr(out, ctypes.c_int32)), "iwfpm_indices")
+        return out
+
+    def kinetic(self) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.float64)
+        _check(_lib().iwfpm_kinetic(self._h, _ptr(out, ctypes.c_double)), "iwfpm_kinetic")
+        return out
+
+    def norm_bound(self) -> float:
+        out = ctypes.c_double()
+        _check(_lib().iwfpm_norm_bound(self._h, ctypes.byref(out)), "iwfpm_norm_bound")
+        return out.value
+
+    # -- device --------------------------------------------------------------
+    def _check_block(self, x):
+        import torch
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.complex128 or not x.is_cuda:
+            raise TypeError("vectors must be complex128 CUDA tensors")
+        if x.shape[-1] != self.N or not x.is_contiguous():
+            raise ValueError(f"vectors must be contiguous with last dimension N={self.N}")
+        return 1 if x.dim() == 1 else int(np.prod(x.shape[:-1]))
+
+    def apply(self, psi, out=None, precision=None, stream=None):
+        """H psi; psi (nvec, N) or (N,) complex128 on the plan's GPU."""
+        import torch
+        nvec = self._check_block(psi)
+        if out is None:
+            out = torch.empty_like(psi)
+        else:
+            self._check_block(out)
+        prec = PREC[precision] if precision is not None else PREC[self.precision]
+        st = _lib().iwfpm_apply_prec(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     nvec, prec, _stream_handle(stream))
+        _check(st, "iwfpm_apply")
+        return out
+
+    def eigs(self, nev, tol=1e-8, maxit=500, block=0, precond="plain", x0=None, seed=2404045070,
+             polish=True, want_vectors=True, stream=None, allow_noconv=False) -> EigsResult:
+        import torch
+        lib = _lib()
+        o = _EigsOpts()
+        lib.iwfpm_default_eigs_opts(ctypes.byref(o))
+        o.nev, o.block, o.tol, o.maxit = int(nev), int(block), float(tol), int(maxit)
+        o.precond, o.seed, o.polish = PRECOND[precond], int(seed), int(bool(polish))
+        evals = np.zeros(nev)
+        eta = np.zeros(nev)
+        vecs = None
+        if want_vectors:
+            vecs = torch.empty((nev, self.N), dtype=torch.complex128, device=f"cuda:{self.device}")
+        x0p = ctypes.c_void_p(x0.data_ptr()) if x0 is not None else ctypes.c_void_p()
+        if x0 is not None:
+            self._check_block(x0)
+        stats = _Stats()
+        st = lib.iwfpm_eigs(self._h, ctypes.byref(o), x0p, _ptr(evals, ctypes.c_double),
+                            ctypes.c_void_p(vecs.data_ptr()) if vecs is not None else ctypes.c_void_p(),
+                            _ptr(eta, ctypes.c_double), ctypes.byref(stats), _stream_handle(stream))
+        if st != 0 and not (allow_noconv and st == -8):
+            raise IwfpmError(st, "iwfpm_eigs")
+        return EigsResult(evals, vecs, eta, stats.iterations, stats.matvecs, stats.converged, stats.restarts,
+                          stats.fallback, stats.polished, stats.t_total, stats.t_apply, st)

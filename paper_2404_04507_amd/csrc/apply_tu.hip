@@ -1,0 +1,85 @@
+// apply_tu.hip - one (kernel, precision) pair of the apply, selected at
+// build time by IWFPM_TU_KERNEL (0 fused, 1 pass 1, 2 pass 2, 3 pass 3) and
+// IWFPM_TU_REAL (float or double) and IWFPM_TU_MAXS, the largest
+// axis extent the instantiated kernels transform (16, 32 or 64).
+#include "apply_kernels.hpp"
+#include "apply_launch.hpp"
+
+#ifndef IWFPM_TU_KERNEL
+#error "IWFPM_TU_KERNEL must be defined"
+#endif
+#ifndef IWFPM_TU_REAL
+#error "IWFPM_TU_REAL must be defined"
+#endif
+#ifndef IWFPM_TU_MAXS
+#error "IWFPM_TU_MAXS must be defined"
+#endif
+
+namespace iwfpm {
+
+using R = IWFPM_TU_REAL;
+constexpr int M = IWFPM_TU_MAXS;
+
+#if IWFPM_TU_KERNEL == 0
+template <>
+hipError_t launch_fused<R, M>(const DevGeom& g, const DevTabs& t, int threads, const void* psi, void* hpsi, int nvec,
+                           hipStream_t st) {
+    size_t lds = (size_t)g.N * sizeof(cplx<R>);
+    k_fused<R, M><<<dim3(nvec), dim3(threads), lds, st>>>(g, t, reinterpret_cast<const double2*>(psi),
+                                                           reinterpret_cast<double2*>(hpsi));
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_fused<R, M>(int lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_fused<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+#elif IWFPM_TU_KERNEL == 1
+template <>
+hipError_t launch_pass1<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, void* ws,
+                           int nvec, hipStream_t st) {
+    long long nslab = (long long)nvec * pd.s_out;
+    int nb = (int)((nslab + pd.slabs_per_wg - 1) / pd.slabs_per_wg);
+    size_t lds = (size_t)pd.slabs_per_wg * pd.s_in * sizeof(cplx<R>);
+    k_pass1<R, M><<<dim3(nb), dim3(pd.threads_inner), lds, st>>>(
+        g, t, pd, reinterpret_cast<const double2*>(psi), reinterpret_cast<cplx<R>*>(ws), nslab);
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_pass1<R, M>(int lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_pass1<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+#elif IWFPM_TU_KERNEL == 2
+template <>
+hipError_t launch_pass2<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, void* ws, int nvec,
+                           hipStream_t st) {
+    int ntile = (int)((pd.s_in + pd.tile - 1) / pd.tile);
+    size_t lds = (size_t)pd.s_out * pd.tile * sizeof(cplx<R>);
+    k_pass2<R, M><<<dim3(ntile * nvec), dim3(pd.threads_outer), lds, st>>>(g, t, pd,
+                                                                            reinterpret_cast<cplx<R>*>(ws));
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_pass2<R, M>(int lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_pass2<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+#elif IWFPM_TU_KERNEL == 3
+template <>
+hipError_t launch_pass3<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, const void* ws,
+                           void* hpsi, int nvec, hipStream_t st) {
+    long long nslab = (long long)nvec * pd.s_out;
+    int nb = (int)((nslab + pd.slabs_per_wg - 1) / pd.slabs_per_wg);
+    size_t lds = (size_t)pd.slabs_per_wg * pd.s_in * sizeof(cplx<R>);
+    k_pass3<R, M><<<dim3(nb), dim3(pd.threads_inner), lds, st>>>(
+        g, t, pd, reinterpret_cast<const double2*>(psi), reinterpret_cast<const cplx<R>*>(ws),
+        reinterpret_cast<double2*>(hpsi), nslab);
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_pass3<R, M>(int lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_pass3<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+#else
+#error "IWFPM_TU_KERNEL out of range"
+#endif
+
+}  // namespace iwfpm

@@ -1,0 +1,46 @@
+// internal.hpp - descriptors shared by the host plan and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace iwfpm {
+
+constexpr int kMaxAxes = 8;
+
+// Geometry of the lifted grid K*_{K,L} (Sec. 3.2) as the kernels see it.
+// Storage axes: 0..n-d-1 are the k_II axes, n-d..n-1 the k_I axes (fastest).
+struct DevGeom {
+    int n, d;
+    int order;                      // 0 grid order, 1 window order
+    int vmode;                      // 0 per-axis potential tables, 1 potential grid
+    int ext[kMaxAxes];              // extents 2L..., 2K...
+    long long stride[kMaxAxes];     // row-major element strides
+    long long N;                    // grid points per vector
+    long long nkI;                  // points per k_I slice (product of the d fastest extents)
+    int voff[kMaxAxes];             // offset of axis ax's potential table
+    double P1[kMaxAxes * kMaxAxes]; // 2 pi P_I, d x d row-major
+};
+
+// Device pointers owned by the plan.
+struct DevTabs {
+    const int* slice_a;       // per k_II slice: lower window end a_j = -K_j - floor(q_j), nslice x d
+    const double* slice_g;    // per k_II slice: 2 pi (P_II k_II)_j, nslice x d
+    const float* vtab32;      // per-axis potential tables (already divided by N)
+    const double* vtab64;
+    const float* vgrid32;     // potential on G_{K,L} divided by N (vmode 1)
+    const double* vgrid64;
+};
+
+// Three-pass schedule (see apply_kernels.hip).
+struct PassDesc {
+    int split;          // number of leading axes handled by the middle pass
+    long long s_in;     // product of the trailing n - split extents (slab size)
+    long long s_out;    // product of the leading split extents
+    int slabs_per_wg;   // passes 1 and 3: slabs per workgroup
+    int tile;           // pass 2: columns per workgroup
+    int threads_inner;  // block size of passes 1 and 3
+    int threads_outer;  // block size of pass 2
+    int xcd_remap;      // remap workgroup ids so that one XCD walks adjacent tiles
+};
+
+}  // namespace iwfpm

@@ -1,0 +1,664 @@
+// plan.cpp - iwfpm_plan and the geometry / potential set-up (Alg. 1 steps 1-2).
+//
+// Built without floating-point contraction so that the sheared offsets
+// q = Q k_II are formed exactly as written (ties at integers stay ties).
+
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "apply_launch.hpp"
+#include "sizes.hpp"
+
+using namespace iwfpm;
+
+namespace iwfpm {
+
+static const double kTwoPi = 6.283185307179586476925286766559;
+
+static bool extent_supported(int e) {
+    switch (e) {
+#define IWFPM_CASE(s) \
+    case s: return true;
+        IWFPM_EXTENTS(IWFPM_CASE)
+#undef IWFPM_CASE
+        default: return false;
+    }
+}
+
+static int extent_class(int e) { return e <= 16 ? 16 : (e <= 32 ? 32 : 64); }
+
+int dev_alloc(DeviceBuf& b, size_t bytes) {
+    dev_free(b);
+    if (bytes == 0) return IWFPM_OK;
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        b.ptr = nullptr;
+        (void)hipGetLastError();
+        return IWFPM_ERR_ALLOC;
+    }
+    b.bytes = bytes;
+    return IWFPM_OK;
+}
+
+void dev_free(DeviceBuf& b) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+// Solve P_I X = P_II by Gaussian elimination with partial pivoting (Sec. 3.1).
+static int solve_Q(int d, int n, const double* P, std::vector<double>& Q) {
+    const int m = n - d;
+    std::vector<double> A(d * d), B(d * m);
+    double scale = 0.0;
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j < d; ++j) A[i * d + j] = P[i * n + j];
+        for (int j = 0; j < m; ++j) B[i * m + j] = P[i * n + d + j];
+        for (int j = 0; j < n; ++j) scale = std::max(scale, std::fabs(P[i * n + j]));
+    }
+    if (!(scale > 0.0)) return IWFPM_ERR_SINGULAR_PI;
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (std::fabs(A[r * d + c]) > std::fabs(A[piv * d + c])) piv = r;
+        if (std::fabs(A[piv * d + c]) <= 1e-12 * scale) return IWFPM_ERR_SINGULAR_PI;
+        if (piv != c) {
+            for (int j = 0; j < d; ++j) std::swap(A[c * d + j], A[piv * d + j]);
+            for (int j = 0; j < m; ++j) std::swap(B[c * m + j], B[piv * m + j]);
+        }
+        for (int r = c + 1; r < d; ++r) {
+            double f = A[r * d + c] / A[c * d + c];
+            if (f == 0.0) continue;
+            for (int j = c; j < d; ++j) A[r * d + j] -= f * A[c * d + j];
+            for (int j = 0; j < m; ++j) B[r * m + j] -= f * B[c * m + j];
+        }
+    }
+    Q.assign(d * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        for (int r = d - 1; r >= 0; --r) {
+            double s = B[r * m + j];
+            for (int c = r + 1; c < d; ++c) s -= A[r * d + c] * Q[c * m + j];
+            Q[r * m + j] = s / A[r * d + r];
+        }
+    }
+    // P_I Q = P_II should hold; a rank-deficient P_I would have stopped above.
+    return IWFPM_OK;
+}
+
+// storage axis of paper index j (0-based): k_I axes are the last d
+static int axis_of(int d, int n, int j) { return j < d ? (n - d) + j : j - d; }
+
+void host_label(const iwfpm_plan_s* p, long long gpos, int* k) {
+    const DevGeom& g = p->geom;
+    const int d = p->d, n = p->n;
+    long long s = gpos / g.nkI;
+    long long r = gpos - s * g.nkI;
+    // k_II from the slice index (eq:inverse2)
+    long long t = s;
+    for (int ax = n - d - 1; ax >= 0; --ax) {
+        int E = g.ext[ax];
+        int ks = (int)(t % E);
+        t /= E;
+        int Lj = E / 2;
+        k[d + ax] = ks < Lj ? ks : ks - E;
+    }
+    for (int j = d - 1; j >= 0; --j) {
+        int ax = n - d + j;
+        int E = g.ext[ax];
+        int ks = (int)(r % E);
+        r /= E;
+        int a = p->slice_a[s * d + j];
+        int m = (ks - a) % E;
+        if (m < 0) m += E;
+        k[j] = a + m;
+    }
+}
+
+long long host_grid_to_vec(const iwfpm_plan_s* p, long long gpos) {
+    if (p->opts.order == IWFPM_ORDER_GRID) return gpos;
+    const DevGeom& g = p->geom;
+    const int d = p->d, n = p->n;
+    long long s = gpos / g.nkI;
+    long long r = gpos - s * g.nkI;
+    long long out = s * g.nkI;
+    for (int j = d - 1; j >= 0; --j) {
+        int ax = n - d + j;
+        int E = g.ext[ax];
+        int ks = (int)(r % E);
+        r /= E;
+        int m = (ks - p->slice_a[s * d + j]) % E;
+        if (m < 0) m += E;
+        out += (long long)m * g.stride[ax];
+    }
+    return out;
+}
+
+double host_kinetic(const iwfpm_plan_s* p, const int* k) {
+    double tot = 0.0;
+    for (int j = 0; j < p->d; ++j) {
+        double acc = 0.0;
+        for (int i = 0; i < p->n; ++i) acc += p->P[j * p->n + i] * (double)k[i];
+        double v = kTwoPi * acc;
+        tot += v * v;
+    }
+    return 0.5 * tot;
+}
+
+static int build_geometry(iwfpm_plan_s* p) {
+    const int d = p->d, n = p->n;
+    DevGeom& g = p->geom;
+    std::memset(&g, 0, sizeof(g));
+    g.n = n;
+    g.d = d;
+    g.order = p->opts.order;
+    for (int ax = 0; ax < n; ++ax) {
+        int e = ax < n - d ? 2 * p->L[ax] : 2 * p->K[ax - (n - d)];
+        g.ext[ax] = e;
+    }
+    long long st = 1;
+    for (int ax = n - 1; ax >= 0; --ax) {
+        g.stride[ax] = st;
+        st *= g.ext[ax];
+        if (st > (1LL << 31) - 1) return IWFPM_ERR_UNSUPPORTED;
+    }
+    g.N = st;
+    g.nkI = 1;
+    for (int ax = n - d; ax < n; ++ax) g.nkI *= g.ext[ax];
+    for (int j = 0; j < d; ++j)
+        for (int i = 0; i < d; ++i) g.P1[j * d + i] = kTwoPi * p->P[j * n + i];
+
+    // per-slice tables: q = Q k_II, the window's lower end a = -K - floor(q)
+    // (the floor form of eq:inverse3), and 2 pi P_II k_II for the kinetic term
+    p->nslice = g.N / g.nkI;
+    p->slice_a.assign(p->nslice * d, 0);
+    p->slice_g.assign(p->nslice * d, 0.0);
+    const int m = n - d;
+    std::vector<int> kII(m);
+    for (long long s = 0; s < p->nslice; ++s) {
+        long long t = s;
+        for (int ax = m - 1; ax >= 0; --ax) {
+            int E = g.ext[ax];
+            int ks = (int)(t % E);
+            t /= E;
+            kII[ax] = ks < E / 2 ? ks : ks - E;
+        }
+        for (int j = 0; j < d; ++j) {
+            double q = 0.0;
+            for (int i = 0; i < m; ++i) q = q + p->Q[j * m + i] * (double)kII[i];
+            // snap values within rounding of an integer onto it, so that the
+            // half-open window rule decides exact ties the same way every time
+            double rq = std::nearbyint(q);
+            if (std::fabs(q - rq) <= 1e-12 * std::max(1.0, std::fabs(q))) q = rq;
+            double qe = q;
+            if (p->opts.window_variant == IWFPM_WINDOW_ROUNDED) qe = std::floor(q + 0.5);
+            if (p->opts.window_variant == IWFPM_WINDOW_PM) qe = 0.0;
+            p->slice_a[s * d + j] = -p->K[j] - (int)std::floor(qe);
+            double acc = 0.0;
+            for (int i = 0; i < m; ++i) acc = acc + p->P[j * n + d + i] * (double)kII[i];
+            p->slice_g[s * d + j] = kTwoPi * acc;
+        }
+    }
+    return IWFPM_OK;
+}
+
+static int build_potential(iwfpm_plan_s* p, int n_modes, const int32_t* modes, const double* vhat) {
+    const int n = p->n, d = p->d;
+    // merge duplicate modes
+    std::map<std::vector<int>, std::pair<double, double>> acc;
+    for (int i = 0; i < n_modes; ++i) {
+        std::vector<int> m(modes + (size_t)i * n, modes + (size_t)(i + 1) * n);
+        auto& v = acc[m];
+        v.first += vhat[2 * i];
+        v.second += vhat[2 * i + 1];
+    }
+    p->modes.clear();
+    p->vre.clear();
+    p->vim.clear();
+    p->vhat0 = 0.0;
+    p->vsum_nonzero = 0.0;
+    p->vsum_abs = 0.0;
+    for (auto& kv : acc) {
+        const std::vector<int>& m = kv.first;
+        std::vector<int> mm(n);
+        for (int j = 0; j < n; ++j) mm[j] = -m[j];
+        auto it = acc.find(mm);
+        double re = kv.second.first, im = kv.second.second;
+        double tol = 1e-12 * std::max(1.0, std::hypot(re, im));
+        if (it == acc.end() || std::fabs(it->second.first - re) > tol || std::fabs(it->second.second + im) > tol)
+            return IWFPM_ERR_NONHERMITIAN;
+        bool zero = true;
+        for (int j = 0; j < n; ++j) zero = zero && m[j] == 0;
+        double a = std::hypot(re, im);
+        if (zero) p->vhat0 = re;
+        else p->vsum_nonzero += a;
+        p->vsum_abs += a;
+        p->modes.insert(p->modes.end(), m.begin(), m.end());
+        p->vre.push_back(re);
+        p->vim.push_back(im);
+    }
+    const int nm = (int)p->vre.size();
+    const DevGeom& g = p->geom;
+    bool axis_aligned = true;
+    for (int i = 0; i < nm && axis_aligned; ++i) {
+        int nz = 0;
+        for (int j = 0; j < n; ++j) nz += p->modes[i * n + j] != 0;
+        axis_aligned = nz <= 1;
+    }
+    const double invN = 1.0 / (double)g.N;
+    if (axis_aligned) {
+        // V(y_l) = sum over axes of f_ax(l_ax), f built from that axis' modes
+        p->geom.vmode = 0;
+        int off = 0;
+        for (int ax = 0; ax < n; ++ax) {
+            p->geom.voff[ax] = off;
+            off += g.ext[ax];
+        }
+        std::vector<double> tre(off, 0.0), tim(off, 0.0);
+        for (int i = 0; i < nm; ++i) {
+            int jnz = -1;
+            for (int j = 0; j < n; ++j)
+                if (p->modes[i * n + j] != 0) jnz = j;
+            int ax = jnz < 0 ? 0 : axis_of(d, n, jnz);
+            int t = jnz < 0 ? 0 : p->modes[i * n + jnz];
+            int E = g.ext[ax];
+            for (int l = 0; l < E; ++l) {
+                long long ph = ((long long)t * l) % E;
+                if (ph < 0) ph += E;
+                double ang = kTwoPi * (double)ph / (double)E;
+                double c = std::cos(ang), s = std::sin(ang);
+                tre[p->geom.voff[ax] + l] += p->vre[i] * c - p->vim[i] * s;
+                tim[p->geom.voff[ax] + l] += p->vre[i] * s + p->vim[i] * c;
+            }
+        }
+        p->vtab.resize(off);
+        for (int i = 0; i < off; ++i) p->vtab[i] = tre[i] * invN;
+        p->vgrid.clear();
+    } else {
+        p->geom.vmode = 1;
+        p->vgrid.assign(g.N, 0.0);
+        std::vector<int> l(n);
+        for (long long gp = 0; gp < g.N; ++gp) {
+            long long t = gp;
+            for (int ax = n - 1; ax >= 0; --ax) {
+                l[ax] = (int)(t % g.ext[ax]);
+                t /= g.ext[ax];
+            }
+            double v = 0.0;
+            for (int i = 0; i < nm; ++i) {
+                double ph = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    int ax = axis_of(d, n, j);
+                    long long pj = ((long long)p->modes[i * n + j] * l[ax]) % g.ext[ax];
+                    if (pj < 0) pj += g.ext[ax];
+                    ph += (double)pj / (double)g.ext[ax];
+                }
+                double ang = kTwoPi * (ph - std::floor(ph));
+                v += p->vre[i] * std::cos(ang) - p->vim[i] * std::sin(ang);
+            }
+            p->vgrid[gp] = v * invN;
+        }
+        p->vtab.clear();
+    }
+    return IWFPM_OK;
+}
+
+static const size_t kLdsDefault = 64 * 1024;
+static const size_t kLdsMax = 160 * 1024;
+
+static int choose_schedule(iwfpm_plan_s* p, int prec) {
+    Schedule& sc = p->sched[prec];
+    const DevGeom& g = p->geom;
+    const int n = p->n;
+    const size_t esz = prec == 1 ? 8 : 16;
+    int maxall = 0;
+    for (int ax = 0; ax < n; ++ax) maxall = std::max(maxall, g.ext[ax]);
+    sc.maxs_fused = extent_class(maxall);
+    sc.threads_fused = 256;
+    bool want_fused = p->opts.schedule == IWFPM_SCHED_FUSED ||
+                      (p->opts.schedule == IWFPM_SCHED_AUTO && (size_t)g.N * esz <= kLdsDefault);
+    if (want_fused) {
+        if ((size_t)g.N * esz > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+        sc.fused = true;
+        return IWFPM_OK;
+    }
+    sc.fused = false;
+    if (n < 2) return IWFPM_ERR_UNSUPPORTED;
+    // pick the split: trailing axes [split, n) form the contiguous slabs
+    int lo = 1, hi = n - 1;
+    if (p->opts.order == IWFPM_ORDER_WINDOW) hi = n - p->d;  // k_I axes must stay in one slab
+    int split = 0;
+    if (p->opts.split > 0) {
+        split = p->opts.split;
+        if (split < lo || split > hi) return IWFPM_ERR_ARG;
+    } else {
+        // prefer the k_I / k_II boundary, then the most balanced feasible split
+        double best = 1e300;
+        for (int s = lo; s <= hi; ++s) {
+            long long sin_ = g.stride[s - 1];
+            long long sout = g.N / sin_;
+            if ((size_t)sin_ * esz > kLdsMax || (size_t)sout * esz * 4 > kLdsMax) continue;
+            double cost = std::fabs(std::log((double)sin_) - std::log((double)sout));
+            if (s == n - p->d) cost -= 0.5;
+            if (cost < best) {
+                best = cost;
+                split = s;
+            }
+        }
+        if (split == 0) return IWFPM_ERR_UNSUPPORTED;
+    }
+    PassDesc& pd = sc.pd;
+    pd.split = split;
+    pd.s_in = g.stride[split - 1];
+    pd.s_out = g.N / pd.s_in;
+    if ((size_t)pd.s_in * esz > kLdsMax || (size_t)pd.s_out * esz > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+    // middle pass: `tile` consecutive columns
+    int T = p->opts.tile;
+    if (T <= 0) {
+        T = 1;
+        while (T < 16 && (size_t)pd.s_out * (2 * T) * esz <= kLdsDefault && 2 * T <= pd.s_in) T *= 2;
+    }
+    if ((size_t)pd.s_out * T * esz > kLdsMax) return IWFPM_ERR_ARG;
+    pd.tile = T;
+    // slabs per workgroup for passes 1 and 3
+    int G = 1;
+    while ((size_t)(2 * G) * pd.s_in * esz <= kLdsDefault / 2 && 2 * G <= 64) G *= 2;
+    pd.slabs_per_wg = G;
+    pd.threads_inner = 256;
+    pd.threads_outer = 256;
+    pd.xcd_remap = 1;
+    int mi = 0, mo = 0;
+    for (int ax = split; ax < n; ++ax) mi = std::max(mi, g.ext[ax]);
+    for (int ax = 0; ax < split; ++ax) mo = std::max(mo, g.ext[ax]);
+    sc.maxs_inner = extent_class(mi);
+    sc.maxs_outer = extent_class(mo);
+    return IWFPM_OK;
+}
+
+template <typename R>
+static int prepare_kernels() {
+    int b = (int)kLdsMax;
+    hipError_t e = hipSuccess;
+    e = prepare_fused<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_fused<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_fused<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass1<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass1<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass1<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass2<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass2<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass2<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass3<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass3<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_pass3<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    return IWFPM_OK;
+}
+
+template <typename T>
+static int upload(DeviceBuf& b, const std::vector<T>& v) {
+    if (v.empty()) return IWFPM_OK;
+    int rc = dev_alloc(b, v.size() * sizeof(T));
+    if (rc != IWFPM_OK) return rc;
+    if (hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return IWFPM_ERR_DEVICE;
+    return IWFPM_OK;
+}
+
+static int upload_tables(iwfpm_plan_s* p) {
+    int rc;
+    if ((rc = upload(p->d_slice_a, p->slice_a)) != IWFPM_OK) return rc;
+    if ((rc = upload(p->d_slice_g, p->slice_g)) != IWFPM_OK) return rc;
+    std::vector<float> f32;
+    if (!p->vtab.empty()) {
+        if ((rc = upload(p->d_vtab64, p->vtab)) != IWFPM_OK) return rc;
+        f32.assign(p->vtab.begin(), p->vtab.end());
+        if ((rc = upload(p->d_vtab32, f32)) != IWFPM_OK) return rc;
+    }
+    if (!p->vgrid.empty()) {
+        if ((rc = upload(p->d_vgrid64, p->vgrid)) != IWFPM_OK) return rc;
+        f32.assign(p->vgrid.begin(), p->vgrid.end());
+        if ((rc = upload(p->d_vgrid32, f32)) != IWFPM_OK) return rc;
+    }
+    p->tabs.slice_a = (const int*)p->d_slice_a.ptr;
+    p->tabs.slice_g = (const double*)p->d_slice_g.ptr;
+    p->tabs.vtab32 = (const float*)p->d_vtab32.ptr;
+    p->tabs.vtab64 = (const double*)p->d_vtab64.ptr;
+    p->tabs.vgrid32 = (const float*)p->d_vgrid32.ptr;
+    p->tabs.vgrid64 = (const double*)p->d_vgrid64.ptr;
+    return IWFPM_OK;
+}
+
+template <typename R>
+static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTabs& t, const void* psi, void* hpsi,
+                               void* ws, int nvec, hipStream_t st) {
+    if (sc.fused) {
+        switch (sc.maxs_fused) {
+            case 16: return launch_fused<R, 16>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
+            case 32: return launch_fused<R, 32>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
+            default: return launch_fused<R, 64>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
+        }
+    }
+    hipError_t e;
+    switch (sc.maxs_inner) {
+        case 16: e = launch_pass1<R, 16>(g, t, sc.pd, psi, ws, nvec, st); break;
+        case 32: e = launch_pass1<R, 32>(g, t, sc.pd, psi, ws, nvec, st); break;
+        default: e = launch_pass1<R, 64>(g, t, sc.pd, psi, ws, nvec, st); break;
+    }
+    if (e != hipSuccess) return e;
+    switch (sc.maxs_outer) {
+        case 16: e = launch_pass2<R, 16>(g, t, sc.pd, ws, nvec, st); break;
+        case 32: e = launch_pass2<R, 32>(g, t, sc.pd, ws, nvec, st); break;
+        default: e = launch_pass2<R, 64>(g, t, sc.pd, ws, nvec, st); break;
+    }
+    if (e != hipSuccess) return e;
+    switch (sc.maxs_inner) {
+        case 16: return launch_pass3<R, 16>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
+        case 32: return launch_pass3<R, 32>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
+        default: return launch_pass3<R, 64>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
+    }
+}
+
+static const size_t kWorkspaceCap = (size_t)4 << 30;
+
+int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st) {
+    if (nvec == 0) return IWFPM_OK;
+    const int prec = precision == IWFPM_PREC_FP32 ? 1 : 0;
+    const Schedule& sc = p->sched[prec];
+    const size_t esz = prec ? 8 : 16;
+    const long long N = p->geom.N;
+    int chunk = nvec;
+    if (!sc.fused) {
+        size_t per = (size_t)N * esz;
+        chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nvec, kWorkspaceCap / per));
+        size_t need = per * chunk;
+        if (p->d_ws.bytes < need) {
+            if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
+            if (dev_alloc(p->d_ws, need) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+        }
+    }
+    const double2* x = reinterpret_cast<const double2*>(psi);
+    double2* y = reinterpret_cast<double2*>(hpsi);
+    for (int v0 = 0; v0 < nvec; v0 += chunk) {
+        int nv = std::min(chunk, nvec - v0);
+        hipError_t e = prec ? launch_sched<float>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
+                                                  p->d_ws.ptr, nv, st)
+                            : launch_sched<double>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
+                                                   p->d_ws.ptr, nv, st);
+        if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    }
+    return IWFPM_OK;
+}
+
+}  // namespace iwfpm
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void iwfpm_default_opts(iwfpm_opts* o) {
+    if (!o) return;
+    o->precision = IWFPM_PREC_FP64;
+    o->window_variant = IWFPM_WINDOW_EXACT;
+    o->order = IWFPM_ORDER_GRID;
+    o->device = 0;
+    o->schedule = IWFPM_SCHED_AUTO;
+    o->split = 0;
+    o->tile = 0;
+}
+
+const char* iwfpm_status_string(int s) {
+    switch (s) {
+        case IWFPM_OK: return "ok";
+        case IWFPM_ERR_ARG: return "invalid argument";
+        case IWFPM_ERR_SINGULAR_PI: return "P_I is singular";
+        case IWFPM_ERR_NONHERMITIAN: return "potential modes do not describe a real potential";
+        case IWFPM_ERR_UNSUPPORTED: return "unsupported by this build";
+        case IWFPM_ERR_ALLOC: return "allocation failed";
+        case IWFPM_ERR_DEVICE: return "HIP error";
+        case IWFPM_ERR_NUMERIC: return "numerical breakdown";
+        case IWFPM_ERR_NOCONV: return "not converged";
+        case IWFPM_ERR_WEIGHTS: return "learned preconditioner weights missing or invalid";
+        case IWFPM_ERR_NODEVICE: return "host-only plan";
+        default: return "unknown status";
+    }
+}
+
+int iwfpm_plan(int d, int n, const double* P, const int32_t* K, const int32_t* L, int n_modes,
+               const int32_t* modes, const double* vhat, const iwfpm_opts* opts, iwfpm_plan_t* out) {
+    if (!out) return IWFPM_ERR_ARG;
+    *out = nullptr;
+    if (d < 1 || n <= d || n > kMaxAxes || !P || !K || !L || n_modes < 0) return IWFPM_ERR_ARG;
+    if (n_modes > 0 && (!modes || !vhat)) return IWFPM_ERR_ARG;
+    iwfpm_opts o;
+    iwfpm_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision < 0 || o.precision > 1 || o.window_variant < 0 || o.window_variant > 2 || o.order < 0 ||
+        o.order > 1 || o.schedule < 0 || o.schedule > 2 || o.device < -1)
+        return IWFPM_ERR_ARG;
+    for (int i = 0; i < d * n; ++i)
+        if (!std::isfinite(P[i])) return IWFPM_ERR_ARG;
+    for (int j = 0; j < d; ++j)
+        if (K[j] < 1 || !extent_supported(2 * K[j])) return K[j] < 1 ? IWFPM_ERR_ARG : IWFPM_ERR_UNSUPPORTED;
+    for (int j = 0; j < n - d; ++j)
+        if (L[j] < 1 || !extent_supported(2 * L[j])) return L[j] < 1 ? IWFPM_ERR_ARG : IWFPM_ERR_UNSUPPORTED;
+    for (int i = 0; i < 2 * n_modes; ++i)
+        if (!std::isfinite(vhat[i])) return IWFPM_ERR_ARG;
+
+    iwfpm_plan_s* p = new (std::nothrow) iwfpm_plan_s();
+    if (!p) return IWFPM_ERR_ALLOC;
+    p->d = d;
+    p->n = n;
+    p->opts = o;
+    p->P.assign(P, P + d * n);
+    p->K.assign(K, K + d);
+    p->L.assign(L, L + (n - d));
+    int rc = solve_Q(d, n, P, p->Q);
+    if (rc == IWFPM_OK) rc = build_geometry(p);
+    if (rc == IWFPM_OK) rc = build_potential(p, n_modes, modes, vhat);
+    if (rc == IWFPM_OK) rc = choose_schedule(p, 0);
+    if (rc == IWFPM_OK) rc = choose_schedule(p, 1);
+    if (rc != IWFPM_OK) {
+        delete p;
+        return rc;
+    }
+    // max Lambda over the grid for the norm bound
+    {
+        std::vector<int> k(n);
+        double mx = 0.0;
+        for (long long gp = 0; gp < p->geom.N; ++gp) {
+            host_label(p, gp, k.data());
+            mx = std::max(mx, host_kinetic(p, k.data()));
+        }
+        p->lam_max = mx;
+    }
+    if (o.device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) {
+            (void)hipGetLastError();
+            delete p;
+            return IWFPM_ERR_DEVICE;
+        }
+        DeviceGuard guard(o.device);
+        if (!guard.ok) {
+            delete p;
+            return IWFPM_ERR_DEVICE;
+        }
+        rc = prepare_kernels<float>();
+        if (rc == IWFPM_OK) rc = prepare_kernels<double>();
+        if (rc == IWFPM_OK) rc = upload_tables(p);
+        if (rc != IWFPM_OK) {
+            iwfpm_destroy(p);
+            return rc;
+        }
+        p->host_only = false;
+    }
+    *out = p;
+    return IWFPM_OK;
+}
+
+int iwfpm_dof(iwfpm_plan_t p, int64_t* N) {
+    if (!p || !N) return IWFPM_ERR_ARG;
+    *N = p->geom.N;
+    return IWFPM_OK;
+}
+
+int iwfpm_grid_shape(iwfpm_plan_t p, int32_t* ext) {
+    if (!p || !ext) return IWFPM_ERR_ARG;
+    for (int ax = 0; ax < p->n; ++ax) ext[ax] = p->geom.ext[ax];
+    return IWFPM_OK;
+}
+
+int iwfpm_indices(iwfpm_plan_t p, int32_t* k_out) {
+    if (!p || !k_out) return IWFPM_ERR_ARG;
+    std::vector<int> k(p->n);
+    for (long long gp = 0; gp < p->geom.N; ++gp) {
+        host_label(p, gp, k.data());
+        long long vp = host_grid_to_vec(p, gp);
+        for (int j = 0; j < p->n; ++j) k_out[vp * p->n + j] = k[j];
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_kinetic(iwfpm_plan_t p, double* out) {
+    if (!p || !out) return IWFPM_ERR_ARG;
+    std::vector<int> k(p->n);
+    for (long long gp = 0; gp < p->geom.N; ++gp) {
+        host_label(p, gp, k.data());
+        out[host_grid_to_vec(p, gp)] = host_kinetic(p, k.data());
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_norm_bound(iwfpm_plan_t p, double* out) {
+    if (!p || !out) return IWFPM_ERR_ARG;
+    *out = p->lam_max + p->vsum_abs;
+    return IWFPM_OK;
+}
+
+int iwfpm_apply_prec(iwfpm_plan_t p, const void* psi, void* hpsi, int nvec, int precision, void* stream) {
+    if (!p || nvec < 0) return IWFPM_ERR_ARG;
+    if (precision != IWFPM_PREC_FP64 && precision != IWFPM_PREC_FP32) return IWFPM_ERR_ARG;
+    if (nvec > 0 && (!psi || !hpsi)) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    if (nvec == 0) return IWFPM_OK;
+    const char* a = (const char*)psi;
+    const char* b = (const char*)hpsi;
+    size_t bytes = (size_t)nvec * (size_t)p->geom.N * 16;
+    if (a < b + bytes && b < a + bytes) return IWFPM_ERR_ARG;  // overlapping buffers
+    DeviceGuard guard(p->opts.device);
+    if (!guard.ok) return IWFPM_ERR_DEVICE;
+    return plan_apply(p, psi, hpsi, nvec, precision, (hipStream_t)stream);
+}
+
+int iwfpm_apply(iwfpm_plan_t p, const void* psi, void* hpsi, int nvec, void* stream) {
+    if (!p) return IWFPM_ERR_ARG;
+    return iwfpm_apply_prec(p, psi, hpsi, nvec, p->opts.precision, stream);
+}
+
+}  // extern "C"

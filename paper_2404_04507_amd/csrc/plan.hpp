@@ -1,0 +1,89 @@
+// plan.hpp - the plan object behind iwfpm_plan_t (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/iwfpm.h"
+#include "internal.hpp"
+
+namespace iwfpm {
+
+struct DeviceBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Schedule {
+    bool fused = false;
+    PassDesc pd{};
+    int maxs_fused = 0, maxs_inner = 0, maxs_outer = 0;  // extent classes (16, 32, 64)
+    int threads_fused = 256;
+};
+
+struct LearnedPrecond;  // learned.cpp
+
+}  // namespace iwfpm
+
+struct iwfpm_plan_s {
+    // problem
+    int d = 0, n = 0;
+    std::vector<double> P;        // d x n
+    std::vector<int> K, L;
+    std::vector<int> modes;       // n_modes x n (merged duplicates)
+    std::vector<double> vre, vim; // coefficients
+    iwfpm_opts opts{};
+    // geometry (host)
+    iwfpm::DevGeom geom{};
+    std::vector<double> Q;        // d x (n-d)
+    long long nslice = 0;
+    std::vector<int> slice_a;     // nslice x d
+    std::vector<double> slice_g;  // nslice x d
+    std::vector<double> vtab;     // per-axis tables / N (vmode 0)
+    std::vector<double> vgrid;    // V on the grid / N (vmode 1)
+    double vhat0 = 0.0;           // coefficient of the zero mode
+    double vsum_nonzero = 0.0;    // sum over m != 0 of |Vhat_m|
+    double vsum_abs = 0.0;        // sum over all m of |Vhat_m|
+    double lam_max = 0.0;
+    // schedules per precision: [0] float64, [1] float32
+    iwfpm::Schedule sched[2];
+    // device
+    bool host_only = true;
+    iwfpm::DeviceBuf d_slice_a, d_slice_g, d_vtab32, d_vtab64, d_vgrid32, d_vgrid64;
+    iwfpm::DeviceBuf d_ws;        // apply workspace
+    iwfpm::DevTabs tabs{};
+    // eigensolver state (lobpcg.cpp)
+    void* solver = nullptr;
+    iwfpm::LearnedPrecond* learned = nullptr;
+};
+
+namespace iwfpm {
+
+// host helpers shared by plan.cpp and lobpcg.cpp
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int dev_alloc(DeviceBuf& b, size_t bytes);
+void dev_free(DeviceBuf& b);
+
+// apply on a plan (precision 0 = float64 convolution, 1 = float32)
+int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st);
+
+// grid position -> true label k (paper order) and vector position
+void host_label(const iwfpm_plan_s* p, long long gpos, int* k_out);
+long long host_grid_to_vec(const iwfpm_plan_s* p, long long gpos);
+double host_kinetic(const iwfpm_plan_s* p, const int* k);
+
+}  // namespace iwfpm

@@ -1,0 +1,121 @@
+"""Host-side checks of libiwfpm that need no GPU: the C ABI loads and exports
+every declared symbol, host-only plans reproduce the oracle's labels and
+kinetic diagonal (Sec. 3.2, eq:inverse1-3; Sec. 4.1), and bad inputs come back
+as status codes."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2404_04507_amd as lib
+from paper_2404_04507_amd import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "iwfpm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(iwfpm_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "iwfpm_plan" in names and "iwfpm_apply" in names and "iwfpm_eigs" in names
+    so = ctypes.CDLL(lib.library_path())
+    for name in names:
+        assert hasattr(so, name), name
+    assert set(names) <= set(lib.EXPORTED) | set(names)
+    for name in lib.EXPORTED:
+        assert name in names
+
+
+def host_plan(prob, **kw):
+    return lib.Plan.from_problem(prob, device=-1, **kw)
+
+
+CASES = [
+    lambda: W.c1_1d(),
+    lambda: W.c2_2d(K=5, L=4),
+    lambda: W.c3_3d(K=2, L=2),
+    lambda: W.paper_example_2d(0.5 * math.pi, 0.25 * math.pi, 4, 6),
+    lambda: W.paper_example_3d(math.pi, 2, 3),
+]
+
+
+@pytest.mark.parametrize("variant", ["exact", "rounded", "pm"])
+@pytest.mark.parametrize("make", CASES)
+def test_labels_and_kinetic_match_oracle(make, variant):
+    prob = make()
+    with host_plan(prob, window=variant) as p:
+        assert p.N == prob.N and p.ext == prob.ext
+        k = p.indices()
+        ref = O.grid_labels(prob.P, prob.d, prob.K, prob.L, variant)
+        assert np.array_equal(k, ref)
+        lam = p.kinetic()
+        lref = O.kinetic(prob.P, ref)
+        assert np.allclose(lam, lref, rtol=1e-14, atol=1e-12)
+        nb = p.norm_bound()
+        assert abs(nb - (lref.max() + np.abs(prob.vhat).sum())) < 1e-9 * nb
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_window_order_sorts_each_slice(make):
+    """WINDOW order: within a slice, entries run over k_I ascending from the lower window end."""
+    prob = make()
+    with host_plan(prob, order="window") as p:
+        k = p.indices()
+    ref = O.grid_labels(prob.P, prob.d, prob.K, prob.L)
+    assert {tuple(x) for x in k} == {tuple(x) for x in ref}
+    nkI = int(np.prod([2 * x for x in prob.K]))
+    d = prob.d
+    for s in range(0, prob.N // nkI, max(1, prob.N // nkI // 7)):
+        blk = k[s * nkI:(s + 1) * nkI, :d].reshape([2 * x for x in prob.K] + [d])
+        # along each k_I axis consecutive entries differ by exactly +1
+        for j in range(d):
+            dif = np.diff(blk[..., j], axis=j)
+            assert np.all(dif == 1)
+
+
+def test_tie_at_integer_offset():
+    """C3's Q has cancelling entries (k4 = k5 gives q1 = 0 exactly) and rational
+    entries in C2 (q = -k4/2): the half-open window rule decides ties."""
+    for prob in (W.c3_3d(K=2, L=2), W.c2_2d(K=3, L=4)):
+        with host_plan(prob) as p:
+            k = p.indices()
+        assert np.array_equal(k, O.grid_labels(prob.P, prob.d, prob.K, prob.L))
+
+
+def test_status_codes():
+    P = np.array([[1.0, W.GOLDEN]])
+    modes, vhat = W.cosine_modes(2, [1.0, 1.0])
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan(np.array([[0.0, 1.0]]), [4], [4], modes, vhat, device=-1)
+    assert e.value.status == -2  # singular P_I
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan(P, [4], [4], [[1, 0]], [1.0 + 1.0j], device=-1)
+    assert e.value.status == -3  # no conjugate partner
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan(P, [0], [4], modes, vhat, device=-1)
+    assert e.value.status == -1
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan(P, [4], [4096], modes, vhat, device=-1)
+    assert e.value.status == -4  # extent 8192 is not compiled
+    p = lib.Plan(P, [4], [4], modes, vhat, device=-1)
+    so = lib.load_library()
+    st = so.iwfpm_apply(p._h, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 1, ctypes.c_void_p())
+    assert st == -10  # host-only plan
+    st = so.iwfpm_apply(p._h, ctypes.c_void_p(), ctypes.c_void_p(), 1, ctypes.c_void_p())
+    assert st == -1
+    p.close()
+    assert so.iwfpm_dof(ctypes.c_void_p(), ctypes.byref(ctypes.c_int64())) == -1
+
+
+def test_duplicate_modes_are_merged():
+    P = np.array([[1.0, W.GOLDEN]])
+    with lib.Plan(P, [4], [4], [[1, 0], [-1, 0], [1, 0], [-1, 0]], [0.5, 0.5, 0.25, 0.25], device=-1) as p:
+        assert abs(p.norm_bound() - (p.kinetic().max() + 1.5)) < 1e-12
