@@ -141,6 +141,19 @@ int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* 
 int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
                      int precision, void* stream);
 
+/*
+ * iwfpm_profile - start (enable = 1) or stop (0) timing the kernels of every
+ * subsequent apply on this plan.  Timing uses HIP events recorded on the
+ * apply's own stream before and after each kernel (fused, or passes 1-3);
+ * nothing blocks while recording.  Enabling resets the totals.
+ * iwfpm_profile_read - totals since the last enable: ms[4] summed kernel time
+ * (fused, pass 1, pass 2, pass 3), launches[4], points[4] (grid points x
+ * vectors processed).  Synchronises with the outstanding events.
+ * Errors: ERR_ARG, ERR_NODEVICE, ERR_DEVICE.
+ */
+int iwfpm_profile(iwfpm_plan_t plan, int enable);
+int iwfpm_profile_read(iwfpm_plan_t plan, double* ms, int64_t* launches, int64_t* points);
+
 typedef struct {
     int nev;            /* eigenpairs wanted (lowest), >= 1 */
     int block;          /* LOBPCG block size m >= nev; 0 = nev + max(2, nev/4) */

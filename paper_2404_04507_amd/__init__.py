@@ -24,7 +24,8 @@ _LIB = None
 
 EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_destroy", "iwfpm_dof",
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
-            "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs"]
+            "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
+            "iwfpm_profile_read"]
 
 PREC = {"fp64": 0, "fp32": 1}
 WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
@@ -87,6 +88,8 @@ def load_library():
     lib.iwfpm_norm_bound.argtypes = [vp, dp]
     lib.iwfpm_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.iwfpm_apply_prec.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.iwfpm_profile.argtypes = [vp, ctypes.c_int]
+    lib.iwfpm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
     lib.iwfpm_default_eigs_opts.restype = None
     lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
@@ -242,6 +245,18 @@ class Plan:
                                      nvec, prec, _stream_handle(stream))
         _check(st, "iwfpm_apply")
         return out
+
+    def profile(self, enable: bool):
+        _check(_lib().iwfpm_profile(self._h, int(bool(enable))), "iwfpm_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(4)
+        la = np.zeros(4, dtype=np.int64)
+        pt = np.zeros(4, dtype=np.int64)
+        _check(_lib().iwfpm_profile_read(self._h, _ptr(ms, ctypes.c_double), _ptr(la, ctypes.c_int64),
+                                         _ptr(pt, ctypes.c_int64)), "iwfpm_profile_read")
+        names = ["fused", "pass1", "pass2", "pass3"]
+        return {n: {"ms": float(ms[i]), "launches": int(la[i]), "points": int(pt[i])} for i, n in enumerate(names)}
 
     def eigs(self, nev, tol=1e-8, maxit=500, block=0, precond="plain", x0=None, seed=2404045070,
              polish=True, want_vectors=True, stream=None, allow_noconv=False) -> EigsResult:

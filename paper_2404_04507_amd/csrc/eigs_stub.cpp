@@ -17,6 +17,9 @@ int iwfpm_destroy(iwfpm_plan_t p) {
         iwfpm::dev_free(p->d_vtab32); iwfpm::dev_free(p->d_vtab64);
         iwfpm::dev_free(p->d_vgrid32); iwfpm::dev_free(p->d_vgrid64);
         iwfpm::dev_free(p->d_ws);
+        for (auto& sl : p->prof.ring)
+            for (auto& e : sl.ev)
+                if (e) (void)hipEventDestroy(e);
     }
     delete p;
     return IWFPM_OK;

@@ -341,7 +341,7 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
         for (int s = lo; s <= hi; ++s) {
             long long sin_ = g.stride[s - 1];
             long long sout = g.N / sin_;
-            if ((size_t)sin_ * esz > kLdsMax || (size_t)sout * esz * 4 > kLdsMax) continue;
+            if ((size_t)sin_ * esz > kLdsMax || (size_t)sout * esz > kLdsMax) continue;
             double cost = std::fabs(std::log((double)sin_) - std::log((double)sout));
             if (s == n - p->d) cost -= 0.5;
             if (cost < best) {
@@ -432,15 +432,51 @@ static int upload_tables(iwfpm_plan_s* p) {
     return IWFPM_OK;
 }
 
+static void prof_collect(ApplyProfiler::Slot& s, ApplyProfiler& pr) {
+    if (!s.pending) return;
+    (void)hipEventSynchronize(s.ev[s.kind ? 3 : 1]);
+    float t = 0.f;
+    if (s.kind == 0) {
+        if (hipEventElapsedTime(&t, s.ev[0], s.ev[1]) == hipSuccess) pr.ms[0] += t;
+        pr.launches[0] += 1;
+        pr.points[0] += s.points;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            if (hipEventElapsedTime(&t, s.ev[k], s.ev[k + 1]) == hipSuccess) pr.ms[k + 1] += t;
+            pr.launches[k + 1] += 1;
+            pr.points[k + 1] += s.points;
+        }
+    }
+    s.pending = false;
+}
+
+// event to record after kernel `i` of this launch sequence (or null)
+static hipEvent_t* prof_slot(ApplyProfiler* pr, bool fused, long long points, hipStream_t st) {
+    if (!pr || !pr->on) return nullptr;
+    if (pr->ring.empty()) return nullptr;
+    ApplyProfiler::Slot& s = pr->ring[pr->head];
+    pr->head = (pr->head + 1) % pr->ring.size();
+    prof_collect(s, *pr);
+    s.kind = fused ? 0 : 1;
+    s.points = points;
+    s.pending = true;
+    (void)hipEventRecord(s.ev[0], st);
+    return s.ev;
+}
+
 template <typename R>
 static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTabs& t, const void* psi, void* hpsi,
-                               void* ws, int nvec, hipStream_t st) {
+                               void* ws, int nvec, hipStream_t st, ApplyProfiler* pr) {
+    hipEvent_t* ev = prof_slot(pr, sc.fused, (long long)nvec * g.N, st);
     if (sc.fused) {
+        hipError_t e;
         switch (sc.maxs_fused) {
-            case 16: return launch_fused<R, 16>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
-            case 32: return launch_fused<R, 32>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
-            default: return launch_fused<R, 64>(g, t, sc.threads_fused, psi, hpsi, nvec, st);
+            case 16: e = launch_fused<R, 16>(g, t, sc.threads_fused, psi, hpsi, nvec, st); break;
+            case 32: e = launch_fused<R, 32>(g, t, sc.threads_fused, psi, hpsi, nvec, st); break;
+            default: e = launch_fused<R, 64>(g, t, sc.threads_fused, psi, hpsi, nvec, st); break;
         }
+        if (ev) (void)hipEventRecord(ev[1], st);
+        return e;
     }
     hipError_t e;
     switch (sc.maxs_inner) {
@@ -448,18 +484,22 @@ static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTa
         case 32: e = launch_pass1<R, 32>(g, t, sc.pd, psi, ws, nvec, st); break;
         default: e = launch_pass1<R, 64>(g, t, sc.pd, psi, ws, nvec, st); break;
     }
+    if (ev) (void)hipEventRecord(ev[1], st);
     if (e != hipSuccess) return e;
     switch (sc.maxs_outer) {
         case 16: e = launch_pass2<R, 16>(g, t, sc.pd, ws, nvec, st); break;
         case 32: e = launch_pass2<R, 32>(g, t, sc.pd, ws, nvec, st); break;
         default: e = launch_pass2<R, 64>(g, t, sc.pd, ws, nvec, st); break;
     }
+    if (ev) (void)hipEventRecord(ev[2], st);
     if (e != hipSuccess) return e;
     switch (sc.maxs_inner) {
-        case 16: return launch_pass3<R, 16>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
-        case 32: return launch_pass3<R, 32>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
-        default: return launch_pass3<R, 64>(g, t, sc.pd, psi, ws, hpsi, nvec, st);
+        case 16: e = launch_pass3<R, 16>(g, t, sc.pd, psi, ws, hpsi, nvec, st); break;
+        case 32: e = launch_pass3<R, 32>(g, t, sc.pd, psi, ws, hpsi, nvec, st); break;
+        default: e = launch_pass3<R, 64>(g, t, sc.pd, psi, ws, hpsi, nvec, st); break;
     }
+    if (ev) (void)hipEventRecord(ev[3], st);
+    return e;
 }
 
 static const size_t kWorkspaceCap = (size_t)4 << 30;
@@ -468,6 +508,7 @@ int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int preci
     if (nvec == 0) return IWFPM_OK;
     const int prec = precision == IWFPM_PREC_FP32 ? 1 : 0;
     const Schedule& sc = p->sched[prec];
+    if (!sc.ok) return IWFPM_ERR_UNSUPPORTED;
     const size_t esz = prec ? 8 : 16;
     const long long N = p->geom.N;
     int chunk = nvec;
@@ -485,9 +526,9 @@ int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int preci
     for (int v0 = 0; v0 < nvec; v0 += chunk) {
         int nv = std::min(chunk, nvec - v0);
         hipError_t e = prec ? launch_sched<float>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                  p->d_ws.ptr, nv, st)
+                                                  p->d_ws.ptr, nv, st, &p->prof)
                             : launch_sched<double>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                   p->d_ws.ptr, nv, st);
+                                                   p->d_ws.ptr, nv, st, &p->prof);
         if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     }
     return IWFPM_OK;
@@ -561,8 +602,14 @@ int iwfpm_plan(int d, int n, const double* P, const int32_t* K, const int32_t* L
     int rc = solve_Q(d, n, P, p->Q);
     if (rc == IWFPM_OK) rc = build_geometry(p);
     if (rc == IWFPM_OK) rc = build_potential(p, n_modes, modes, vhat);
-    if (rc == IWFPM_OK) rc = choose_schedule(p, 0);
-    if (rc == IWFPM_OK) rc = choose_schedule(p, 1);
+    if (rc == IWFPM_OK) {
+        // a precision whose tiles do not fit is reported at apply time only
+        int r64 = choose_schedule(p, 0), r32 = choose_schedule(p, 1);
+        p->sched[0].ok = r64 == IWFPM_OK;
+        p->sched[1].ok = r32 == IWFPM_OK;
+        if (r64 == IWFPM_ERR_ARG || r32 == IWFPM_ERR_ARG) rc = IWFPM_ERR_ARG;
+        else if (!p->sched[o.precision].ok) rc = o.precision ? r32 : r64;
+    }
     if (rc != IWFPM_OK) {
         delete p;
         return rc;
@@ -654,6 +701,42 @@ int iwfpm_apply_prec(iwfpm_plan_t p, const void* psi, void* hpsi, int nvec, int 
     DeviceGuard guard(p->opts.device);
     if (!guard.ok) return IWFPM_ERR_DEVICE;
     return plan_apply(p, psi, hpsi, nvec, precision, (hipStream_t)stream);
+}
+
+int iwfpm_profile(iwfpm_plan_t p, int enable) {
+    if (!p) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    DeviceGuard guard(p->opts.device);
+    ApplyProfiler& pr = p->prof;
+    for (auto& s : pr.ring) prof_collect(s, pr);
+    if (enable) {
+        if (pr.ring.empty()) {
+            pr.ring.resize(1024);
+            for (auto& s : pr.ring)
+                for (auto& e : s.ev)
+                    if (hipEventCreate(&e) != hipSuccess) return IWFPM_ERR_DEVICE;
+        }
+        for (int k = 0; k < 4; ++k) {
+            pr.ms[k] = 0.0;
+            pr.launches[k] = 0;
+            pr.points[k] = 0;
+        }
+    }
+    pr.on = enable != 0;
+    return IWFPM_OK;
+}
+
+int iwfpm_profile_read(iwfpm_plan_t p, double* ms, int64_t* launches, int64_t* points) {
+    if (!p || !ms || !launches || !points) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    DeviceGuard guard(p->opts.device);
+    for (auto& s : p->prof.ring) prof_collect(s, p->prof);
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = p->prof.ms[k];
+        launches[k] = p->prof.launches[k];
+        points[k] = p->prof.points[k];
+    }
+    return IWFPM_OK;
 }
 
 int iwfpm_apply(iwfpm_plan_t p, const void* psi, void* hpsi, int nvec, void* stream) {

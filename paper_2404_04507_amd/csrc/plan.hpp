@@ -18,6 +18,7 @@ struct DeviceBuf {
 };
 
 struct Schedule {
+    bool ok = false;
     bool fused = false;
     PassDesc pd{};
     int maxs_fused = 0, maxs_inner = 0, maxs_outer = 0;  // extent classes (16, 32, 64)
@@ -25,6 +26,23 @@ struct Schedule {
 };
 
 struct LearnedPrecond;  // learned.cpp
+
+// Per-kernel timing of applies: HIP events recorded on the apply's stream
+// around each kernel, read back lazily so that recording never blocks.
+struct ApplyProfiler {
+    bool on = false;
+    struct Slot {
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        int kind = 0;            // 0 fused (ev0..ev1), 1 three-pass (ev0..ev3)
+        long long points = 0;    // grid points processed by each kernel
+        bool pending = false;
+    };
+    std::vector<Slot> ring;
+    size_t head = 0;
+    double ms[4] = {0, 0, 0, 0};        // fused, pass 1, pass 2, pass 3
+    long long launches[4] = {0, 0, 0, 0};
+    long long points[4] = {0, 0, 0, 0};
+};
 
 }  // namespace iwfpm
 
@@ -55,6 +73,7 @@ struct iwfpm_plan_s {
     iwfpm::DeviceBuf d_slice_a, d_slice_g, d_vtab32, d_vtab64, d_vgrid32, d_vgrid64;
     iwfpm::DeviceBuf d_ws;        // apply workspace
     iwfpm::DevTabs tabs{};
+    iwfpm::ApplyProfiler prof;
     // eigensolver state (lobpcg.cpp)
     void* solver = nullptr;
     iwfpm::LearnedPrecond* learned = nullptr;
