@@ -194,6 +194,22 @@ void iwfpm_default_eigs_opts(iwfpm_eigs_opts* opts);
 int iwfpm_eigs(iwfpm_plan_t plan, const iwfpm_eigs_opts* opts, const void* x0,
                double* evals, void* evecs, double* eta, iwfpm_stats* stats, void* stream);
 
+/*
+ * Host-side small dense solvers used by iwfpm_eigs's Rayleigh-Ritz step,
+ * exported so that they can be checked on their own (no device needed).
+ * Matrices are complex float64, column-major, interleaved (re, im), n x n.
+ * iwfpm_dense_geneig - A c = w B c for Hermitian A and Hermitian positive
+ *   definite B (B = NULL means the identity): Cholesky of B, reduction to a
+ *   standard problem, cyclic Jacobi.  w: n ascending eigenvalues; C: the
+ *   B-orthonormal eigenvectors.  Errors: ERR_ARG (n < 1 or n > 512),
+ *   ERR_NUMERIC (B not positive definite).
+ * iwfpm_dense_svqb - for a Gram matrix G = V^H V (k x k) returns T (k x rank)
+ *   with (V T)^H (V T) = I, dropping directions whose scaled eigenvalue is
+ *   below 1e-12 of the largest.  T must hold k*k entries.
+ */
+int iwfpm_dense_geneig(int n, const double* A, const double* B, double* w, double* C);
+int iwfpm_dense_svqb(int k, const double* G, double* T, int* rank);
+
 #ifdef __cplusplus
 }
 #endif

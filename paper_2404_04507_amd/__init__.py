@@ -25,7 +25,7 @@ _LIB = None
 EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_destroy", "iwfpm_dof",
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
             "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
-            "iwfpm_profile_read"]
+            "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb"]
 
 PREC = {"fp64": 0, "fp32": 1}
 WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
@@ -90,6 +90,8 @@ def load_library():
     lib.iwfpm_apply_prec.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.iwfpm_profile.argtypes = [vp, ctypes.c_int]
     lib.iwfpm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.iwfpm_dense_geneig.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+    lib.iwfpm_dense_svqb.argtypes = [ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
     lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
     lib.iwfpm_default_eigs_opts.restype = None
     lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
@@ -126,6 +128,31 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def dense_geneig(A, B=None):
+    """The library's host Rayleigh-Ritz solver: A c = w B c (Hermitian, B PD)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    a = _f64(np.asfortranarray(A).reshape(-1, order="F").view(np.float64))
+    b = None if B is None else _f64(np.asfortranarray(np.asarray(B, dtype=np.complex128)).reshape(-1, order="F").view(np.float64))
+    w = np.zeros(n)
+    C = np.zeros(2 * n * n)
+    st = _lib().iwfpm_dense_geneig(n, _ptr(a, ctypes.c_double), None if b is None else _ptr(b, ctypes.c_double),
+                                   _ptr(w, ctypes.c_double), _ptr(C, ctypes.c_double))
+    _check(st, "iwfpm_dense_geneig")
+    return w, C.view(np.complex128).reshape(n, n, order="F")
+
+
+def dense_svqb(G):
+    G = np.asarray(G, dtype=np.complex128)
+    k = G.shape[0]
+    g = _f64(np.asfortranarray(G).reshape(-1, order="F").view(np.float64))
+    T = np.zeros(2 * k * k)
+    r = ctypes.c_int()
+    _check(_lib().iwfpm_dense_svqb(k, _ptr(g, ctypes.c_double), _ptr(T, ctypes.c_double), ctypes.byref(r)),
+           "iwfpm_dense_svqb")
+    return T.view(np.complex128)[:k * r.value].reshape(k, r.value, order="F")
 
 
 @dataclass

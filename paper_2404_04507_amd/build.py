@@ -32,8 +32,8 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arc
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-HOST_SOURCES = ["plan.cpp", "eigs_stub.cpp"]
-DEVICE_SOURCES = []
+HOST_SOURCES = ["plan.cpp", "lobpcg.cpp", "learned.cpp"]
+DEVICE_SOURCES = ["blas_kernels.hip"]
 APPLY_TUS = [(k, r, m) for k in range(4) for r in ("float", "double") for m in (16, 32, 64)]
 
 

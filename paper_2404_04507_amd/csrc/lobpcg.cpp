@@ -1,0 +1,755 @@
+// lobpcg.cpp - iwfpm_eigs: block LOBPCG for the lowest eigenpairs of H~.
+//
+// The paper solves H~ U = E U with LOBPCG and the diagonal preconditioner of
+// eq:precond (Sec. 4.1).  This is the block form: an orthonormal block X of
+// m >= nev vectors, the preconditioned residuals W and the previous search
+// directions P span the trial subspace of each Rayleigh-Ritz step.
+//
+//  * Every tall N x k operation runs on the GPU in float64 (blas_kernels.hip);
+//    the apply runs in the plan's precision.  Only the small Gram matrices
+//    (at most 96 x 96) come to the host, where the generalised eigenproblem is
+//    solved by Cholesky + cyclic Jacobi (both written here).
+//  * W and P are orthonormalised by SVQB (scaled Gram eigen-decomposition),
+//    which drops numerically dependent directions instead of failing.
+//  * Soft locking: converged columns keep their place in X but get no W / P.
+//  * Convergence: eta_i = ||H x_i - theta_i x_i|| / ((||H||_est + |theta_i|) ||x_i||)
+//    with ||H||_est = max Lambda + sum |Vhat_m|.
+//  * Float32-convolution plans iterate with float32 applies; convergence is
+//    always confirmed by a final Rayleigh-Ritz with float64 applies, and when
+//    float32 stalls (or the float64 check fails) the solver continues with
+//    float64 applies (polish).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "blas.hpp"
+#include "learned.hpp"
+#include "plan.hpp"
+
+using cd = std::complex<double>;
+
+namespace iwfpm {
+
+// ---------------------------------------------------------------------------
+// small dense Hermitian linear algebra (column-major, A[i + j*n])
+// ---------------------------------------------------------------------------
+
+// A = L L^H, L lower triangular stored in A; false if A is not (numerically) PD
+static bool cholesky(std::vector<cd>& A, int n) {
+    double scale = 0.0;
+    for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(A[i + i * n].real()));
+    for (int j = 0; j < n; ++j) {
+        double d = A[j + j * n].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(A[j + k * n]);
+        if (!(d > 1e-13 * scale)) return false;
+        double l = std::sqrt(d);
+        A[j + j * n] = l;
+        for (int i = j + 1; i < n; ++i) {
+            cd s = A[i + j * n];
+            for (int k = 0; k < j; ++k) s -= A[i + k * n] * std::conj(A[j + k * n]);
+            A[i + j * n] = s / l;
+        }
+        for (int i = 0; i < j; ++i) A[i + j * n] = 0.0;
+    }
+    return true;
+}
+
+// cyclic Jacobi for Hermitian A: A = V diag(w) V^H, w ascending
+static void jacobi_eigh(std::vector<cd> A, int n, std::vector<double>& w, std::vector<cd>& V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i + i * n] = 1.0;
+    double fro = 0.0;
+    for (auto& a : A) fro += std::norm(a);
+    fro = std::sqrt(fro);
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < j; ++i) off += std::norm(A[i + j * n]);
+        if (std::sqrt(off) <= 1e-17 * fro || fro == 0.0) break;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                cd apq = A[p + q * n];
+                double g = std::abs(apq);
+                if (g <= 1e-300) continue;
+                double app = A[p + p * n].real(), aqq = A[q + q * n].real();
+                // phase so that the (p, q) entry becomes real and positive
+                cd ph = apq / g;  // e^{i phi}
+                double tau = (aqq - app) / (2.0 * g);
+                double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                // J = diag(1, conj(ph)) * [[c, s], [-s, c]]
+                cd j00 = c, j01 = s, j10 = -s * std::conj(ph), j11 = c * std::conj(ph);
+                for (int k = 0; k < n; ++k) {  // columns: A J
+                    cd akp = A[k + p * n], akq = A[k + q * n];
+                    A[k + p * n] = akp * j00 + akq * j10;
+                    A[k + q * n] = akp * j01 + akq * j11;
+                }
+                for (int k = 0; k < n; ++k) {  // rows: J^H A
+                    cd apk = A[p + k * n], aqk = A[q + k * n];
+                    A[p + k * n] = std::conj(j00) * apk + std::conj(j10) * aqk;
+                    A[q + k * n] = std::conj(j01) * apk + std::conj(j11) * aqk;
+                }
+                A[p + q * n] = 0.0;
+                A[q + p * n] = 0.0;
+                A[p + p * n] = A[p + p * n].real();
+                A[q + q * n] = A[q + q * n].real();
+                for (int k = 0; k < n; ++k) {
+                    cd vkp = V[k + p * n], vkq = V[k + q * n];
+                    V[k + p * n] = vkp * j00 + vkq * j10;
+                    V[k + q * n] = vkp * j01 + vkq * j11;
+                }
+            }
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::vector<double> d(n);
+    for (int i = 0; i < n; ++i) d[i] = A[i + i * n].real();
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    std::vector<cd> Vs((size_t)n * n);
+    w.resize(n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = d[idx[j]];
+        for (int i = 0; i < n; ++i) Vs[i + j * n] = V[i + idx[j] * n];
+    }
+    V.swap(Vs);
+}
+
+// SVQB: T (k x r) with (B T)^H (B T) = I for the Gram matrix G = B^H B (k x k);
+// directions whose scaled eigenvalue is below eps are dropped.  Returns r.
+static int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps = 1e-12) {
+    std::vector<double> dsc(k);
+    for (int i = 0; i < k; ++i) {
+        double g = G[i + i * k].real();
+        dsc[i] = g > 0.0 ? 1.0 / std::sqrt(g) : 0.0;
+    }
+    std::vector<cd> S((size_t)k * k);
+    for (int j = 0; j < k; ++j)
+        for (int i = 0; i < k; ++i) S[i + j * k] = dsc[i] * G[i + j * k] * dsc[j];
+    for (int j = 0; j < k; ++j)  // exact Hermitian symmetry
+        for (int i = 0; i < j; ++i) {
+            cd a = 0.5 * (S[i + j * k] + std::conj(S[j + i * k]));
+            S[i + j * k] = a;
+            S[j + i * k] = std::conj(a);
+        }
+    std::vector<double> w;
+    std::vector<cd> U;
+    jacobi_eigh(S, k, w, U);
+    double wmax = k ? w[k - 1] : 0.0;
+    std::vector<int> keep;
+    for (int j = 0; j < k; ++j)
+        if (w[j] > eps * wmax && w[j] > 0.0) keep.push_back(j);
+    int r = (int)keep.size();
+    T.assign((size_t)k * r, 0.0);
+    for (int c = 0; c < r; ++c) {
+        int j = keep[c];
+        double f = 1.0 / std::sqrt(w[j]);
+        for (int i = 0; i < k; ++i) T[i + c * k] = dsc[i] * U[i + j * k] * f;
+    }
+    return r;
+}
+
+// A c = theta B c (Hermitian A, Hermitian PD B): theta ascending, C (n x n)
+static bool gen_eigh(const std::vector<cd>& A, const std::vector<cd>& B, int n, std::vector<double>& theta,
+                     std::vector<cd>& C) {
+    std::vector<cd> L = B;
+    if (!cholesky(L, n)) return false;
+    // Z = L^{-1} A
+    std::vector<cd> Z = A;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            cd s = Z[i + j * n];
+            for (int k = 0; k < i; ++k) s -= L[i + k * n] * Z[k + j * n];
+            Z[i + j * n] = s / L[i + i * n];
+        }
+    // At = L^{-1} Z^H
+    std::vector<cd> At((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            cd s = std::conj(Z[j + i * n]);
+            for (int k = 0; k < i; ++k) s -= L[i + k * n] * At[k + j * n];
+            At[i + j * n] = s / L[i + i * n];
+        }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < j; ++i) {
+            cd a = 0.5 * (At[i + j * n] + std::conj(At[j + i * n]));
+            At[i + j * n] = a;
+            At[j + i * n] = std::conj(a);
+        }
+    std::vector<cd> Y;
+    jacobi_eigh(At, n, theta, Y);
+    // C = L^{-H} Y
+    C.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = n - 1; i >= 0; --i) {
+            cd s = Y[i + j * n];
+            for (int k = i + 1; k < n; ++k) s -= std::conj(L[k + i * n]) * C[k + j * n];
+            C[i + j * n] = s / L[i + i * n].real();
+        }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// solver state
+// ---------------------------------------------------------------------------
+
+enum { B_X, B_HX, B_XN, B_HXN, B_P, B_HP, B_PN, B_HPN, B_W, B_HW, B_T1, B_COUNT };
+
+struct Solver {
+    long long N = 0;
+    int mcap = 0;
+    DeviceBuf buf[B_COUNT];
+    DeviceBuf M;          // preconditioner diagonal
+    int Mkind = -1;
+    DeviceBuf partial;    // gram / norm partials
+    DeviceBuf small;      // small matrices on the device
+    double2* hsmall = nullptr;  // pinned host mirror
+    size_t hsmall_bytes = 0;
+    int max_blocks = 512;
+};
+
+static void solver_free(Solver* s) {
+    if (!s) return;
+    for (auto& b : s->buf) dev_free(b);
+    dev_free(s->M);
+    dev_free(s->partial);
+    dev_free(s->small);
+    if (s->hsmall) (void)hipHostFree(s->hsmall);
+    delete s;
+}
+
+static int solver_ensure(iwfpm_plan_s* p, int m) {
+    Solver* s = (Solver*)p->solver;
+    if (!s) {
+        s = new Solver();
+        p->solver = s;
+    }
+    s->N = p->geom.N;
+    if (s->mcap < m) {
+        for (auto& b : s->buf)
+            if (dev_alloc(b, (size_t)s->N * m * sizeof(double2)) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+        s->mcap = m;
+    }
+    size_t need_partial = (size_t)s->max_blocks * kMaxCols * kMaxCols * sizeof(double2);
+    if (s->partial.bytes < need_partial && dev_alloc(s->partial, need_partial) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+    size_t need_small = (size_t)4 * 96 * 96 * sizeof(double2);
+    if (s->small.bytes < need_small && dev_alloc(s->small, need_small) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+    if (!s->hsmall) {
+        if (hipHostMalloc((void**)&s->hsmall, need_small) != hipSuccess) return IWFPM_ERR_ALLOC;
+        s->hsmall_bytes = need_small;
+    }
+    return IWFPM_OK;
+}
+
+// diagonal of eq:precond for H~ + sigma I (closed form for non-aliasing modes)
+static int solver_precond(iwfpm_plan_s* p, int kind) {
+    Solver* s = (Solver*)p->solver;
+    if (s->Mkind == kind && s->M.ptr) return IWFPM_OK;
+    const long long N = p->geom.N;
+    std::vector<double> M(N, 1.0);
+    if (kind == IWFPM_PRECOND_PLAIN) {
+        double sigma = std::max(0.0, p->vsum_nonzero - p->vhat0);
+        double S = 0.0;
+        const int n = p->n;
+        for (size_t i = 0; i < p->vre.size(); ++i) {
+            bool zero = true;
+            for (int j = 0; j < n; ++j) zero = zero && p->modes[i * n + j] == 0;
+            if (!zero) S += p->vre[i] * p->vre[i] + p->vim[i] * p->vim[i];
+        }
+        std::vector<int> k(n);
+        for (long long gp = 0; gp < N; ++gp) {
+            host_label(p, gp, k.data());
+            double h = host_kinetic(p, k.data()) + p->vhat0 + sigma;
+            M[host_grid_to_vec(p, gp)] = h / (h * h + S);
+        }
+    }
+    if (dev_alloc(s->M, N * sizeof(double)) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+    if (hipMemcpy(s->M.ptr, M.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return IWFPM_ERR_DEVICE;
+    s->Mkind = kind;
+    return IWFPM_OK;
+}
+
+struct Ctx {
+    iwfpm_plan_s* p;
+    Solver* s;
+    hipStream_t st;
+    long long N;
+    double2* col(int b, int j) const { return (double2*)s->buf[b].ptr + (size_t)j * N; }
+};
+
+#define CHECK_HIP(x)                                  \
+    do {                                              \
+        if ((x) != hipSuccess) return IWFPM_ERR_DEVICE; \
+    } while (0)
+
+// C (p x q) = L^H R on the host, chunking both sides by kMaxCols
+static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<double2*>& R, std::vector<cd>& C) {
+    const int p = (int)L.size(), q = (int)R.size();
+    C.assign((size_t)p * q, 0.0);
+    double2* dC = (double2*)c.s->small.ptr;
+    for (int i0 = 0; i0 < p; i0 += kMaxCols) {
+        int pi = std::min(kMaxCols, p - i0);
+        for (int j0 = 0; j0 < q; j0 += kMaxCols) {
+            int qj = std::min(kMaxCols, q - j0);
+            ColPtrs a{}, b{};
+            for (int i = 0; i < pi; ++i) a.p[i] = L[i0 + i];
+            for (int j = 0; j < qj; ++j) b.p[j] = R[j0 + j];
+            CHECK_HIP(gram(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, dC, c.st));
+            CHECK_HIP(hipMemcpyAsync(c.s->hsmall, dC, (size_t)pi * qj * sizeof(double2), hipMemcpyDeviceToHost, c.st));
+            CHECK_HIP(hipStreamSynchronize(c.st));
+            for (int j = 0; j < qj; ++j)
+                for (int i = 0; i < pi; ++i) {
+                    double2 v = c.s->hsmall[(size_t)j * pi + i];
+                    C[(size_t)(i0 + i) + (size_t)(j0 + j) * p] = cd(v.x, v.y);
+                }
+        }
+    }
+    return IWFPM_OK;
+}
+
+// Y_j (+)= sum_i A_i C[i + j*ldc]  for the q outputs, rows of C offset by r0
+static int dev_lincomb(Ctx& c, const std::vector<double2*>& A, const std::vector<double2*>& Y, const std::vector<cd>& Cm,
+                       int ldc, int r0, double beta) {
+    const int p = (int)A.size(), q = (int)Y.size();
+    if (q == 0) return IWFPM_OK;
+    if (p == 0) {
+        if (beta == 0.0)
+            for (auto y : Y) CHECK_HIP(hipMemsetAsync(y, 0, c.N * sizeof(double2), c.st));
+        return IWFPM_OK;
+    }
+    double2* dC = (double2*)c.s->small.ptr + 96 * 96;
+    for (int j0 = 0; j0 < q; j0 += 32) {
+        int qj = std::min(32, q - j0);
+        // pack C[r0 .. r0+p) x [j0 .. j0+qj) column-major p x qj
+        double2* h = c.s->hsmall + 96 * 96;
+        CHECK_HIP(hipStreamSynchronize(c.st));  // the host mirror is reused
+        for (int j = 0; j < qj; ++j)
+            for (int i = 0; i < p; ++i) {
+                cd v = Cm[(size_t)(r0 + i) + (size_t)(j0 + j) * ldc];
+                h[(size_t)j * p + i] = make_double2(v.real(), v.imag());
+            }
+        CHECK_HIP(hipMemcpyAsync(dC, h, (size_t)p * qj * sizeof(double2), hipMemcpyHostToDevice, c.st));
+        ColPtrs a{}, y{};
+        for (int i = 0; i < p; ++i) a.p[i] = A[i];
+        for (int j = 0; j < qj; ++j) y.p[j] = Y[j0 + j];
+        CHECK_HIP(lincomb(a, p, y, qj, dC, beta, c.N, c.st));
+    }
+    return IWFPM_OK;
+}
+
+static int col_norms(Ctx& c, const std::vector<double2*>& V, std::vector<double>& out) {
+    const int m = (int)V.size();
+    out.assign(m, 0.0);
+    double* dOut = (double*)((double2*)c.s->small.ptr + 2 * 96 * 96);
+    for (int j0 = 0; j0 < m; j0 += kMaxCols) {
+        int mj = std::min(kMaxCols, m - j0);
+        ColPtrs v{};
+        for (int j = 0; j < mj; ++j) v.p[j] = V[j0 + j];
+        CHECK_HIP(colnorm2(v, mj, c.N, (double*)c.s->partial.ptr, c.s->max_blocks, dOut, c.st));
+        double* h = (double*)(c.s->hsmall + 2 * 96 * 96);
+        CHECK_HIP(hipMemcpyAsync(h, dOut, mj * sizeof(double), hipMemcpyDeviceToHost, c.st));
+        CHECK_HIP(hipStreamSynchronize(c.st));
+        for (int j = 0; j < mj; ++j) out[j0 + j] = std::sqrt(std::max(0.0, h[j]));
+    }
+    return IWFPM_OK;
+}
+
+static std::vector<double2*> cols(Ctx& c, int b, int j0, int cnt) {
+    std::vector<double2*> v(cnt);
+    for (int j = 0; j < cnt; ++j) v[j] = c.col(b, j0 + j);
+    return v;
+}
+
+// Rayleigh-Ritz on the block X alone (orthonormal X, HX = H X): X <- X C, HX <- HX C
+static int rr_block(Ctx& c, int m, std::vector<double>& theta) {
+    std::vector<cd> G;
+    int rc = host_gram(c, cols(c, B_X, 0, m), cols(c, B_HX, 0, m), G);
+    if (rc) return rc;
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < j; ++i) {
+            cd a = 0.5 * (G[i + j * m] + std::conj(G[j + i * m]));
+            G[i + j * m] = a;
+            G[j + i * m] = std::conj(a);
+        }
+    std::vector<cd> C;
+    jacobi_eigh(G, m, theta, C);
+    if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
+    if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), cols(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
+    std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
+    std::swap(c.s->buf[B_HX], c.s->buf[B_HXN]);
+    return IWFPM_OK;
+}
+
+static int apply_block(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats* stats) {
+    if (cnt <= 0) return IWFPM_OK;
+    int rc = plan_apply(c.p, c.col(bin, 0), c.col(bout, 0), cnt, prec, c.st);
+    if (stats) stats->matvecs += cnt;
+    return rc;
+}
+
+static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
+               iwfpm_stats* stats, hipStream_t st) {
+    const int nev = o.nev;
+    int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
+    if (m < nev || m > 32) return IWFPM_ERR_ARG;
+    if (m > p->geom.N) return IWFPM_ERR_ARG;
+    int rc = solver_ensure(p, m);
+    if (rc) return rc;
+    int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
+    if ((rc = solver_precond(p, pk))) return rc;
+    Solver* s = (Solver*)p->solver;
+    Ctx c{p, s, st, p->geom.N};
+    const long long N = c.N;
+    const double hnorm = p->lam_max + p->vsum_abs;
+    int prec = p->opts.precision;
+    if (!p->sched[prec].ok) prec = 1 - prec;
+    if (!p->sched[prec].ok) return IWFPM_ERR_UNSUPPORTED;
+    const bool can64 = p->sched[0].ok;
+    const char* venv = std::getenv("IWFPM_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
+    LearnedPrecond* lp = nullptr;
+    if (o.precond == IWFPM_PRECOND_LEARNED) {
+        lp = p->learned;
+        if (!lp || !learned_ready(lp, p)) return IWFPM_ERR_WEIGHTS;
+    }
+
+    // start block
+    if (x0) {
+        CHECK_HIP(hipMemcpyAsync(c.col(B_X, 0), x0, (size_t)N * m * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    } else {
+        CHECK_HIP(randn(c.col(B_X, 0), N * m, o.seed, st));
+    }
+    {
+        std::vector<cd> G, T;
+        if ((rc = host_gram(c, cols(c, B_X, 0, m), cols(c, B_X, 0, m), G))) return rc;
+        int r = svqb(G, m, T);
+        if (r < m) return IWFPM_ERR_NUMERIC;
+        if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), T, m, 0, 0.0))) return rc;
+        std::swap(s->buf[B_X], s->buf[B_XN]);
+    }
+    if ((rc = apply_block(c, B_X, B_HX, m, prec, stats))) return rc;
+    std::vector<double> theta;
+    if ((rc = rr_block(c, m, theta))) return rc;
+
+    int mp = 0;                        // columns of P / HP
+    std::vector<double> eta(m, 1.0);
+    int it = 0, polished = 0, restarts = 0, fallback = 0;
+    double best_eta = 1e300;
+    int best_it = 0;
+    bool done = false;
+    int status = IWFPM_OK;
+    for (;;) {
+        // residuals and convergence
+        {
+            std::vector<double2*> X = cols(c, B_X, 0, m), HX = cols(c, B_HX, 0, m), R = cols(c, B_T1, 0, m);
+            ColPtrs hx{}, x{}, r{};
+            Reals th{};
+            for (int j = 0; j < m; ++j) {
+                hx.p[j] = HX[j];
+                x.p[j] = X[j];
+                r.p[j] = R[j];
+                th.v[j] = theta[j];
+            }
+            CHECK_HIP(residual(hx, x, r, th, m, N, st));
+            std::vector<double> rn;
+            if ((rc = col_norms(c, R, rn))) return rc;
+            for (int j = 0; j < m; ++j) {
+                eta[j] = rn[j] / (hnorm + std::fabs(theta[j]));
+                if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
+            }
+        }
+        int conv = 0;
+        double worst = 0.0;
+        for (int j = 0; j < nev; ++j) {
+            conv += eta[j] <= o.tol;
+            worst = std::max(worst, eta[j]);
+        }
+        if (verbose)
+            std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d\n", it,
+                         prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp);
+        if (conv == nev) {
+            if (prec == 0) {
+                done = true;
+                break;
+            }
+            // confirm with float64 applies: Rayleigh-Ritz of X with the float64 H
+            if (!can64) {
+                done = true;
+                break;
+            }
+            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
+            if ((rc = rr_block(c, m, theta))) return rc;
+            prec = 0;
+            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
+            continue;  // recompute residuals with float64; iterate on if needed
+        }
+        if (it >= o.maxit) {
+            status = IWFPM_ERR_NOCONV;
+            break;
+        }
+        // float32 stall detection -> continue with float64 applies: either the
+        // residuals reached the float32 convolution noise floor, or they stopped
+        // improving
+        const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
+        if (prec == 1 && o.polish && can64 && worst < floor32 && worst > o.tol) {
+            prec = 0;
+            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
+            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
+            if ((rc = rr_block(c, m, theta))) return rc;
+            best_eta = 1e300;
+            continue;
+        }
+        if (worst < 0.5 * best_eta) {
+            best_eta = worst;
+            best_it = it;
+        } else if (prec == 1 && o.polish && can64 && worst < 1e-5 && it - best_it >= 20) {
+            prec = 0;
+            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
+            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
+            if ((rc = rr_block(c, m, theta))) return rc;
+            best_eta = 1e300;
+            continue;
+        }
+        ++it;
+        if (prec == 0 && p->opts.precision == 1) ++polished;
+
+        // active set and preconditioned residuals W = M R_A
+        std::vector<int> act;
+        for (int j = 0; j < m; ++j)
+            if (eta[j] > o.tol) act.push_back(j);
+        const int ma = (int)act.size();
+        {
+            ColPtrs r{}, w{};
+            for (int a = 0; a < ma; ++a) {
+                r.p[a] = c.col(B_T1, act[a]);
+                w.p[a] = c.col(B_W, a);
+            }
+            bool used_learned = false;
+            if (lp) {
+                int lrc = learned_apply(lp, p, r, w, ma, st);
+                if (lrc == IWFPM_OK) used_learned = true;
+                else {
+                    fallback = 1;
+                    lp = nullptr;
+                }
+            }
+            if (!used_learned) CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
+        }
+        // Orthonormal trial basis [X, P, W] (each block orthonormal and
+        // orthogonal to the previous ones), so that the Rayleigh-Ritz Gram
+        // matrix of the basis stays close to the identity and float32 noise
+        // in H W is not amplified near convergence.
+        //   P_A <- P_A - X (X^H P_A), HP_A likewise, then SVQB  -> PN / HPN
+        //   W   <- W - X (X^H W) - PN (PN^H W), twice, then SVQB -> W
+        int mq = 0;
+        if (mp > 0) {
+            std::vector<double2*> Pa, HPa;
+            for (int a : act)
+                if (a < mp) {
+                    Pa.push_back(c.col(B_P, a));
+                    HPa.push_back(c.col(B_HP, a));
+                }
+            const int k = (int)Pa.size();
+            if (k > 0) {
+                std::vector<cd> G, T;
+                if ((rc = host_gram(c, cols(c, B_X, 0, m), Pa, G))) return rc;
+                for (auto& g : G) g = -g;
+                if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), Pa, G, m, 0, 1.0))) return rc;
+                if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), HPa, G, m, 0, 1.0))) return rc;
+                if ((rc = host_gram(c, Pa, Pa, G))) return rc;
+                mq = svqb(G, k, T);
+                if ((rc = dev_lincomb(c, Pa, cols(c, B_PN, 0, mq), T, k, 0, 0.0))) return rc;
+                if ((rc = dev_lincomb(c, HPa, cols(c, B_HPN, 0, mq), T, k, 0, 0.0))) return rc;
+            }
+        }
+        int mw = 0;
+        {
+            std::vector<double2*> XP = cols(c, B_X, 0, m);
+            for (int j = 0; j < mq; ++j) XP.push_back(c.col(B_PN, j));
+            for (int pass = 0; pass < 2; ++pass) {
+                std::vector<cd> G;
+                if ((rc = host_gram(c, XP, cols(c, B_W, 0, ma), G))) return rc;
+                for (auto& g : G) g = -g;
+                if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G, (int)XP.size(), 0, 1.0))) return rc;
+            }
+            std::vector<cd> G, T;
+            if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
+            mw = svqb(G, ma, T, 1e-10);
+            if ((rc = dev_lincomb(c, cols(c, B_W, 0, ma), cols(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
+            std::swap(s->buf[B_W], s->buf[B_T1]);
+        }
+        if ((rc = apply_block(c, B_W, B_HW, mw, prec, stats))) return rc;
+        // Rayleigh-Ritz on span[X, W, P]
+        std::vector<cd> Cm;
+        std::vector<double> th;
+        int ns = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            int mqq = attempt == 0 ? mq : 0;
+            ns = m + mw + mqq;
+            std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m);
+            for (int j = 0; j < mw; ++j) {
+                S.push_back(c.col(B_W, j));
+                HS.push_back(c.col(B_HW, j));
+            }
+            for (int j = 0; j < mqq; ++j) {
+                S.push_back(c.col(B_PN, j));
+                HS.push_back(c.col(B_HPN, j));
+            }
+            std::vector<cd> A, B;
+            if ((rc = host_gram(c, S, HS, A))) return rc;
+            if ((rc = host_gram(c, S, S, B))) return rc;
+            for (int j = 0; j < ns; ++j)
+                for (int i = 0; i <= j; ++i) {
+                    cd a = 0.5 * (A[i + j * ns] + std::conj(A[j + i * ns]));
+                    A[i + j * ns] = a;
+                    A[j + i * ns] = std::conj(a);
+                    cd b = 0.5 * (B[i + j * ns] + std::conj(B[j + i * ns]));
+                    B[i + j * ns] = b;
+                    B[j + i * ns] = std::conj(b);
+                }
+            if (gen_eigh(A, B, ns, th, Cm)) {
+                mq = mqq;
+                break;
+            }
+            if (attempt == 1 || mq == 0) return IWFPM_ERR_NUMERIC;
+            ++restarts;
+        }
+        // updates: X <- S C, HX <- HS C, P <- [W P] C_WP, HP <- [HW HP] C_WP
+        {
+            std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m), SWP, HSWP;
+            for (int j = 0; j < mw; ++j) {
+                S.push_back(c.col(B_W, j));
+                HS.push_back(c.col(B_HW, j));
+                SWP.push_back(c.col(B_W, j));
+                HSWP.push_back(c.col(B_HW, j));
+            }
+            for (int j = 0; j < mq; ++j) {
+                S.push_back(c.col(B_PN, j));
+                HS.push_back(c.col(B_HPN, j));
+                SWP.push_back(c.col(B_PN, j));
+                HSWP.push_back(c.col(B_HPN, j));
+            }
+            if ((rc = dev_lincomb(c, S, cols(c, B_XN, 0, m), Cm, ns, 0, 0.0))) return rc;
+            if ((rc = dev_lincomb(c, HS, cols(c, B_HXN, 0, m), Cm, ns, 0, 0.0))) return rc;
+            if ((rc = dev_lincomb(c, SWP, cols(c, B_P, 0, m), Cm, ns, m, 0.0))) return rc;
+            if ((rc = dev_lincomb(c, HSWP, cols(c, B_HP, 0, m), Cm, ns, m, 0.0))) return rc;
+            std::swap(s->buf[B_X], s->buf[B_XN]);
+            std::swap(s->buf[B_HX], s->buf[B_HXN]);
+            mp = m;
+        }
+        theta.assign(th.begin(), th.begin() + m);
+    }
+    (void)done;
+    if (stats) {
+        stats->iterations = it;
+        stats->restarts = restarts;
+        stats->fallback = fallback;
+        stats->polished = polished;
+        int conv = 0;
+        for (int j = 0; j < nev; ++j) conv += eta[j] <= o.tol;
+        stats->converged = conv;
+    }
+    for (int j = 0; j < nev; ++j) {
+        evals[j] = theta[j];
+        if (eta_out) eta_out[j] = eta[j];
+    }
+    if (evecs)
+        CHECK_HIP(hipMemcpyAsync(evecs, c.col(B_X, 0), (size_t)N * nev * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    return status;
+}
+
+}  // namespace iwfpm
+
+using namespace iwfpm;
+
+extern "C" {
+
+void iwfpm_default_eigs_opts(iwfpm_eigs_opts* o) {
+    if (!o) return;
+    o->nev = 8;
+    o->block = 0;
+    o->tol = 1e-8;
+    o->maxit = 1000;
+    o->precond = IWFPM_PRECOND_PLAIN;
+    o->seed = 2404045070ull;
+    o->polish = 1;
+}
+
+int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, double* evals, void* evecs, double* eta,
+               iwfpm_stats* stats, void* stream) {
+    if (!p || !opts || !evals) return IWFPM_ERR_ARG;
+    if (opts->nev < 1 || opts->nev > p->geom.N || !(opts->tol > 0.0) || opts->maxit < 0) return IWFPM_ERR_ARG;
+    if (opts->precond < 0 || opts->precond > 2) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    DeviceGuard guard(p->opts.device);
+    if (!guard.ok) return IWFPM_ERR_DEVICE;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = run(p, *opts, x0, evals, evecs, eta, stats, (hipStream_t)stream);
+    if (stats) stats->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int iwfpm_dense_geneig(int n, const double* A, const double* B, double* w, double* C) {
+    if (n < 1 || n > 512 || !A || !w || !C) return IWFPM_ERR_ARG;
+    std::vector<cd> a((size_t)n * n), b((size_t)n * n, 0.0), c;
+    for (size_t i = 0; i < a.size(); ++i) a[i] = cd(A[2 * i], A[2 * i + 1]);
+    if (B)
+        for (size_t i = 0; i < b.size(); ++i) b[i] = cd(B[2 * i], B[2 * i + 1]);
+    else
+        for (int i = 0; i < n; ++i) b[i + (size_t)i * n] = 1.0;
+    std::vector<double> th;
+    if (!gen_eigh(a, b, n, th, c)) return IWFPM_ERR_NUMERIC;
+    for (int i = 0; i < n; ++i) w[i] = th[i];
+    for (size_t i = 0; i < c.size(); ++i) {
+        C[2 * i] = c[i].real();
+        C[2 * i + 1] = c[i].imag();
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_dense_svqb(int k, const double* G, double* T, int* rank) {
+    if (k < 1 || k > 512 || !G || !T || !rank) return IWFPM_ERR_ARG;
+    std::vector<cd> g((size_t)k * k), t;
+    for (size_t i = 0; i < g.size(); ++i) g[i] = cd(G[2 * i], G[2 * i + 1]);
+    *rank = svqb(g, k, t);
+    for (size_t i = 0; i < t.size(); ++i) {
+        T[2 * i] = t[i].real();
+        T[2 * i + 1] = t[i].imag();
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_destroy(iwfpm_plan_t p) {
+    if (!p) return IWFPM_ERR_ARG;
+    if (!p->host_only) {
+        DeviceGuard g(p->opts.device);
+        (void)hipDeviceSynchronize();
+        dev_free(p->d_slice_a);
+        dev_free(p->d_slice_g);
+        dev_free(p->d_vtab32);
+        dev_free(p->d_vtab64);
+        dev_free(p->d_vgrid32);
+        dev_free(p->d_vgrid64);
+        dev_free(p->d_ws);
+        for (auto& sl : p->prof.ring)
+            for (auto& e : sl.ev)
+                if (e) (void)hipEventDestroy(e);
+        solver_free((Solver*)p->solver);
+        learned_free(p->learned);
+    }
+    delete p;
+    return IWFPM_OK;
+}
+
+}  // extern "C"

@@ -14,6 +14,7 @@ import pytest
 import oracle as O
 import paper_2404_04507_amd as lib
 from paper_2404_04507_amd import workloads as W
+from paper_2404_04507_amd import dense_geneig, dense_svqb  # noqa: F401
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "iwfpm.h")
 
@@ -119,3 +120,40 @@ def test_duplicate_modes_are_merged():
     P = np.array([[1.0, W.GOLDEN]])
     with lib.Plan(P, [4], [4], [[1, 0], [-1, 0], [1, 0], [-1, 0]], [0.5, 0.5, 0.25, 0.25], device=-1) as p:
         assert abs(p.norm_bound() - (p.kinetic().max() + 1.5)) < 1e-12
+
+
+# --- the host Rayleigh-Ritz solver of iwfpm_eigs ---------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 48, 96])
+def test_dense_geneig_matches_lapack(n):
+    """Cholesky + cyclic Jacobi against LAPACK's generalised Hermitian eigensolver."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = A + A.conj().T
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    B = Z @ Z.conj().T + n * np.eye(n)
+    w, C = lib.dense_geneig(A, B)
+    wr = sla.eigh(A, B, eigvals_only=True)
+    assert np.allclose(w, wr, rtol=1e-12, atol=1e-12 * np.abs(wr).max())
+    assert np.allclose(C.conj().T @ B @ C, np.eye(n), atol=1e-10)
+    assert np.allclose(A @ C, B @ C * w[None, :], atol=1e-9 * np.abs(A).max())
+
+
+def test_dense_geneig_degenerate_and_identity():
+    A = np.diag([3.0, 1.0, 1.0, -2.0]).astype(complex)
+    A[0, 3] = A[3, 0] = 1e-9
+    w, C = lib.dense_geneig(A)
+    assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-14)
+    with pytest.raises(lib.IwfpmError):
+        lib.dense_geneig(A, -np.eye(4))
+
+
+def test_dense_svqb_drops_dependent_directions():
+    rng = np.random.default_rng(3)
+    V = rng.standard_normal((200, 5)) + 1j * rng.standard_normal((200, 5))
+    V = np.concatenate([V, V[:, :2] * 2.0 + V[:, 2:4]], axis=1)  # rank 5 of 7
+    T = lib.dense_svqb(V.conj().T @ V)
+    assert T.shape == (7, 5)
+    Q = V @ T
+    assert np.allclose(Q.conj().T @ Q, np.eye(5), atol=1e-10)
