@@ -23,18 +23,26 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// gram: partial[b][j][i] = sum over rows of block b of conj(L_i[r]) R_j[r]
-// Thread (ti, tj) of a 16 x 16 grid owns the 4 x 4 output tile
-// i = 4 ti + a, j = 4 tj + b.  Rows are staged through LDS 16 at a time.
+// gram: partial[b][j*p + i] = sum over the rows of block b of conj(L_i[r]) R_j[r]
+//
+// The p x q output is cut into 4 x 4 tiles; with ntile tiles, the 256 threads
+// form 256 / ntile row groups, each summing its own subset of the staged rows
+// for its tile, so that small Grams still keep every thread busy.  Rows are
+// staged through LDS `rows` at a time (as many as fit); at the end the row
+// groups are summed in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int kGramRows = 16;
-
 __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long rows_per_block,
-                                              double2* __restrict__ partial) {
-    __shared__ double2 sL[kGramRows][kMaxCols + 1];
-    __shared__ double2 sR[kGramRows][kMaxCols + 1];
+                                              int rows, double2* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pl = p | 1, pr = q | 1;  // odd pitches
+    double2* sL = reinterpret_cast<double2*>(smem);
+    double2* sR = sL + rows * pl;
     const int tid = threadIdx.x;
-    const int ti = tid & 15, tj = tid >> 4;
+    const int TP = (p + 3) >> 2, TQ = (q + 3) >> 2, ntile = TP * TQ;
+    const int ngroups = 256 / ntile;
+    const int grp = tid / ntile, tile = tid - grp * ntile;
+    const bool active = grp < ngroups;
+    const int ti = tile % TP, tj = tile / TP;
     double2 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -42,30 +50,34 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
     const long long r0 = (long long)blockIdx.x * rows_per_block;
     const long long r1 = min(N, r0 + rows_per_block);
-    for (long long rb = r0; rb < r1; rb += kGramRows) {
-        const int nr = (int)min((long long)kGramRows, r1 - rb);
-        // stage: column c, row rr; consecutive threads take consecutive rows
-        for (int e = tid; e < kGramRows * p; e += 256) {
-            int c = e / kGramRows, rr = e - c * kGramRows;
-            sL[rr][c] = rr < nr ? L.p[c][rb + rr] : make_double2(0.0, 0.0);
+    for (long long rb = r0; rb < r1; rb += rows) {
+        const int nr = (int)min((long long)rows, r1 - rb);
+        for (int e = tid; e < rows * p; e += 256) {
+            int c = e / rows, rr = e - c * rows;
+            sL[rr * pl + c] = rr < nr ? L.p[c][rb + rr] : make_double2(0.0, 0.0);
         }
-        for (int e = tid; e < kGramRows * q; e += 256) {
-            int c = e / kGramRows, rr = e - c * kGramRows;
-            sR[rr][c] = rr < nr ? R.p[c][rb + rr] : make_double2(0.0, 0.0);
+        for (int e = tid; e < rows * q; e += 256) {
+            int c = e / rows, rr = e - c * rows;
+            sR[rr * pr + c] = rr < nr ? R.p[c][rb + rr] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        if (4 * ti < p && 4 * tj < q) {
-            for (int rr = 0; rr < nr; ++rr) {
+        if (active) {
+            for (int rr = grp; rr < nr; rr += ngroups) {
                 double2 l[4], r[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) l[a] = sL[rr][4 * ti + a];
+                for (int a = 0; a < 4; ++a) {
+                    int i = 4 * ti + a;
+                    l[a] = i < p ? sL[rr * pl + i] : make_double2(0.0, 0.0);
+                }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) r[b] = sR[rr][4 * tj + b];
+                for (int b = 0; b < 4; ++b) {
+                    int j = 4 * tj + b;
+                    r[b] = j < q ? sR[rr * pr + j] : make_double2(0.0, 0.0);
+                }
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
-                        // conj(l) * r
                         acc[a][b].x += l[a].x * r[b].x + l[a].y * r[b].y;
                         acc[a][b].y += l[a].x * r[b].y - l[a].y * r[b].x;
                     }
@@ -73,36 +85,60 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
         }
         __syncthreads();
     }
+    // sum the row groups: red[grp][tile][16]
+    double2* red = reinterpret_cast<double2*>(smem);
+    if (active) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) red[((size_t)grp * ntile + tile) * 16 + a * 4 + b] = acc[a][b];
+    }
+    __syncthreads();
     double2* out = partial + (size_t)blockIdx.x * p * q;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int i = 4 * ti + a, j = 4 * tj + b;
-            if (i < p && j < q) out[(size_t)j * p + i] = acc[a][b];
+    for (int e = tid; e < ntile * 16; e += 256) {
+        int t = e >> 4, ab = e & 15;
+        int i = 4 * (t % TP) + (ab >> 2), j = 4 * (t / TP) + (ab & 3);
+        if (i >= p || j >= q) continue;
+        double2 sum = make_double2(0.0, 0.0);
+        for (int g = 0; g < ngroups; ++g) {
+            double2 v = red[((size_t)g * ntile + t) * 16 + ab];
+            sum.x += v.x;
+            sum.y += v.y;
         }
+        out[(size_t)j * p + i] = sum;
+    }
 }
 
-// sum the partials of nb blocks in block order: C[j*p + i]
-__global__ void k_reduce_partials(const double2* __restrict__ partial, int nb, int count, double2* __restrict__ C) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
+__global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restrict__ partial, int nb, int count,
+                                                         double2* __restrict__ C) {
+    __shared__ double2 red[256];
+    const int e = blockIdx.x;
     double2 s = make_double2(0.0, 0.0);
-    for (int b = 0; b < nb; ++b) {
+    for (int b = threadIdx.x; b < nb; b += 256) {
         double2 v = partial[(size_t)b * count + e];
         s.x += v.x;
         s.y += v.y;
     }
-    C[e] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x].x += red[threadIdx.x + w].x;
+            red[threadIdx.x].y += red[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C[e] = red[0];
 }
 
 // ---------------------------------------------------------------------------
-// lincomb: Y_j = beta Y_j + sum_i A_i C[j*p + i]   (q <= QB)
+// lincomb: Y_j = beta Y_j + sum_i A_i C[j*p + i]   (q <= QB <= 48)
 // ---------------------------------------------------------------------------
 template <int QB>
 __global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, int q, const double2* __restrict__ C,
                                                  double beta, long long N) {
-    __shared__ double2 sC[kMaxCols * 32];
+    __shared__ double2 sC[kMaxCols * 48];
     for (int e = threadIdx.x; e < p * q; e += blockDim.x) sC[e] = C[e];
     __syncthreads();
     for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
@@ -168,12 +204,46 @@ __global__ void __launch_bounds__(256) k_colnorm2(ColPtrs V, int m, long long N,
     }
 }
 
-__global__ void k_reduce_real(const double* __restrict__ partial, int nb, int count, double* __restrict__ out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+__global__ void __launch_bounds__(256) k_reduce_real(const double* __restrict__ partial, int nb, int count,
+                                                     double* __restrict__ out) {
+    __shared__ double red[256];
+    const int e = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * count + e];
-    out[e] = s;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[(size_t)b * count + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = red[0];
+}
+
+// R_j = HX_j - theta_j X_j and the block's partial sums of ||R_j||^2
+__global__ void __launch_bounds__(256) k_residual_norm(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
+                                                       long long N, long long rows_per_block,
+                                                       double* __restrict__ partial) {
+    __shared__ double red[256];
+    const long long r0 = (long long)blockIdx.x * rows_per_block;
+    const long long r1 = min(N, r0 + rows_per_block);
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        const double t = theta.v[j];
+        for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+            double2 h = HX.p[j][r], x = X.p[j][r];
+            double2 v = make_double2(h.x - t * x.x, h.y - t * x.y);
+            Rout.p[j][r] = v;
+            s += v.x * v.x + v.y * v.y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * m + j] = red[0];
+        __syncthreads();
+    }
 }
 
 __global__ void k_precond(ColPtrs R, ColPtrs W, int m, const double* __restrict__ M, long long N) {
@@ -221,12 +291,17 @@ static int grid_for(long long N, int threads, int cap = 4096) {
 hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
                 double2* C, hipStream_t st) {
     if (p <= 0 || q <= 0) return hipSuccess;
+    const int pl = p | 1, pr = q | 1;
+    int rows = (int)std::min<long long>(128, (48 * 1024) / ((pl + pr) * (long long)sizeof(double2)));
+    rows = std::max(rows, 8);
     long long rpb = (N + max_blocks - 1) / max_blocks;
-    rpb = ((rpb + kGramRows - 1) / kGramRows) * kGramRows;
+    rpb = ((rpb + rows - 1) / rows) * rows;
     int nb = (int)((N + rpb - 1) / rpb);
-    k_gram<<<nb, 256, 0, st>>>(L, p, R, q, N, rpb, partial);
+    int ntile = ((p + 3) / 4) * ((q + 3) / 4);
+    size_t lds = std::max((size_t)rows * (pl + pr) * sizeof(double2), (size_t)(256 / ntile) * ntile * 16 * sizeof(double2));
+    k_gram<<<nb, 256, lds, st>>>(L, p, R, q, N, rpb, rows, partial);
     int cnt = p * q;
-    k_reduce_partials<<<(cnt + 255) / 256, 256, 0, st>>>(partial, nb, cnt, C);
+    k_reduce_partials<<<cnt, 256, 0, st>>>(partial, nb, cnt, C);
     return hipGetLastError();
 }
 
@@ -236,7 +311,8 @@ hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const doubl
     int nb = grid_for(N, 256, 2048);
     if (q <= 8) k_lincomb<8><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
     else if (q <= 16) k_lincomb<16><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-    else k_lincomb<32><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+    else if (q <= 32) k_lincomb<32><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+    else k_lincomb<48><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
     return hipGetLastError();
 }
 
@@ -252,7 +328,17 @@ hipError_t colnorm2(const ColPtrs& V, int m, long long N, double* partial, int m
     long long rpb = (N + max_blocks - 1) / max_blocks;
     int nb = (int)((N + rpb - 1) / rpb);
     k_colnorm2<<<nb, 256, 0, st>>>(V, m, N, rpb, partial);
-    k_reduce_real<<<(m + 255) / 256, 256, 0, st>>>(partial, nb, m, out);
+    k_reduce_real<<<m, 256, 0, st>>>(partial, nb, m, out);
+    return hipGetLastError();
+}
+
+hipError_t residual_norm(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, const Reals& theta, int m, long long N,
+                         double* partial, int max_blocks, double* out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    long long rpb = (N + max_blocks - 1) / max_blocks;
+    int nb = (int)((N + rpb - 1) / rpb);
+    k_residual_norm<<<nb, 256, 0, st>>>(HX, X, R, theta, m, N, rpb, partial);
+    k_reduce_real<<<m, 256, 0, st>>>(partial, nb, m, out);
     return hipGetLastError();
 }
 

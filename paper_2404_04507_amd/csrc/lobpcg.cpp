@@ -9,9 +9,15 @@
 //    the apply runs in the plan's precision.  Only the small Gram matrices
 //    (at most 96 x 96) come to the host, where the generalised eigenproblem is
 //    solved by Cholesky + cyclic Jacobi (both written here).
-//  * W and P are orthonormalised by SVQB (scaled Gram eigen-decomposition),
-//    which drops numerically dependent directions instead of failing.
-//  * Soft locking: converged columns keep their place in X but get no W / P.
+//  * The trial basis [X W P] is kept orthonormal (so its Gram matrix is the
+//    identity): W is orthogonalised against X and P twice and orthonormalised
+//    by SVQB (scaled Gram eigen-decomposition, which drops numerically
+//    dependent directions instead of failing); the next P is formed in the
+//    small coefficient space, orthogonal to the new X, so no tall
+//    orthogonalisation of P is needed.  X^H H X = diag(theta) is reused, so
+//    only [X W P]^H [HW HP] is computed on the GPU.
+//  * Soft locking: converged columns keep their place in X but contribute no
+//    W and no P direction.
 //  * Convergence: eta_i = ||H x_i - theta_i x_i|| / ((||H||_est + |theta_i|) ||x_i||)
 //    with ||H||_est = max Lambda + sum |Vhat_m|.
 //  * Float32-convolution plans iterate with float32 applies; convergence is
@@ -203,6 +209,11 @@ static bool gen_eigh(const std::vector<cd>& A, const std::vector<cd>& B, int n, 
 
 enum { B_X, B_HX, B_XN, B_HXN, B_P, B_HP, B_PN, B_HPN, B_W, B_HW, B_T1, B_COUNT };
 
+// staging for small coefficient matrices sent to the device: a ring of
+// pinned host slots, so that enqueueing never waits on the previous copy
+constexpr int kRingSlots = 64;
+constexpr size_t kSlot = (size_t)kMaxCols * 48;  // complex entries per slot
+
 struct Solver {
     long long N = 0;
     int mcap = 0;
@@ -210,10 +221,13 @@ struct Solver {
     DeviceBuf M;          // preconditioner diagonal
     int Mkind = -1;
     DeviceBuf partial;    // gram / norm partials
-    DeviceBuf small;      // small matrices on the device
-    double2* hsmall = nullptr;  // pinned host mirror
-    size_t hsmall_bytes = 0;
-    int max_blocks = 512;
+    DeviceBuf small;      // gram results and norms on the device
+    DeviceBuf dring;      // coefficient slots on the device
+    double2* hsmall = nullptr;  // pinned host mirror of `small`
+    double2* hring = nullptr;   // pinned coefficient slots
+    int ring_next = 0;
+    int ring_since_sync = 0;
+    int max_blocks = 1024;
 };
 
 static void solver_free(Solver* s) {
@@ -222,7 +236,9 @@ static void solver_free(Solver* s) {
     dev_free(s->M);
     dev_free(s->partial);
     dev_free(s->small);
+    dev_free(s->dring);
     if (s->hsmall) (void)hipHostFree(s->hsmall);
+    if (s->hring) (void)hipHostFree(s->hring);
     delete s;
 }
 
@@ -240,12 +256,12 @@ static int solver_ensure(iwfpm_plan_s* p, int m) {
     }
     size_t need_partial = (size_t)s->max_blocks * kMaxCols * kMaxCols * sizeof(double2);
     if (s->partial.bytes < need_partial && dev_alloc(s->partial, need_partial) != IWFPM_OK) return IWFPM_ERR_ALLOC;
-    size_t need_small = (size_t)4 * 96 * 96 * sizeof(double2);
+    size_t need_small = (size_t)2 * 96 * 96 * sizeof(double2);
     if (s->small.bytes < need_small && dev_alloc(s->small, need_small) != IWFPM_OK) return IWFPM_ERR_ALLOC;
-    if (!s->hsmall) {
-        if (hipHostMalloc((void**)&s->hsmall, need_small) != hipSuccess) return IWFPM_ERR_ALLOC;
-        s->hsmall_bytes = need_small;
-    }
+    size_t need_ring = (size_t)kRingSlots * kSlot * sizeof(double2);
+    if (s->dring.bytes < need_ring && dev_alloc(s->dring, need_ring) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+    if (!s->hsmall && hipHostMalloc((void**)&s->hsmall, need_small) != hipSuccess) return IWFPM_ERR_ALLOC;
+    if (!s->hring && hipHostMalloc((void**)&s->hring, need_ring) != hipSuccess) return IWFPM_ERR_ALLOC;
     return IWFPM_OK;
 }
 
@@ -291,6 +307,12 @@ struct Ctx {
         if ((x) != hipSuccess) return IWFPM_ERR_DEVICE; \
     } while (0)
 
+static int sync(Ctx& c) {
+    CHECK_HIP(hipStreamSynchronize(c.st));
+    c.s->ring_since_sync = 0;
+    return IWFPM_OK;
+}
+
 // C (p x q) = L^H R on the host, chunking both sides by kMaxCols
 static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<double2*>& R, std::vector<cd>& C) {
     const int p = (int)L.size(), q = (int)R.size();
@@ -305,7 +327,7 @@ static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<d
             for (int j = 0; j < qj; ++j) b.p[j] = R[j0 + j];
             CHECK_HIP(gram(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, dC, c.st));
             CHECK_HIP(hipMemcpyAsync(c.s->hsmall, dC, (size_t)pi * qj * sizeof(double2), hipMemcpyDeviceToHost, c.st));
-            CHECK_HIP(hipStreamSynchronize(c.st));
+            if (int rc = sync(c)) return rc;
             for (int j = 0; j < qj; ++j)
                 for (int i = 0; i < pi; ++i) {
                     double2 v = c.s->hsmall[(size_t)j * pi + i];
@@ -316,7 +338,7 @@ static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<d
     return IWFPM_OK;
 }
 
-// Y_j (+)= sum_i A_i C[i + j*ldc]  for the q outputs, rows of C offset by r0
+// Y_j = beta Y_j + sum_i A_i C[(r0 + i) + j*ldc] for the q outputs
 static int dev_lincomb(Ctx& c, const std::vector<double2*>& A, const std::vector<double2*>& Y, const std::vector<cd>& Cm,
                        int ldc, int r0, double beta) {
     const int p = (int)A.size(), q = (int)Y.size();
@@ -326,12 +348,15 @@ static int dev_lincomb(Ctx& c, const std::vector<double2*>& A, const std::vector
             for (auto y : Y) CHECK_HIP(hipMemsetAsync(y, 0, c.N * sizeof(double2), c.st));
         return IWFPM_OK;
     }
-    double2* dC = (double2*)c.s->small.ptr + 96 * 96;
-    for (int j0 = 0; j0 < q; j0 += 32) {
-        int qj = std::min(32, q - j0);
-        // pack C[r0 .. r0+p) x [j0 .. j0+qj) column-major p x qj
-        double2* h = c.s->hsmall + 96 * 96;
-        CHECK_HIP(hipStreamSynchronize(c.st));  // the host mirror is reused
+    for (int j0 = 0; j0 < q; j0 += 48) {
+        int qj = std::min(48, q - j0);
+        if (c.s->ring_since_sync >= kRingSlots - 1)
+            if (int rc = sync(c)) return rc;
+        int slot = c.s->ring_next;
+        c.s->ring_next = (slot + 1) % kRingSlots;
+        c.s->ring_since_sync++;
+        double2* h = c.s->hring + (size_t)slot * kSlot;
+        double2* dC = (double2*)c.s->dring.ptr + (size_t)slot * kSlot;
         for (int j = 0; j < qj; ++j)
             for (int i = 0; i < p; ++i) {
                 cd v = Cm[(size_t)(r0 + i) + (size_t)(j0 + j) * ldc];
@@ -346,27 +371,21 @@ static int dev_lincomb(Ctx& c, const std::vector<double2*>& A, const std::vector
     return IWFPM_OK;
 }
 
-static int col_norms(Ctx& c, const std::vector<double2*>& V, std::vector<double>& out) {
-    const int m = (int)V.size();
-    out.assign(m, 0.0);
-    double* dOut = (double*)((double2*)c.s->small.ptr + 2 * 96 * 96);
-    for (int j0 = 0; j0 < m; j0 += kMaxCols) {
-        int mj = std::min(kMaxCols, m - j0);
-        ColPtrs v{};
-        for (int j = 0; j < mj; ++j) v.p[j] = V[j0 + j];
-        CHECK_HIP(colnorm2(v, mj, c.N, (double*)c.s->partial.ptr, c.s->max_blocks, dOut, c.st));
-        double* h = (double*)(c.s->hsmall + 2 * 96 * 96);
-        CHECK_HIP(hipMemcpyAsync(h, dOut, mj * sizeof(double), hipMemcpyDeviceToHost, c.st));
-        CHECK_HIP(hipStreamSynchronize(c.st));
-        for (int j = 0; j < mj; ++j) out[j0 + j] = std::sqrt(std::max(0.0, h[j]));
-    }
-    return IWFPM_OK;
-}
-
 static std::vector<double2*> cols(Ctx& c, int b, int j0, int cnt) {
     std::vector<double2*> v(cnt);
     for (int j = 0; j < cnt; ++j) v[j] = c.col(b, j0 + j);
     return v;
+}
+
+static void hermitian_part(std::vector<cd>& A, int n) {
+    for (int j = 0; j < n; ++j) {
+        A[j + (size_t)j * n] = A[j + (size_t)j * n].real();
+        for (int i = 0; i < j; ++i) {
+            cd a = 0.5 * (A[i + (size_t)j * n] + std::conj(A[j + (size_t)i * n]));
+            A[i + (size_t)j * n] = a;
+            A[j + (size_t)i * n] = std::conj(a);
+        }
+    }
 }
 
 // Rayleigh-Ritz on the block X alone (orthonormal X, HX = H X): X <- X C, HX <- HX C
@@ -374,12 +393,7 @@ static int rr_block(Ctx& c, int m, std::vector<double>& theta) {
     std::vector<cd> G;
     int rc = host_gram(c, cols(c, B_X, 0, m), cols(c, B_HX, 0, m), G);
     if (rc) return rc;
-    for (int j = 0; j < m; ++j)
-        for (int i = 0; i < j; ++i) {
-            cd a = 0.5 * (G[i + j * m] + std::conj(G[j + i * m]));
-            G[i + j * m] = a;
-            G[j + i * m] = std::conj(a);
-        }
+    hermitian_part(G, m);
     std::vector<cd> C;
     jacobi_eigh(G, m, theta, C);
     if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
@@ -422,7 +436,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         if (!lp || !learned_ready(lp, p)) return IWFPM_ERR_WEIGHTS;
     }
 
-    // start block
+    // start block: orthonormalise, apply H, Rayleigh-Ritz
     if (x0) {
         CHECK_HIP(hipMemcpyAsync(c.col(B_X, 0), x0, (size_t)N * m * sizeof(double2), hipMemcpyDeviceToDevice, st));
     } else {
@@ -440,30 +454,32 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     std::vector<double> theta;
     if ((rc = rr_block(c, m, theta))) return rc;
 
-    int mp = 0;                        // columns of P / HP
+    // P holds mp orthonormal columns orthogonal to X (built in coefficient space)
+    int mp = 0;
     std::vector<double> eta(m, 1.0);
-    int it = 0, polished = 0, restarts = 0, fallback = 0;
+    int it = 0, polished = 0, fallback = 0;
     double best_eta = 1e300;
     int best_it = 0;
-    bool done = false;
     int status = IWFPM_OK;
+    const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
+    double* dNorm = (double*)((double2*)s->small.ptr + 96 * 96);
     for (;;) {
-        // residuals and convergence
+        // residuals R = HX - X theta and their norms
         {
-            std::vector<double2*> X = cols(c, B_X, 0, m), HX = cols(c, B_HX, 0, m), R = cols(c, B_T1, 0, m);
             ColPtrs hx{}, x{}, r{};
             Reals th{};
             for (int j = 0; j < m; ++j) {
-                hx.p[j] = HX[j];
-                x.p[j] = X[j];
-                r.p[j] = R[j];
+                hx.p[j] = c.col(B_HX, j);
+                x.p[j] = c.col(B_X, j);
+                r.p[j] = c.col(B_T1, j);
                 th.v[j] = theta[j];
             }
-            CHECK_HIP(residual(hx, x, r, th, m, N, st));
-            std::vector<double> rn;
-            if ((rc = col_norms(c, R, rn))) return rc;
+            CHECK_HIP(residual_norm(hx, x, r, th, m, N, (double*)s->partial.ptr, s->max_blocks, dNorm, st));
+            double* h = (double*)(s->hsmall + 96 * 96);
+            CHECK_HIP(hipMemcpyAsync(h, dNorm, m * sizeof(double), hipMemcpyDeviceToHost, st));
+            if ((rc = sync(c))) return rc;
             for (int j = 0; j < m; ++j) {
-                eta[j] = rn[j] / (hnorm + std::fabs(theta[j]));
+                eta[j] = std::sqrt(std::max(0.0, h[j])) / (hnorm + std::fabs(theta[j]));
                 if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
             }
         }
@@ -477,41 +493,28 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d\n", it,
                          prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp);
         if (conv == nev) {
-            if (prec == 0) {
-                done = true;
-                break;
-            }
-            // confirm with float64 applies: Rayleigh-Ritz of X with the float64 H
-            if (!can64) {
-                done = true;
-                break;
-            }
-            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
-            if ((rc = rr_block(c, m, theta))) return rc;
+            if (prec == 0 || !can64) break;
+            // confirm with float64 applies (Rayleigh-Ritz of X with the float64 H)
             prec = 0;
+            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
             if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
-            continue;  // recompute residuals with float64; iterate on if needed
+            if ((rc = rr_block(c, m, theta))) return rc;
+            continue;
         }
         if (it >= o.maxit) {
             status = IWFPM_ERR_NOCONV;
             break;
         }
-        // float32 stall detection -> continue with float64 applies: either the
-        // residuals reached the float32 convolution noise floor, or they stopped
-        // improving
-        const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
-        if (prec == 1 && o.polish && can64 && worst < floor32 && worst > o.tol) {
-            prec = 0;
-            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
-            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
-            if ((rc = rr_block(c, m, theta))) return rc;
-            best_eta = 1e300;
-            continue;
-        }
+        // float32 convolution: continue with float64 applies once the residuals
+        // reach its noise floor or stop improving
+        bool stalled = false;
         if (worst < 0.5 * best_eta) {
             best_eta = worst;
             best_it = it;
-        } else if (prec == 1 && o.polish && can64 && worst < 1e-5 && it - best_it >= 20) {
+        } else {
+            stalled = worst < 1e-5 && it - best_it >= 20;
+        }
+        if (prec == 1 && o.polish && can64 && (worst < floor32 || stalled)) {
             prec = 0;
             if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
             if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
@@ -522,7 +525,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         ++it;
         if (prec == 0 && p->opts.precision == 1) ++polished;
 
-        // active set and preconditioned residuals W = M R_A
+        // active set, W = M R_A
         std::vector<int> act;
         for (int j = 0; j < m; ++j)
             if (eta[j] > o.tol) act.push_back(j);
@@ -544,37 +547,15 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             }
             if (!used_learned) CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
         }
-        // Orthonormal trial basis [X, P, W] (each block orthonormal and
-        // orthogonal to the previous ones), so that the Rayleigh-Ritz Gram
-        // matrix of the basis stays close to the identity and float32 noise
-        // in H W is not amplified near convergence.
-        //   P_A <- P_A - X (X^H P_A), HP_A likewise, then SVQB  -> PN / HPN
-        //   W   <- W - X (X^H W) - PN (PN^H W), twice, then SVQB -> W
-        int mq = 0;
-        if (mp > 0) {
-            std::vector<double2*> Pa, HPa;
-            for (int a : act)
-                if (a < mp) {
-                    Pa.push_back(c.col(B_P, a));
-                    HPa.push_back(c.col(B_HP, a));
-                }
-            const int k = (int)Pa.size();
-            if (k > 0) {
-                std::vector<cd> G, T;
-                if ((rc = host_gram(c, cols(c, B_X, 0, m), Pa, G))) return rc;
-                for (auto& g : G) g = -g;
-                if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), Pa, G, m, 0, 1.0))) return rc;
-                if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), HPa, G, m, 0, 1.0))) return rc;
-                if ((rc = host_gram(c, Pa, Pa, G))) return rc;
-                mq = svqb(G, k, T);
-                if ((rc = dev_lincomb(c, Pa, cols(c, B_PN, 0, mq), T, k, 0, 0.0))) return rc;
-                if ((rc = dev_lincomb(c, HPa, cols(c, B_HPN, 0, mq), T, k, 0, 0.0))) return rc;
-            }
-        }
+        // P: built last iteration from the then-active Ritz vectors only,
+        // orthonormal and orthogonal to X
+        std::vector<double2*> Pa = cols(c, B_P, 0, mp), HPa = cols(c, B_HP, 0, mp);
+        const int mq = mp;
+        // W <- W - [X P_A] ([X P_A]^H W), twice; then SVQB
         int mw = 0;
         {
             std::vector<double2*> XP = cols(c, B_X, 0, m);
-            for (int j = 0; j < mq; ++j) XP.push_back(c.col(B_PN, j));
+            XP.insert(XP.end(), Pa.begin(), Pa.end());
             for (int pass = 0; pass < 2; ++pass) {
                 std::vector<cd> G;
                 if ((rc = host_gram(c, XP, cols(c, B_W, 0, ma), G))) return rc;
@@ -588,70 +569,97 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             std::swap(s->buf[B_W], s->buf[B_T1]);
         }
         if ((rc = apply_block(c, B_W, B_HW, mw, prec, stats))) return rc;
-        // Rayleigh-Ritz on span[X, W, P]
-        std::vector<cd> Cm;
-        std::vector<double> th;
-        int ns = 0;
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            int mqq = attempt == 0 ? mq : 0;
-            ns = m + mw + mqq;
-            std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m);
-            for (int j = 0; j < mw; ++j) {
-                S.push_back(c.col(B_W, j));
-                HS.push_back(c.col(B_HW, j));
-            }
-            for (int j = 0; j < mqq; ++j) {
-                S.push_back(c.col(B_PN, j));
-                HS.push_back(c.col(B_HPN, j));
-            }
-            std::vector<cd> A, B;
-            if ((rc = host_gram(c, S, HS, A))) return rc;
-            if ((rc = host_gram(c, S, S, B))) return rc;
-            for (int j = 0; j < ns; ++j)
-                for (int i = 0; i <= j; ++i) {
-                    cd a = 0.5 * (A[i + j * ns] + std::conj(A[j + i * ns]));
-                    A[i + j * ns] = a;
-                    A[j + i * ns] = std::conj(a);
-                    cd b = 0.5 * (B[i + j * ns] + std::conj(B[j + i * ns]));
-                    B[i + j * ns] = b;
-                    B[j + i * ns] = std::conj(b);
-                }
-            if (gen_eigh(A, B, ns, th, Cm)) {
-                mq = mqq;
-                break;
-            }
-            if (attempt == 1 || mq == 0) return IWFPM_ERR_NUMERIC;
-            ++restarts;
+        // Rayleigh-Ritz on the orthonormal basis S = [X W P_A]:
+        // A = S^H H S with X^H H X = diag(theta); only [X W P_A]^H [HW HP_A] is formed
+        const int ns = m + mw + mq;
+        std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m);
+        for (int j = 0; j < mw; ++j) {
+            S.push_back(c.col(B_W, j));
+            HS.push_back(c.col(B_HW, j));
         }
-        // updates: X <- S C, HX <- HS C, P <- [W P] C_WP, HP <- [HW HP] C_WP
+        S.insert(S.end(), Pa.begin(), Pa.end());
+        HS.insert(HS.end(), HPa.begin(), HPa.end());
+        std::vector<cd> A((size_t)ns * ns, 0.0);
         {
-            std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m), SWP, HSWP;
-            for (int j = 0; j < mw; ++j) {
-                S.push_back(c.col(B_W, j));
-                HS.push_back(c.col(B_HW, j));
-                SWP.push_back(c.col(B_W, j));
-                HSWP.push_back(c.col(B_HW, j));
+            std::vector<double2*> HR(HS.begin() + m, HS.end());
+            std::vector<cd> G;
+            if ((rc = host_gram(c, S, HR, G))) return rc;
+            const int nr = ns - m;
+            for (int j = 0; j < nr; ++j)
+                for (int i = 0; i < ns; ++i) {
+                    A[i + (size_t)(m + j) * ns] = G[i + (size_t)j * ns];
+                    if (i < m) A[(m + j) + (size_t)i * ns] = std::conj(G[i + (size_t)j * ns]);
+                }
+            for (int j = 0; j < m; ++j) A[j + (size_t)j * ns] = theta[j];
+            hermitian_part(A, ns);
+        }
+        std::vector<double> th;
+        std::vector<cd> Cfull;
+        jacobi_eigh(A, ns, th, Cfull);
+        // next P: the non-X part of the new Ritz vectors, orthogonalised against
+        // them and orthonormalised, all in the ns-dimensional coefficient space
+        std::vector<cd> Z((size_t)ns * m, 0.0);
+        for (int a = 0; a < ma; ++a)
+            for (int i = m; i < ns; ++i) Z[i + (size_t)a * ns] = Cfull[i + (size_t)act[a] * ns];
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<cd> G((size_t)m * m, 0.0);  // C_x^H Z
+            for (int j = 0; j < ma; ++j)
+                for (int i = 0; i < m; ++i) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < ns; ++k) acc += std::conj(Cfull[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                    G[i + (size_t)j * m] = acc;
+                }
+            for (int j = 0; j < ma; ++j)
+                for (int k = 0; k < ns; ++k) {
+                    cd acc = 0.0;
+                    for (int i = 0; i < m; ++i) acc += Cfull[k + (size_t)i * ns] * G[i + (size_t)j * m];
+                    Z[k + (size_t)j * ns] -= acc;
+                }
+        }
+        int mpn = 0;
+        std::vector<cd> U((size_t)ns * (2 * m), 0.0);  // [C_x | Z T]
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < ns; ++i) U[i + (size_t)j * ns] = Cfull[i + (size_t)j * ns];
+        if (ns > m && ma > 0) {
+            std::vector<cd> G((size_t)ma * ma, 0.0), T;
+            for (int j = 0; j < ma; ++j)
+                for (int i = 0; i < ma; ++i) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < ns; ++k) acc += std::conj(Z[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                    G[i + (size_t)j * ma] = acc;
+                }
+            double gmax = 0.0;
+            for (int j = 0; j < ma; ++j) gmax = std::max(gmax, G[j + (size_t)j * ma].real());
+            if (gmax > 1e-28) {
+                mpn = svqb(G, ma, T, 1e-12);
+                for (int j = 0; j < mpn; ++j)
+                    for (int i = 0; i < ns; ++i) {
+                        cd acc = 0.0;
+                        for (int k = 0; k < ma; ++k) acc += Z[i + (size_t)k * ns] * T[k + (size_t)j * ma];
+                        U[i + (size_t)(m + j) * ns] = acc;
+                    }
             }
-            for (int j = 0; j < mq; ++j) {
-                S.push_back(c.col(B_PN, j));
-                HS.push_back(c.col(B_HPN, j));
-                SWP.push_back(c.col(B_PN, j));
-                HSWP.push_back(c.col(B_HPN, j));
+        }
+        // [X_new | P_new] = S U,  [HX_new | HP_new] = HS U
+        {
+            std::vector<double2*> out = cols(c, B_XN, 0, m), hout = cols(c, B_HXN, 0, m);
+            for (int j = 0; j < mpn; ++j) {
+                out.push_back(c.col(B_PN, j));
+                hout.push_back(c.col(B_HPN, j));
             }
-            if ((rc = dev_lincomb(c, S, cols(c, B_XN, 0, m), Cm, ns, 0, 0.0))) return rc;
-            if ((rc = dev_lincomb(c, HS, cols(c, B_HXN, 0, m), Cm, ns, 0, 0.0))) return rc;
-            if ((rc = dev_lincomb(c, SWP, cols(c, B_P, 0, m), Cm, ns, m, 0.0))) return rc;
-            if ((rc = dev_lincomb(c, HSWP, cols(c, B_HP, 0, m), Cm, ns, m, 0.0))) return rc;
+            if ((rc = dev_lincomb(c, S, out, U, ns, 0, 0.0))) return rc;
+            if ((rc = dev_lincomb(c, HS, hout, U, ns, 0, 0.0))) return rc;
             std::swap(s->buf[B_X], s->buf[B_XN]);
             std::swap(s->buf[B_HX], s->buf[B_HXN]);
-            mp = m;
+            std::swap(s->buf[B_P], s->buf[B_PN]);
+            std::swap(s->buf[B_HP], s->buf[B_HPN]);
+            mp = mpn;
         }
         theta.assign(th.begin(), th.begin() + m);
     }
-    (void)done;
     if (stats) {
         stats->iterations = it;
-        stats->restarts = restarts;
+        stats->restarts = 0;
         stats->fallback = fallback;
         stats->polished = polished;
         int conv = 0;
