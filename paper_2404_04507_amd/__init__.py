@@ -60,7 +60,7 @@ class _Stats(ctypes.Structure):
 
 
 def library_path() -> str:
-    return os.path.join(_HERE, "libiwfpm.so")
+    return os.environ.get("IWFPM_LIBRARY") or os.path.join(_HERE, "libiwfpm.so")
 
 
 def load_library():

@@ -24,8 +24,12 @@
 // first forward axis are fused in registers.
 //
 // Every 1-D transform is one pencil per thread (fft_reg.hpp); LDS holds the
-// tile between axes.  The potential is either a sum of per-axis tables
-// (all modes on coordinate axes, the common case) or a full grid.
+// tile between axes.  Slab tiles pad their last (contiguous) axis to an odd
+// pitch so that the pencils along it, one per lane, hit distinct banks.  The
+// per-element index work of the gather / scatter and of the kinetic term is
+// hoisted into a per-row table (a row = one line along the last axis): within
+// a row the true label along the last axis only wraps once, so each element
+// costs a compare and a few fused multiply-adds.
 
 #pragma once
 
@@ -81,7 +85,7 @@ __device__ __forceinline__ void pencil_conv(cplx<R>* base, int es, const VPencil
 template <int SIGN, typename R, int MAXS>
 __device__ __forceinline__ void dispatch_fft(int S, cplx<R>* base, int es) {
     switch (S) {
-#define IWFPM_CASE(s) \
+#define IWFPM_CASE(s)                                              \
     case s:                                                       \
         if constexpr (s <= MAXS) pencil_fft<s, SIGN, R>(base, es); \
         break;
@@ -94,8 +98,8 @@ __device__ __forceinline__ void dispatch_fft(int S, cplx<R>* base, int es) {
 template <typename R, int MAXS>
 __device__ __forceinline__ void dispatch_conv(int S, cplx<R>* base, int es, const VPencil<R>& vp) {
     switch (S) {
-#define IWFPM_CASE(s) \
-    case s:                                                \
+#define IWFPM_CASE(s)                                             \
+    case s:                                                      \
         if constexpr (s <= MAXS) pencil_conv<s, R>(base, es, vp); \
         break;
         IWFPM_EXTENTS(IWFPM_CASE)
@@ -104,13 +108,22 @@ __device__ __forceinline__ void dispatch_conv(int S, cplx<R>* base, int es, cons
     }
 }
 
-// all pencils of one axis of an LDS tile: pencil p starts at
-// (p / es) * es * S + p % es and steps by es
+// Pencil p of an axis with extent S and logical element stride es starts at
+// the logical offset (p / es) * es * S + p % es.  A logical offset L maps to
+// (L / sl) * sp + L % sl in a tile whose rows of sl elements are padded to a
+// pitch sp; a pencil either stays inside one row (es < sl) or steps by whole
+// rows (es a multiple of sl).
+__device__ __forceinline__ int phys(int L, RowGeom rg) {
+    int r = L / rg.sl;
+    return r * rg.sp + (L - r * rg.sl);
+}
+
 template <int SIGN, typename R, int MAXS>
-__device__ __forceinline__ void run_axis(cplx<R>* lds, int S, int npencil, int es) {
+__device__ __forceinline__ void run_axis(cplx<R>* lds, int S, int npencil, int es, RowGeom rg) {
+    const int pes = es < rg.sl ? es : (es / rg.sl) * rg.sp;
     for (int p = threadIdx.x; p < npencil; p += blockDim.x) {
         int hi = p / es, lo = p - hi * es;
-        dispatch_fft<SIGN, R, MAXS>(S, lds + hi * es * S + lo, es);
+        dispatch_fft<SIGN, R, MAXS>(S, lds + phys(hi * es * S + lo, rg), pes);
     }
 }
 
@@ -123,59 +136,90 @@ __device__ __forceinline__ int pmod(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
+// Per-row data of the kinetic term and of the window order, for the row whose
+// first element sits at grid position r0 (a multiple of the last extent):
+//   B_j    = 2 pi (P_II k_II)_j + sum_{i < d-1} (2 pi P_I)_{j i} k_i     (j < d)
+//   alast  = lower window end of the last k_I axis in this slice
+//   amod   = alast mod ext_last
+//   vrow   = vector position of the row's first element in window order
+//            (minus the rotation of the last axis), or r0 in grid order
+// With them, the element in column c of the row has the last true label
+// k_last = alast + ((c - amod) mod ext_last) (eq:inverse3 in floor form) and
+// Lambda = 1/2 sum_j (B_j + (2 pi P_I)_{j, d-1} k_last)^2.
+struct RowTable {
+    double* B;   // rows x d
+    int* alast;
+    int* amod;
+    int* vrow;
+};
+
+__device__ __forceinline__ RowTable row_table_at(unsigned char* base, int rows, int d) {
+    RowTable t;
+    t.B = reinterpret_cast<double*>(base);
+    t.alast = reinterpret_cast<int*>(t.B + (size_t)rows * d);
+    t.amod = t.alast + rows;
+    t.vrow = t.amod + rows;
+    return t;
+}
+
+__device__ __forceinline__ void row_entry(const DevGeom& g, const DevTabs& t, int r0, RowTable tab, int row) {
+    const int d = g.d, n = g.n;
+    const int s = r0 / g.nkI;
+    int q = r0 - s * g.nkI;
+    const int* a = t.slice_a + s * d;
+    const double* gg = t.slice_g + s * d;
+    double kI[kMaxAxes];
+    int vrow = s * g.nkI;
+    q /= g.ext[n - 1];  // the row starts at column 0 of the last axis
+    for (int j = d - 2; j >= 0; --j) {
+        int ax = n - d + j;
+        int E = g.ext[ax];
+        int ks = q % E;
+        q /= E;
+        int pj = pmod(ks - a[j], E);
+        kI[j] = (double)(a[j] + pj);
+        vrow += (g.order ? pj : ks) * g.stride[ax];
+    }
+    for (int j = 0; j < d; ++j) {
+        double b = gg[j];
+        for (int i = 0; i < d - 1; ++i) b += g.P1[j * d + i] * kI[i];
+        tab.B[row * d + j] = b;
+    }
+    const int El = g.ext[n - 1];
+    tab.alast[row] = a[d - 1];
+    tab.amod[row] = pmod(a[d - 1], El);
+    tab.vrow[row] = vrow;
+}
+
+// kinetic term and vector position of column c of a row (see RowTable)
+__device__ __forceinline__ double row_kinetic(const DevGeom& g, const RowTable& tab, int row, int c, int* vpos) {
+    const int d = g.d;
+    const int El = g.ext[g.n - 1];
+    int pl = c - tab.amod[row];
+    pl += pl < 0 ? El : 0;
+    const double kl = (double)(tab.alast[row] + pl);
+    double lam = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double v = tab.B[row * d + j] + g.P1[j * d + d - 1] * kl;
+        lam += v * v;
+    }
+    *vpos = tab.vrow[row] + (g.order ? pl : c);
+    return 0.5 * lam;
+}
+
 // window-order position r (within one vector) -> grid-order position
 __device__ __forceinline__ int vec_to_grid(const DevGeom& g, const int* __restrict__ slice_a, int r) {
-    int s = (int)(r / g.nkI);
-    int q = r - s * (int)g.nkI;
-    int out = s * (int)g.nkI;
+    int s = r / g.nkI;
+    int q = r - s * g.nkI;
+    int out = s * g.nkI;
     for (int j = g.d - 1; j >= 0; --j) {
         int ax = g.n - g.d + j;
         int E = g.ext[ax];
         int pj = q % E;
         q /= E;
-        out += pmod(pj + slice_a[s * g.d + j], E) * (int)g.stride[ax];
+        out += pmod(pj + slice_a[s * g.d + j], E) * g.stride[ax];
     }
     return out;
-}
-
-// grid-order position -> window-order position
-__device__ __forceinline__ int grid_to_vec(const DevGeom& g, const int* __restrict__ slice_a, int r) {
-    int s = (int)(r / g.nkI);
-    int q = r - s * (int)g.nkI;
-    int out = s * (int)g.nkI;
-    for (int j = g.d - 1; j >= 0; --j) {
-        int ax = g.n - g.d + j;
-        int E = g.ext[ax];
-        int kj = q % E;
-        q /= E;
-        out += pmod(kj - slice_a[s * g.d + j], E) * (int)g.stride[ax];
-    }
-    return out;
-}
-
-// Lambda at grid position r: k_II from the slice (eq:inverse2), k_I = a +
-// ((k* - a) mod 2K) (eq:inverse3 written with the slice's lower window end a),
-// then 1/2 |2 pi P_II k_II + 2 pi P_I k_I|^2 in float64.
-__device__ __forceinline__ double kinetic_at(const DevGeom& g, const int* __restrict__ slice_a,
-                                             const double* __restrict__ slice_g, int r) {
-    int s = (int)(r / g.nkI);
-    int q = r - s * (int)g.nkI;
-    double kI[kMaxAxes];
-    for (int j = g.d - 1; j >= 0; --j) {
-        int ax = g.n - g.d + j;
-        int E = g.ext[ax];
-        int ks = q % E;
-        q /= E;
-        int a = slice_a[s * g.d + j];
-        kI[j] = (double)(a + pmod(ks - a, E));
-    }
-    double tot = 0.0;
-    for (int j = 0; j < g.d; ++j) {
-        double v = slice_g[s * g.d + j];
-        for (int i = 0; i < g.d; ++i) v += g.P1[j * g.d + i] * kI[i];
-        tot += v * v;
-    }
-    return 0.5 * tot;
 }
 
 template <typename R>
@@ -197,7 +241,7 @@ __device__ __forceinline__ R vsum_except(const DevGeom& g, const R* __restrict__
     R acc = R(0);
     for (int ax = 0; ax < g.n; ++ax) {
         if (ax == skip) continue;
-        int l = (int)((r / g.stride[ax]) % g.ext[ax]);
+        int l = (r / g.stride[ax]) % g.ext[ax];
         acc += vtab[g.voff[ax] + l];
     }
     return acc;
@@ -207,7 +251,7 @@ template <typename R>
 __device__ __forceinline__ VPencil<R> make_vpencil(const DevGeom& g, const DevTabs& t, int ax, int gbase) {
     VPencil<R> vp;
     vp.gbase = gbase;
-    vp.gstep = (int)g.stride[ax];
+    vp.gstep = g.stride[ax];
     if (g.vmode == 1) {
         vp.vgrid = vgrid_of<R>(t);
         vp.vaxis = nullptr;
@@ -225,11 +269,147 @@ __device__ __forceinline__ int remap_block(int bid, int nblocks, int on) {
     // Workgroups are dealt round-robin over the 8 XCDs; give XCD x a
     // contiguous run of tiles so neighbouring tiles share its L2.
     if (!on || nblocks < 16) return bid;
-    int per = nblocks / 8, rem = nblocks - per * 8;
+    int per = nblocks / 8;
     int xcd = bid & 7, local = bid >> 3;
     if (local < per) return xcd * per + local;
-    (void)rem;
     return bid;  // the ragged tail keeps its order
+}
+
+// independent global loads each thread keeps in flight in the tile copies
+constexpr int kBatch = 8;
+
+// element iterator over a tile of `rows` rows of length sl: thread-strided,
+// with row / column updated incrementally (no division per element)
+struct RowIter {
+    int e, row, col, drow, dcol, sl;
+    __device__ __forceinline__ RowIter(int start, int step, int sl_) : e(start), sl(sl_) {
+        row = start / sl_;
+        col = start - row * sl_;
+        drow = step / sl_;
+        dcol = step - drow * sl_;
+    }
+    __device__ __forceinline__ void next(int step) {
+        e += step;
+        row += drow;
+        col += dcol;
+        if (col >= sl) {
+            col -= sl;
+            ++row;
+        }
+    }
+};
+
+// load `count` vector-order elements starting at vector position v0 into a
+// grid-order LDS tile (padded rows); in window order the rows are gathered
+template <typename R>
+__device__ __forceinline__ void load_gather(const DevGeom& g, const DevTabs& t, const double2* __restrict__ x,
+                                            int v0, int count, cplx<R>* tile, RowGeom rg, int* rowmap) {
+    const int nt = blockDim.x;
+    if (g.order) {
+        // rowmap[rv] = (grid row within the tile) * sp, and the rotation of the last axis
+        const int rows = count / rg.sl;
+        for (int rv = threadIdx.x; rv < rows; rv += nt) {
+            int gp = vec_to_grid(g, t.slice_a, v0 + rv * rg.sl);  // element 0 of this vector row
+            int grow = (gp - v0) / rg.sl;
+            rowmap[2 * rv] = grow * rg.sp;
+            rowmap[2 * rv + 1] = gp - v0 - grow * rg.sl;  // its column = a_last mod sl
+        }
+        __syncthreads();
+        for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count;) {
+            double2 v[kBatch];
+            RowIter j = it;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                v[u] = j.e < count ? x[v0 + j.e] : make_double2(0.0, 0.0);
+                j.next(nt);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count) {
+                    int c = it.col + rowmap[2 * it.row + 1];
+                    c -= c >= rg.sl ? rg.sl : 0;
+                    tile[rowmap[2 * it.row] + c] = cplx<R>{R(v[u].x), R(v[u].y)};
+                }
+                it.next(nt);
+            }
+        }
+    } else {
+        for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count;) {
+            double2 v[kBatch];
+            RowIter j = it;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                v[u] = j.e < count ? x[v0 + j.e] : make_double2(0.0, 0.0);
+                j.next(nt);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count) tile[it.row * rg.sp + it.col] = cplx<R>{R(v[u].x), R(v[u].y)};
+                it.next(nt);
+            }
+        }
+    }
+}
+
+// copy `count` grid-order elements between global memory and a padded tile,
+// kBatch independent loads in flight per thread
+template <typename R>
+__device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ w, int count, cplx<R>* tile, RowGeom rg) {
+    const int nt = blockDim.x;
+    for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count;) {
+        cplx<R> v[kBatch];
+        RowIter j = it;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            v[u] = j.e < count ? w[j.e] : cplx<R>{R(0), R(0)};
+            j.next(nt);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
+            it.next(nt);
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void store_tile(cplx<R>* __restrict__ w, int count, const cplx<R>* tile, RowGeom rg) {
+    const int nt = blockDim.x;
+    for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count; it.next(nt)) w[it.e] = tile[it.row * rg.sp + it.col];
+}
+
+// kinetic term + scatter for `count` grid-order elements starting at grid
+// position r0 of one vector: y[v] = Lambda x[v] + tile
+template <typename R>
+__device__ __forceinline__ void kinetic_scatter(const DevGeom& g, const DevTabs& t, const double2* __restrict__ x,
+                                                double2* __restrict__ y, int r0, int count, const cplx<R>* tile,
+                                                RowGeom rg, RowTable tab) {
+    const int nt = blockDim.x;
+    const int rows = count / rg.sl;
+    for (int r = threadIdx.x; r < rows; r += nt) row_entry(g, t, r0 + r * rg.sl, tab, r);
+    __syncthreads();
+    for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count;) {
+        int vpos[kBatch];
+        double lam[kBatch];
+        double2 xv[kBatch];
+        RowIter j = it;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (j.e < count) {
+                lam[u] = row_kinetic(g, tab, j.row, j.col, &vpos[u]);
+                xv[u] = x[vpos[u]];
+            }
+            j.next(nt);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (it.e < count) {
+                cplx<R> c = tile[it.row * rg.sp + it.col];
+                y[vpos[u]] = make_double2(lam[u] * xv[u].x + (double)c.x, lam[u] * xv[u].y + (double)c.y);
+            }
+            it.next(nt);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -237,175 +417,164 @@ __device__ __forceinline__ int remap_block(int bid, int nblocks, int on) {
 // ---------------------------------------------------------------------------
 
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, const double2* __restrict__ psi,
+__global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, RowGeom rg, const double2* __restrict__ psi,
                                                double2* __restrict__ hpsi) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
-    const int N = (int)g.N;
-    const long long off = (long long)blockIdx.x * g.N;
+    const int N = g.N;
+    const int rows = N / rg.sl;
+    unsigned char* extra = smem + (size_t)rows * rg.sp * sizeof(cplx<R>);
+    const long long off = (long long)blockIdx.x * N;
     const double2* __restrict__ x = psi + off;
     double2* __restrict__ y = hpsi + off;
 
-    for (int e = threadIdx.x; e < N; e += blockDim.x) {
-        int gp = g.order ? vec_to_grid(g, t.slice_a, e) : e;
-        double2 v = x[e];
-        tile[gp] = cplx<R>{R(v.x), R(v.y)};
-    }
+    load_gather<R>(g, t, x, 0, N, tile, rg, reinterpret_cast<int*>(extra));
     __syncthreads();
     for (int ax = 0; ax < g.n - 1; ++ax) {
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], (int)g.stride[ax]);
+        run_axis<+1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
     {
-        const int ax = g.n - 1;
-        const int S = g.ext[ax], es = (int)g.stride[ax], np = N / S;
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            int hi = p / es, lo = p - hi * es;
-            int base = hi * es * S + lo;
-            VPencil<R> vp = make_vpencil<R>(g, t, ax, base);
-            dispatch_conv<R, MAXS>(S, tile + base, es, vp);
+        // last axis (contiguous, es = 1): inverse, potential, forward
+        const int S = rg.sl;
+        for (int p = threadIdx.x; p < rows; p += blockDim.x) {
+            VPencil<R> vp = make_vpencil<R>(g, t, g.n - 1, p * S);
+            dispatch_conv<R, MAXS>(S, tile + p * rg.sp, 1, vp);
         }
         __syncthreads();
     }
     for (int ax = g.n - 2; ax >= 0; --ax) {
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], (int)g.stride[ax]);
+        run_axis<-1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < N; e += blockDim.x) {
-        int vp = g.order ? grid_to_vec(g, t.slice_a, e) : e;
-        double lam = kinetic_at(g, t.slice_a, t.slice_g, e);
-        double2 xv = x[vp];
-        cplx<R> c = tile[e];
-        y[vp] = make_double2(lam * xv.x + (double)c.x, lam * xv.y + (double)c.y);
-    }
+    kinetic_scatter<R>(g, t, x, y, 0, N, tile, rg, row_table_at(extra, rows, g.d));
 }
 
 // ---------------------------------------------------------------------------
-// three-pass schedule
+// three-pass schedule.  Passes 1 and 3 give each workgroup up to
+// slabs_per_wg consecutive slabs of one vector.
 // ---------------------------------------------------------------------------
 
 // pass 1: gather (window order) + inverse DFT along the trailing axes
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_pass1(DevGeom g, DevTabs t, PassDesc pd, const double2* __restrict__ psi,
-                                               cplx<R>* __restrict__ ws, long long nslab) {
+__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
+                                               const double2* __restrict__ psi, cplx<R>* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
-    const int G = pd.slabs_per_wg;
-    const int sin_ = (int)pd.s_in;
+    const int G = pd.slabs_per_wg, sin_ = pd.s_in;
+    const int bpv = (pd.s_out + G - 1) / G;
     const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
-    const long long slab0 = (long long)bid * G;
-    const int nsl = (int)min((long long)G, nslab - slab0);
-    const int nload = nsl * sin_;
-    const long long gbase = slab0 * sin_;
+    const int vec = bid / bpv;
+    const int slab0 = (bid - vec * bpv) * G;
+    const int nsl = min(G, pd.s_out - slab0);
+    const int count = nsl * sin_;
+    const int r0 = slab0 * sin_;
+    const long long off = (long long)vec * g.N;
+    unsigned char* extra = smem + (size_t)(G * sin_ / rg.sl) * rg.sp * sizeof(cplx<R>);
 
-    for (int e = threadIdx.x; e < G * sin_; e += blockDim.x) {
-        if (e < nload) {
-            long long gi = gbase + e;
-            double2 v = psi[gi];
-            int lo = e;
-            if (g.order) {
-                long long vec = gi / g.N;
-                int r = (int)(gi - vec * g.N);
-                lo = (int)(vec * g.N + vec_to_grid(g, t.slice_a, r) - gbase);
-            }
-            tile[lo] = cplx<R>{R(v.x), R(v.y)};
-        } else {
-            tile[e] = cplx<R>{R(0), R(0)};
-        }
-    }
+    load_gather<R>(g, t, psi + off, r0, count, tile, rg, reinterpret_cast<int*>(extra));
     __syncthreads();
     for (int ax = pd.split; ax < g.n; ++ax) {
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], G * sin_ / g.ext[ax], (int)g.stride[ax]);
+        run_axis<+1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < nload; e += blockDim.x) ws[gbase + e] = tile[e];
+    store_tile<R>(ws + off + r0, count, tile, rg);
 }
 
 // pass 2: inverse DFT along the leading axes, x V, forward DFT, on a tile of
-// `tile` consecutive columns of one vector
+// `tile` consecutive columns of one vector.  The LDS tile is [outer][column];
+// its rows (one line of the last leading axis times the columns) are padded
+// by `tile` entries, which spreads the lanes of the pencils along that axis
+// over distinct banks.
 template <typename R, int MAXS>
 __global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
-    const int T = pd.tile;
-    const int sin_ = (int)pd.s_in, sout = (int)pd.s_out;
+    const int T = pd.tile, lgT = __ffs(T) - 1;
+    const int sin_ = pd.s_in, sout = pd.s_out;
     const int ntile = (sin_ + T - 1) / T;
     const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
     const int vec = bid / ntile;
     const int c0 = (bid - vec * ntile) * T;
     const int tw = min(T, sin_ - c0);
-    cplx<R>* __restrict__ w = ws + (long long)vec * g.N;
+    cplx<R>* __restrict__ w = ws + (long long)vec * g.N + c0;
+    const int split = pd.split;
+    const int El = g.ext[split - 1];
+    const RowGeom rg{El << lgT, (El + 1) << lgT};
+    const int count = sout << lgT;
 
-    for (int e = threadIdx.x; e < sout * T; e += blockDim.x) {
-        int o = e / T, tt = e - o * T;
-        tile[e] = tt < tw ? w[(long long)o * sin_ + c0 + tt] : cplx<R>{R(0), R(0)};
+    // logical element e = row * (El T) + col: outer index o = row El + col / T, column col % T
+    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
+        cplx<R> v[kBatch];
+        RowIter j = it;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            int o = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
+            v[u] = (j.e < count && tt < tw) ? w[o * sin_ + tt] : cplx<R>{R(0), R(0)};
+            j.next(blockDim.x);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
+            it.next(blockDim.x);
+        }
     }
     __syncthreads();
-    const int split = pd.split;
     for (int ax = 0; ax < split - 1; ++ax) {
-        int es = (int)(g.stride[ax] / sin_) * T;
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], sout * T / g.ext[ax], es);
+        int es = (g.stride[ax] / sin_) << lgT;
+        run_axis<+1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
         __syncthreads();
     }
     {
         const int ax = split - 1;
-        const int S = g.ext[ax];
-        const int es = (int)(g.stride[ax] / sin_) * T;
-        const int np = sout * T / S;
+        const int S = El;
+        const int es = T;
+        const int np = count / S;
         for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            int hi = p / es, lo = p - hi * es;
-            int base = hi * es * S + lo;
-            int tt = base % T;
-            int ob = base / T;
-            int gb = ob * sin_ + c0 + min(tt, tw - 1);
+            int hi = p >> lgT, lo = p & (T - 1);  // hi: row, lo: column
+            int gb = hi * El * sin_ + c0 + min(lo, tw - 1);
             VPencil<R> vp = make_vpencil<R>(g, t, ax, gb);
-            dispatch_conv<R, MAXS>(S, tile + base, es, vp);
+            dispatch_conv<R, MAXS>(S, tile + hi * rg.sp + lo, es, vp);
         }
         __syncthreads();
     }
     for (int ax = split - 2; ax >= 0; --ax) {
-        int es = (int)(g.stride[ax] / sin_) * T;
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], sout * T / g.ext[ax], es);
+        int es = (g.stride[ax] / sin_) << lgT;
+        run_axis<-1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < sout * T; e += blockDim.x) {
-        int o = e / T, tt = e - o * T;
-        if (tt < tw) w[(long long)o * sin_ + c0 + tt] = tile[e];
+    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
+        int o = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
+        if (tt < tw) w[o * sin_ + tt] = tile[it.row * rg.sp + it.col];
     }
 }
 
 // pass 3: forward DFT along the trailing axes + kinetic term + scatter
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_pass3(DevGeom g, DevTabs t, PassDesc pd, const double2* __restrict__ psi,
-                                               const cplx<R>* __restrict__ ws, double2* __restrict__ hpsi,
-                                               long long nslab) {
+__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass3(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
+                                               const double2* __restrict__ psi, const cplx<R>* __restrict__ ws,
+                                               double2* __restrict__ hpsi) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
-    const int G = pd.slabs_per_wg;
-    const int sin_ = (int)pd.s_in;
+    const int G = pd.slabs_per_wg, sin_ = pd.s_in;
+    const int bpv = (pd.s_out + G - 1) / G;
     const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
-    const long long slab0 = (long long)bid * G;
-    const int nsl = (int)min((long long)G, nslab - slab0);
-    const int nload = nsl * sin_;
-    const long long gbase = slab0 * sin_;
+    const int vec = bid / bpv;
+    const int slab0 = (bid - vec * bpv) * G;
+    const int nsl = min(G, pd.s_out - slab0);
+    const int count = nsl * sin_;
+    const int r0 = slab0 * sin_;
+    const long long off = (long long)vec * g.N;
+    unsigned char* extra = smem + (size_t)(G * sin_ / rg.sl) * rg.sp * sizeof(cplx<R>);
 
-    for (int e = threadIdx.x; e < G * sin_; e += blockDim.x)
-        tile[e] = e < nload ? ws[gbase + e] : cplx<R>{R(0), R(0)};
+    load_tile<R>(ws + off + r0, count, tile, rg);
     __syncthreads();
     for (int ax = g.n - 1; ax >= pd.split; --ax) {
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], G * sin_ / g.ext[ax], (int)g.stride[ax]);
+        run_axis<-1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < nload; e += blockDim.x) {
-        long long gi = gbase + e;
-        long long vec = gi / g.N;
-        int r = (int)(gi - vec * g.N);
-        long long vi = g.order ? vec * g.N + grid_to_vec(g, t.slice_a, r) : gi;
-        double lam = kinetic_at(g, t.slice_a, t.slice_g, r);
-        double2 xv = psi[vi];
-        cplx<R> c = tile[e];
-        hpsi[vi] = make_double2(lam * xv.x + (double)c.x, lam * xv.y + (double)c.y);
-    }
+    kinetic_scatter<R>(g, t, psi + off, hpsi + off, r0, count, tile, rg,
+                       row_table_at(extra, G * sin_ / rg.sl, g.d));
 }
 
 }  // namespace iwfpm

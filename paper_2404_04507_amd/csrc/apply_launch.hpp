@@ -9,6 +9,28 @@
 
 namespace iwfpm {
 
+// padded row geometry of slab tiles: last extent sl, odd pitch sp
+inline RowGeom row_geom(const DevGeom& g) {
+    int sl = g.ext[g.n - 1];
+    return RowGeom{sl, sl + ((sl & 1) ? 0 : 1)};
+}
+// dynamic LDS of the fused kernel and of passes 1/3 (tile + row table)
+inline size_t lds_fused(const DevGeom& g, size_t esz) {
+    RowGeom rg = row_geom(g);
+    int rows = g.N / rg.sl;
+    return (size_t)rows * rg.sp * esz + row_table_bytes(rows, g.d);
+}
+inline size_t lds_slabs(const DevGeom& g, const PassDesc& pd, size_t esz) {
+    RowGeom rg = row_geom(g);
+    int rows = pd.slabs_per_wg * pd.s_in / rg.sl;
+    return (size_t)rows * rg.sp * esz + row_table_bytes(rows, g.d);
+}
+// pass 2 tile: rows of (last leading extent) x tile columns, padded by `tile`
+inline size_t lds_columns(const DevGeom& g, const PassDesc& pd, size_t esz) {
+    int El = g.ext[pd.split - 1];
+    return (size_t)(pd.s_out / El) * (El + 1) * pd.tile * esz;
+}
+
 template <typename R, int MAXS>
 hipError_t launch_fused(const DevGeom& g, const DevTabs& t, int threads, const void* psi, void* hpsi, int nvec,
                         hipStream_t st);

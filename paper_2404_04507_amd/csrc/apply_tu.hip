@@ -24,8 +24,8 @@ constexpr int M = IWFPM_TU_MAXS;
 template <>
 hipError_t launch_fused<R, M>(const DevGeom& g, const DevTabs& t, int threads, const void* psi, void* hpsi, int nvec,
                            hipStream_t st) {
-    size_t lds = (size_t)g.N * sizeof(cplx<R>);
-    k_fused<R, M><<<dim3(nvec), dim3(threads), lds, st>>>(g, t, reinterpret_cast<const double2*>(psi),
+    size_t lds = lds_fused(g, sizeof(cplx<R>));
+    k_fused<R, M><<<dim3(nvec), dim3(threads), lds, st>>>(g, t, row_geom(g), reinterpret_cast<const double2*>(psi),
                                                            reinterpret_cast<double2*>(hpsi));
     return hipGetLastError();
 }
@@ -37,11 +37,10 @@ hipError_t prepare_fused<R, M>(int lds_bytes) {
 template <>
 hipError_t launch_pass1<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, void* ws,
                            int nvec, hipStream_t st) {
-    long long nslab = (long long)nvec * pd.s_out;
-    int nb = (int)((nslab + pd.slabs_per_wg - 1) / pd.slabs_per_wg);
-    size_t lds = (size_t)pd.slabs_per_wg * pd.s_in * sizeof(cplx<R>);
+    int nb = ((pd.s_out + pd.slabs_per_wg - 1) / pd.slabs_per_wg) * nvec;
+    size_t lds = lds_slabs(g, pd, sizeof(cplx<R>));
     k_pass1<R, M><<<dim3(nb), dim3(pd.threads_inner), lds, st>>>(
-        g, t, pd, reinterpret_cast<const double2*>(psi), reinterpret_cast<cplx<R>*>(ws), nslab);
+        g, t, pd, row_geom(g), reinterpret_cast<const double2*>(psi), reinterpret_cast<cplx<R>*>(ws));
     return hipGetLastError();
 }
 template <>
@@ -52,8 +51,8 @@ hipError_t prepare_pass1<R, M>(int lds_bytes) {
 template <>
 hipError_t launch_pass2<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, void* ws, int nvec,
                            hipStream_t st) {
-    int ntile = (int)((pd.s_in + pd.tile - 1) / pd.tile);
-    size_t lds = (size_t)pd.s_out * pd.tile * sizeof(cplx<R>);
+    int ntile = (pd.s_in + pd.tile - 1) / pd.tile;
+    size_t lds = lds_columns(g, pd, sizeof(cplx<R>));
     k_pass2<R, M><<<dim3(ntile * nvec), dim3(pd.threads_outer), lds, st>>>(g, t, pd,
                                                                             reinterpret_cast<cplx<R>*>(ws));
     return hipGetLastError();
@@ -66,12 +65,11 @@ hipError_t prepare_pass2<R, M>(int lds_bytes) {
 template <>
 hipError_t launch_pass3<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, const void* ws,
                            void* hpsi, int nvec, hipStream_t st) {
-    long long nslab = (long long)nvec * pd.s_out;
-    int nb = (int)((nslab + pd.slabs_per_wg - 1) / pd.slabs_per_wg);
-    size_t lds = (size_t)pd.slabs_per_wg * pd.s_in * sizeof(cplx<R>);
+    int nb = ((pd.s_out + pd.slabs_per_wg - 1) / pd.slabs_per_wg) * nvec;
+    size_t lds = lds_slabs(g, pd, sizeof(cplx<R>));
     k_pass3<R, M><<<dim3(nb), dim3(pd.threads_inner), lds, st>>>(
-        g, t, pd, reinterpret_cast<const double2*>(psi), reinterpret_cast<const cplx<R>*>(ws),
-        reinterpret_cast<double2*>(hpsi), nslab);
+        g, t, pd, row_geom(g), reinterpret_cast<const double2*>(psi), reinterpret_cast<const cplx<R>*>(ws),
+        reinterpret_cast<double2*>(hpsi));
     return hipGetLastError();
 }
 template <>

@@ -14,9 +14,9 @@ struct DevGeom {
     int order;                      // 0 grid order, 1 window order
     int vmode;                      // 0 per-axis potential tables, 1 potential grid
     int ext[kMaxAxes];              // extents 2L..., 2K...
-    long long stride[kMaxAxes];     // row-major element strides
-    long long N;                    // grid points per vector
-    long long nkI;                  // points per k_I slice (product of the d fastest extents)
+    int stride[kMaxAxes];           // row-major element strides
+    int N;                          // grid points per vector (< 2^31)
+    int nkI;                        // points per k_I slice (product of the d fastest extents)
     int voff[kMaxAxes];             // offset of axis ax's potential table
     double P1[kMaxAxes * kMaxAxes]; // 2 pi P_I, d x d row-major
 };
@@ -34,13 +34,21 @@ struct DevTabs {
 // Three-pass schedule (see apply_kernels.hip).
 struct PassDesc {
     int split;          // number of leading axes handled by the middle pass
-    long long s_in;     // product of the trailing n - split extents (slab size)
-    long long s_out;    // product of the leading split extents
+    int s_in;           // product of the trailing n - split extents (slab size)
+    int s_out;          // product of the leading split extents
     int slabs_per_wg;   // passes 1 and 3: slabs per workgroup
-    int tile;           // pass 2: columns per workgroup
+    int tile;           // pass 2: columns per workgroup (a power of two)
     int threads_inner;  // block size of passes 1 and 3
     int threads_outer;  // block size of pass 2
     int xcd_remap;      // remap workgroup ids so that one XCD walks adjacent tiles
 };
+
+// LDS layout of a tile whose last axis (extent sl) is padded to an odd pitch sp
+struct RowGeom {
+    int sl, sp;
+};
+
+// bytes of the per-row table (kinetic and window data) for `rows` rows, d k_I axes
+inline int row_table_bytes(int rows, int d) { return rows * (8 * d + 12); }
 
 }  // namespace iwfpm

@@ -310,6 +310,8 @@ static int build_potential(iwfpm_plan_s* p, int n_modes, const int32_t* modes, c
 static const size_t kLdsDefault = 64 * 1024;
 static const size_t kLdsMax = 160 * 1024;
 
+static int round64(int x) { return ((x + 63) / 64) * 64; }
+
 static int choose_schedule(iwfpm_plan_s* p, int prec) {
     Schedule& sc = p->sched[prec];
     const DevGeom& g = p->geom;
@@ -318,12 +320,15 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
     int maxall = 0;
     for (int ax = 0; ax < n; ++ax) maxall = std::max(maxall, g.ext[ax]);
     sc.maxs_fused = extent_class(maxall);
-    sc.threads_fused = 256;
+    const size_t lf = lds_fused(g, esz);
     bool want_fused = p->opts.schedule == IWFPM_SCHED_FUSED ||
-                      (p->opts.schedule == IWFPM_SCHED_AUTO && (size_t)g.N * esz <= kLdsDefault);
+                      (p->opts.schedule == IWFPM_SCHED_AUTO && lf <= kLdsDefault);
     if (want_fused) {
-        if ((size_t)g.N * esz > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+        if (lf > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
         sc.fused = true;
+        int maxp = 0;
+        for (int ax = 0; ax < n; ++ax) maxp = std::max(maxp, g.N / g.ext[ax]);
+        sc.threads_fused = std::min(256, round64(maxp));
         return IWFPM_OK;
     }
     sc.fused = false;
@@ -331,6 +336,8 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
     // pick the split: trailing axes [split, n) form the contiguous slabs
     int lo = 1, hi = n - 1;
     if (p->opts.order == IWFPM_ORDER_WINDOW) hi = n - p->d;  // k_I axes must stay in one slab
+    PassDesc& pd = sc.pd;
+    pd.xcd_remap = 1;
     int split = 0;
     if (p->opts.split > 0) {
         split = p->opts.split;
@@ -339,10 +346,14 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
         // prefer the k_I / k_II boundary, then the most balanced feasible split
         double best = 1e300;
         for (int s = lo; s <= hi; ++s) {
-            long long sin_ = g.stride[s - 1];
-            long long sout = g.N / sin_;
-            if ((size_t)sin_ * esz > kLdsMax || (size_t)sout * esz > kLdsMax) continue;
-            double cost = std::fabs(std::log((double)sin_) - std::log((double)sout));
+            PassDesc t{};
+            t.s_in = g.stride[s - 1];
+            t.s_out = g.N / t.s_in;
+            t.slabs_per_wg = 1;
+            t.tile = 1;
+            t.split = s;
+            if (lds_slabs(g, t, esz) > kLdsMax || lds_columns(g, t, esz) > kLdsMax) continue;
+            double cost = std::fabs(std::log((double)t.s_in) - std::log((double)t.s_out));
             if (s == n - p->d) cost -= 0.5;
             if (cost < best) {
                 best = cost;
@@ -351,29 +362,47 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
         }
         if (split == 0) return IWFPM_ERR_UNSUPPORTED;
     }
-    PassDesc& pd = sc.pd;
     pd.split = split;
     pd.s_in = g.stride[split - 1];
     pd.s_out = g.N / pd.s_in;
-    if ((size_t)pd.s_in * esz > kLdsMax || (size_t)pd.s_out * esz > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
-    // middle pass: `tile` consecutive columns
+    // middle pass: `tile` consecutive columns (a power of two)
     int T = p->opts.tile;
+    if (T > 0 && (T & (T - 1))) return IWFPM_ERR_ARG;
+    if (T > 0) {
+        pd.tile = T;
+        if (lds_columns(g, pd, esz) > kLdsMax) T = 0;  // does not fit this precision: choose here
+    }
     if (T <= 0) {
         T = 1;
-        while (T < 16 && (size_t)pd.s_out * (2 * T) * esz <= kLdsDefault && 2 * T <= pd.s_in) T *= 2;
+        for (;;) {
+            pd.tile = 2 * T;
+            if (2 * T > 16 || lds_columns(g, pd, esz) > kLdsDefault || 2 * T > pd.s_in) break;
+            T *= 2;
+        }
     }
-    if ((size_t)pd.s_out * T * esz > kLdsMax) return IWFPM_ERR_ARG;
     pd.tile = T;
-    // slabs per workgroup for passes 1 and 3
+    if (lds_columns(g, pd, esz) > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+    // slabs per workgroup for passes 1 and 3: up to ~40 KB of LDS each, and
+    // enough pencils per axis to keep a few waves busy
     int G = 1;
-    while ((size_t)(2 * G) * pd.s_in * esz <= kLdsDefault / 2 && 2 * G <= 64) G *= 2;
+    for (;;) {
+        pd.slabs_per_wg = 2 * G;
+        if (2 * G > 64 || 2 * G > pd.s_out || lds_slabs(g, pd, esz) > kLdsDefault * 5 / 8) break;
+        G *= 2;
+    }
     pd.slabs_per_wg = G;
-    pd.threads_inner = 256;
-    pd.threads_outer = 256;
-    pd.xcd_remap = 1;
-    int mi = 0, mo = 0;
-    for (int ax = split; ax < n; ++ax) mi = std::max(mi, g.ext[ax]);
-    for (int ax = 0; ax < split; ++ax) mo = std::max(mo, g.ext[ax]);
+    if (lds_slabs(g, pd, esz) > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+    int maxpi = 0, maxpo = 0, mi = 0, mo = 0;
+    for (int ax = split; ax < n; ++ax) {
+        maxpi = std::max(maxpi, G * pd.s_in / g.ext[ax]);
+        mi = std::max(mi, g.ext[ax]);
+    }
+    for (int ax = 0; ax < split; ++ax) {
+        maxpo = std::max(maxpo, pd.s_out * T / g.ext[ax]);
+        mo = std::max(mo, g.ext[ax]);
+    }
+    pd.threads_inner = std::min(256, round64(maxpi));
+    pd.threads_outer = std::min(256, round64(maxpo));
     sc.maxs_inner = extent_class(mi);
     sc.maxs_outer = extent_class(mo);
     return IWFPM_OK;
