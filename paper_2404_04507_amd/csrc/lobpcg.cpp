@@ -129,6 +129,134 @@ static void jacobi_eigh(std::vector<cd> A, int n, std::vector<double>& w, std::v
     V.swap(Vs);
 }
 
+// Hermitian eigen-decomposition A = V diag(w) V^H (w ascending) by Householder
+// reduction to a real symmetric tridiagonal matrix followed by the implicit QL
+// iteration with Wilkinson shifts; false if QL does not converge.
+static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std::vector<cd>& V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i + (size_t)i * n] = 1.0;
+    std::vector<cd> v(n), pv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        // reflector H = I - 2 u u^H on rows/cols k+1..n-1 that zeroes A[k+2.., k]
+        double xn = 0.0;
+        for (int i = k + 1; i < n; ++i) xn += std::norm(A[i + (size_t)k * n]);
+        xn = std::sqrt(xn);
+        cd x0 = A[(k + 1) + (size_t)k * n];
+        double tail = xn * xn - std::norm(x0);
+        if (xn == 0.0 || tail <= 1e-300) continue;
+        cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
+        cd alpha = -ph * xn;
+        double un = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            v[i] = A[i + (size_t)k * n];
+            if (i == k + 1) v[i] -= alpha;
+            un += std::norm(v[i]);
+        }
+        un = std::sqrt(un);
+        for (int i = k + 1; i < n; ++i) v[i] /= un;
+        // p = A u, K = u^H p, w = p - K u; A <- A - 2 (u w^H + w u^H)  (on the trailing block and row/col k)
+        for (int i = k; i < n; ++i) {
+            cd acc = 0.0;
+            for (int j = k + 1; j < n; ++j) acc += A[i + (size_t)j * n] * v[j];
+            pv[i] = acc;
+        }
+        cd K = 0.0;
+        for (int i = k + 1; i < n; ++i) K += std::conj(v[i]) * pv[i];
+        for (int i = k + 1; i < n; ++i) pv[i] -= K.real() * v[i];
+        // row/col k: only the (i, k) and (k, i) entries change: A[i,k] <- A[i,k] - 2 u_i (u^H A[:,k])
+        // handled by the general update with u_k = 0
+        for (int j = k; j < n; ++j) {
+            cd vj = j > k ? v[j] : cd(0.0);
+            for (int i = k; i < n; ++i) {
+                cd vi = i > k ? v[i] : cd(0.0);
+                A[i + (size_t)j * n] -= 2.0 * (vi * std::conj(pv[j]) + pv[i] * std::conj(vj));
+            }
+        }
+        // V <- V H
+        for (int r = 0; r < n; ++r) {
+            cd acc = 0.0;
+            for (int j = k + 1; j < n; ++j) acc += V[r + (size_t)j * n] * v[j];
+            for (int j = k + 1; j < n; ++j) V[r + (size_t)j * n] -= 2.0 * acc * std::conj(v[j]);
+        }
+    }
+    // real tridiagonal: d (diagonal), e (sub-diagonal made real by a diagonal phase)
+    std::vector<double> d(n), e(n, 0.0);
+    cd phase = 1.0;
+    for (int k = 0; k < n; ++k) {
+        d[k] = A[k + (size_t)k * n].real();
+        if (k + 1 < n) {
+            cd sub = A[(k + 1) + (size_t)k * n];
+            double a = std::abs(sub);
+            cd next = a > 0.0 ? phase * (sub / a) : phase;
+            e[k] = a;
+            for (int r = 0; r < n; ++r) V[r + (size_t)(k + 1) * n] *= next;
+            phase = next;
+        }
+    }
+    // implicit QL with Wilkinson shifts (e[k] couples k and k+1)
+    for (int l = 0; l < n; ++l) {
+        int iter = 0, m;
+        do {
+            for (m = l; m < n - 1; ++m) {
+                double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+            }
+            if (m != l) {
+                if (++iter > 80) return false;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = std::hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+                double sn = 1.0, cs = 1.0, pp = 0.0;
+                int i;
+                bool deflated = false;
+                for (i = m - 1; i >= l; --i) {
+                    double f = sn * e[i], b = cs * e[i];
+                    r = std::hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= pp;
+                        e[m] = 0.0;
+                        deflated = true;
+                        break;
+                    }
+                    sn = f / r;
+                    cs = g / r;
+                    g = d[i + 1] - pp;
+                    r = (d[i] - g) * sn + 2.0 * cs * b;
+                    pp = sn * r;
+                    d[i + 1] = g + pp;
+                    g = cs * r - b;
+                    for (int k = 0; k < n; ++k) {
+                        cd fz = V[k + (size_t)(i + 1) * n];
+                        V[k + (size_t)(i + 1) * n] = sn * V[k + (size_t)i * n] + cs * fz;
+                        V[k + (size_t)i * n] = cs * V[k + (size_t)i * n] - sn * fz;
+                    }
+                }
+                if (deflated) continue;
+                d[l] -= pp;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        } while (m != l);
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    std::vector<cd> Vs((size_t)n * n);
+    w.resize(n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = d[idx[j]];
+        for (int i = 0; i < n; ++i) Vs[i + (size_t)j * n] = V[i + (size_t)idx[j] * n];
+    }
+    V.swap(Vs);
+    return true;
+}
+
+// Hermitian eigensolver used throughout: Householder + QL, Jacobi as fallback
+static void heev(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) {
+    if (!householder_ql(A, n, w, V)) jacobi_eigh(A, n, w, V);
+}
+
 // SVQB: T (k x r) with (B T)^H (B T) = I for the Gram matrix G = B^H B (k x k);
 // directions whose scaled eigenvalue is below eps are dropped.  Returns r.
 static int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps = 1e-12) {
@@ -148,7 +276,7 @@ static int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps 
         }
     std::vector<double> w;
     std::vector<cd> U;
-    jacobi_eigh(S, k, w, U);
+    heev(S, k, w, U);
     double wmax = k ? w[k - 1] : 0.0;
     std::vector<int> keep;
     for (int j = 0; j < k; ++j)
@@ -191,7 +319,7 @@ static bool gen_eigh(const std::vector<cd>& A, const std::vector<cd>& B, int n, 
             At[j + i * n] = std::conj(a);
         }
     std::vector<cd> Y;
-    jacobi_eigh(At, n, theta, Y);
+    heev(At, n, theta, Y);
     // C = L^{-H} Y
     C.assign((size_t)n * n, 0.0);
     for (int j = 0; j < n; ++j)
@@ -395,7 +523,7 @@ static int rr_block(Ctx& c, int m, std::vector<double>& theta) {
     if (rc) return rc;
     hermitian_part(G, m);
     std::vector<cd> C;
-    jacobi_eigh(G, m, theta, C);
+    heev(G, m, theta, C);
     if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
     if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), cols(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
     std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
@@ -595,7 +723,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         }
         std::vector<double> th;
         std::vector<cd> Cfull;
-        jacobi_eigh(A, ns, th, Cfull);
+        heev(A, ns, th, Cfull);
         // next P: the non-X part of the new Ritz vectors, orthogonalised against
         // them and orthonormalised, all in the ns-dimensional coefficient space
         std::vector<cd> Z((size_t)ns * m, 0.0);
