@@ -51,6 +51,7 @@ extern "C" {
 #endif
 
 typedef struct iwfpm_plan_s* iwfpm_plan_t;
+typedef struct iwfpm_batch_s* iwfpm_batch_t;
 
 typedef enum {
     IWFPM_OK = 0,
@@ -140,6 +141,47 @@ int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* 
 /* As iwfpm_apply but forcing the convolution precision (IWFPM_PREC_*). */
 int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
                      int precision, void* stream);
+
+/*
+ * Ragged batches: many plans (for example a sweep of couplings whose windows,
+ * and so grid sizes, differ) applied together, Sec. 4.1's H~ psi per plan.
+ * iwfpm_batch_create - B plans on one device, convolution precision
+ *   IWFPM_PREC_*; use_graph != 0 captures the batch's launches (one persistent
+ *   launch per pass walking a work table in device memory) into a hipGraph on
+ *   the first apply and replays it afterwards.  The plans must outlive the
+ *   batch and must not be used concurrently with it.
+ * iwfpm_batch_apply - hpsi[i] = H~_i psi[i] for nvec[i] vectors of plan i
+ *   (device pointers, same layout as iwfpm_apply; nvec[i] = 0 skips plan i).
+ *   Asynchronous on `stream`; the work table is refreshed by a copy on the same
+ *   stream, so consecutive applies may change pointers and counts freely.
+ *   A captured graph is bound to the stream it was captured on; another
+ *   stream re-captures; on the null stream the launches are issued directly.
+ *   A plan may appear only once in a batch.
+ * iwfpm_batch_destroy - release (synchronises the device).
+ * Errors: ERR_ARG (plans on different devices, bad counts or pointers),
+ * ERR_NODEVICE, ERR_UNSUPPORTED, ERR_ALLOC, ERR_DEVICE.
+ */
+int iwfpm_batch_create(int B, const iwfpm_plan_t* plans, int precision, int use_graph, iwfpm_batch_t* out);
+int iwfpm_batch_apply(iwfpm_batch_t batch, const void* const* psi, void* const* hpsi, const int* nvec,
+                      void* stream);
+int iwfpm_batch_destroy(iwfpm_batch_t batch);
+
+/*
+ * iwfpm_tune - autotuner: times every feasible apply schedule of the plan on
+ * its device (fused, or three-pass over every axis split x middle-pass tile
+ * width x slabs per workgroup) on nvec scratch vectors with HIP events on
+ * `stream`, and keeps the fastest for `precision` (IWFPM_PREC_*, or -1 for the
+ * plan's).  With the environment variable IWFPM_TUNE_CACHE naming a file,
+ * earlier results for the same (precision, order, potential form, d, nvec,
+ * extents) are reused and new ones appended (one line per key).  best_us
+ * (may be NULL) receives the best time per apply in microseconds, or -1 when
+ * the cache answered.  Allocates 2 x nvec vectors of scratch; blocking.
+ * iwfpm_schedule - the current schedule for `precision`: out[4] = {fused,
+ * split, tile, slabs per workgroup}.
+ * Errors: ERR_ARG, ERR_NODEVICE, ERR_UNSUPPORTED, ERR_ALLOC, ERR_DEVICE.
+ */
+int iwfpm_tune(iwfpm_plan_t plan, int nvec, int precision, void* stream, double* best_us);
+int iwfpm_schedule(iwfpm_plan_t plan, int precision, int32_t* out);
 
 /*
  * iwfpm_profile - start (enable = 1) or stop (0) timing the kernels of every

@@ -25,7 +25,8 @@ _LIB = None
 EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_destroy", "iwfpm_dof",
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
             "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
-            "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb"]
+            "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb", "iwfpm_tune", "iwfpm_schedule",
+            "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy"]
 
 PREC = {"fp64": 0, "fp32": 1}
 WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
@@ -90,6 +91,11 @@ def load_library():
     lib.iwfpm_apply_prec.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.iwfpm_profile.argtypes = [vp, ctypes.c_int]
     lib.iwfpm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.iwfpm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.iwfpm_batch_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), vp]
+    lib.iwfpm_batch_destroy.argtypes = [vp]
+    lib.iwfpm_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, dp]
+    lib.iwfpm_schedule.argtypes = [vp, ctypes.c_int, ip]
     lib.iwfpm_dense_geneig.argtypes = [ctypes.c_int, dp, dp, dp, dp]
     lib.iwfpm_dense_svqb.argtypes = [ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
     lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
@@ -153,6 +159,46 @@ def dense_svqb(G):
     _check(_lib().iwfpm_dense_svqb(k, _ptr(g, ctypes.c_double), _ptr(T, ctypes.c_double), ctypes.byref(r)),
            "iwfpm_dense_svqb")
     return T.view(np.complex128)[:k * r.value].reshape(k, r.value, order="F")
+
+
+class Batch:
+    """A ragged batch of plans applied by one persistent launch per pass (iwfpm_batch_*)."""
+
+    def __init__(self, plans, precision="fp32", graph=True):
+        lib = _lib()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.iwfpm_batch_create(len(self.plans), arr, PREC[precision], int(bool(graph)), ctypes.byref(h)),
+               "iwfpm_batch_create")
+        self._h = h
+
+    def apply(self, psis, outs, stream=None):
+        n = len(self.plans)
+        nv = (ctypes.c_int * n)()
+        ps = (ctypes.c_void_p * n)()
+        hs = (ctypes.c_void_p * n)()
+        for i, (plan, x, y) in enumerate(zip(self.plans, psis, outs)):
+            if x is None or x.numel() == 0:
+                nv[i] = 0
+                continue
+            nv[i] = plan._check_block(x)
+            plan._check_block(y)
+            ps[i] = x.data_ptr()
+            hs[i] = y.data_ptr()
+        _check(_lib().iwfpm_batch_apply(self._h, ps, hs, nv, _stream_handle(stream)), "iwfpm_batch_apply")
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().iwfpm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass
@@ -272,6 +318,19 @@ class Plan:
                                      nvec, prec, _stream_handle(stream))
         _check(st, "iwfpm_apply")
         return out
+
+    def tune(self, nvec=16, precision=None, stream=None) -> float:
+        """Autotune the apply schedule on the device; returns the best microseconds per apply."""
+        best = ctypes.c_double()
+        prec = -1 if precision is None else PREC[precision]
+        _check(_lib().iwfpm_tune(self._h, int(nvec), prec, _stream_handle(stream), ctypes.byref(best)), "iwfpm_tune")
+        return best.value
+
+    def schedule(self, precision=None) -> dict:
+        out = np.zeros(4, dtype=np.int32)
+        prec = -1 if precision is None else PREC[precision]
+        _check(_lib().iwfpm_schedule(self._h, prec, _ptr(out, ctypes.c_int32)), "iwfpm_schedule")
+        return {"fused": bool(out[0]), "split": int(out[1]), "tile": int(out[2]), "slabs_per_wg": int(out[3])}
 
     def profile(self, enable: bool):
         _check(_lib().iwfpm_profile(self._h, int(bool(enable))), "iwfpm_profile")

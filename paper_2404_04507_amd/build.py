@@ -33,9 +33,9 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arc
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-HOST_SOURCES = ["plan.cpp", "lobpcg.cpp", "learned.cpp"]
+HOST_SOURCES = ["plan.cpp", "batch.cpp", "lobpcg.cpp", "learned.cpp"]
 DEVICE_SOURCES = ["blas_kernels.hip"]
-APPLY_TUS = [(k, r, m) for k in range(4) for r in ("float", "double") for m in (16, 32, 64)]
+APPLY_TUS = [(k, r, m) for k in range(5) for r in ("float", "double") for m in (16, 32, 64)]
 
 
 def _jobs():

@@ -417,14 +417,14 @@ __device__ __forceinline__ void kinetic_scatter(const DevGeom& g, const DevTabs&
 // ---------------------------------------------------------------------------
 
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, RowGeom rg, const double2* __restrict__ psi,
-                                               double2* __restrict__ hpsi) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void fused_body(const DevGeom& g, const DevTabs& t, RowGeom rg,
+                                           const double2* __restrict__ psi, double2* __restrict__ hpsi, int vecid,
+                                           unsigned char* smem) {
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
     const int N = g.N;
     const int rows = N / rg.sl;
     unsigned char* extra = smem + (size_t)rows * rg.sp * sizeof(cplx<R>);
-    const long long off = (long long)blockIdx.x * N;
+    const long long off = (long long)vecid * N;
     const double2* __restrict__ x = psi + off;
     double2* __restrict__ y = hpsi + off;
 
@@ -450,6 +450,13 @@ __global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, RowGeom rg,
     kinetic_scatter<R>(g, t, x, y, 0, N, tile, rg, row_table_at(extra, rows, g.d));
 }
 
+template <typename R, int MAXS>
+__global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, RowGeom rg, const double2* __restrict__ psi,
+                                               double2* __restrict__ hpsi) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    fused_body<R, MAXS>(g, t, rg, psi, hpsi, blockIdx.x, smem);
+}
+
 // ---------------------------------------------------------------------------
 // three-pass schedule.  Passes 1 and 3 give each workgroup up to
 // slabs_per_wg consecutive slabs of one vector.
@@ -457,13 +464,13 @@ __global__ void __launch_bounds__(256) k_fused(DevGeom g, DevTabs t, RowGeom rg,
 
 // pass 1: gather (window order) + inverse DFT along the trailing axes
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
-                                               const double2* __restrict__ psi, cplx<R>* __restrict__ ws) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void pass1_body(const DevGeom& g, const DevTabs& t, const PassDesc& pd, RowGeom rg,
+                                           const double2* __restrict__ psi, cplx<R>* __restrict__ ws, int bid_raw,
+                                           int nblocks, unsigned char* smem) {
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
     const int G = pd.slabs_per_wg, sin_ = pd.s_in;
     const int bpv = (pd.s_out + G - 1) / G;
-    const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
+    const int bid = remap_block(bid_raw, nblocks, pd.xcd_remap);
     const int vec = bid / bpv;
     const int slab0 = (bid - vec * bpv) * G;
     const int nsl = min(G, pd.s_out - slab0);
@@ -481,19 +488,26 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g
     store_tile<R>(ws + off + r0, count, tile, rg);
 }
 
+template <typename R, int MAXS>
+__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
+                                               const double2* __restrict__ psi, cplx<R>* __restrict__ ws) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass1_body<R, MAXS>(g, t, pd, rg, psi, ws, blockIdx.x, gridDim.x, smem);
+}
+
 // pass 2: inverse DFT along the leading axes, x V, forward DFT, on a tile of
 // `tile` consecutive columns of one vector.  The LDS tile is [outer][column];
 // its rows (one line of the last leading axis times the columns) are padded
 // by `tile` entries, which spreads the lanes of the pencils along that axis
 // over distinct banks.
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, const PassDesc& pd,
+                                           cplx<R>* __restrict__ ws, int bid_raw, int nblocks, unsigned char* smem) {
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
     const int T = pd.tile, lgT = __ffs(T) - 1;
     const int sin_ = pd.s_in, sout = pd.s_out;
     const int ntile = (sin_ + T - 1) / T;
-    const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
+    const int bid = remap_block(bid_raw, nblocks, pd.xcd_remap);
     const int vec = bid / ntile;
     const int c0 = (bid - vec * ntile) * T;
     const int tw = min(T, sin_ - c0);
@@ -549,16 +563,22 @@ __global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd
     }
 }
 
+template <typename R, int MAXS>
+__global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass2_body<R, MAXS>(g, t, pd, ws, blockIdx.x, gridDim.x, smem);
+}
+
 // pass 3: forward DFT along the trailing axes + kinetic term + scatter
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass3(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
-                                               const double2* __restrict__ psi, const cplx<R>* __restrict__ ws,
-                                               double2* __restrict__ hpsi) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void pass3_body(const DevGeom& g, const DevTabs& t, const PassDesc& pd, RowGeom rg,
+                                           const double2* __restrict__ psi, const cplx<R>* __restrict__ ws,
+                                           double2* __restrict__ hpsi, int bid_raw, int nblocks,
+                                           unsigned char* smem) {
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
     const int G = pd.slabs_per_wg, sin_ = pd.s_in;
     const int bpv = (pd.s_out + G - 1) / G;
-    const int bid = remap_block(blockIdx.x, gridDim.x, pd.xcd_remap);
+    const int bid = remap_block(bid_raw, nblocks, pd.xcd_remap);
     const int vec = bid / bpv;
     const int slab0 = (bid - vec * bpv) * G;
     const int nsl = min(G, pd.s_out - slab0);
@@ -575,6 +595,73 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass3(DevGeom g
     }
     kinetic_scatter<R>(g, t, psi + off, hpsi + off, r0, count, tile, rg,
                        row_table_at(extra, G * sin_ / rg.sl, g.d));
+}
+
+template <typename R, int MAXS>
+__global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass3(DevGeom g, DevTabs t, PassDesc pd, RowGeom rg,
+                                               const double2* __restrict__ psi, const cplx<R>* __restrict__ ws,
+                                               double2* __restrict__ hpsi) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pass3_body<R, MAXS>(g, t, pd, rg, psi, ws, hpsi, blockIdx.x, gridDim.x, smem);
+}
+
+// ---------------------------------------------------------------------------
+// ragged batches: one persistent launch per pass walks a work table of many
+// plans (e.g. a sweep of couplings whose windows differ).  Work items of
+// instance i are [start[i], start[i+1]); every workgroup strides over the
+// items, so the grid size is independent of the batch and a captured graph
+// of the launches stays valid while the table in device memory changes.
+// ---------------------------------------------------------------------------
+
+struct BatchItem {
+    DevGeom g;
+    DevTabs t;
+    PassDesc pd;
+    RowGeom rg;
+    const double2* psi;
+    double2* hpsi;
+    void* ws;
+    int fused;
+    int start[3];  // first work item of this instance in passes 1, 2, 3 (fused: pass 1 = vectors)
+};
+
+struct BatchHead {
+    int B;
+    int total[3];  // work items per pass
+};
+
+__device__ __forceinline__ int find_item(const BatchItem* __restrict__ items, int B, int pass, int w) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].start[pass] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R, int MAXS>
+__global__ void __launch_bounds__(256) k_batch_pass(const BatchHead* __restrict__ head,
+                                                    const BatchItem* __restrict__ items, int pass) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int B = head->B, total = head->total[pass];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const int i = find_item(items, B, pass, w);
+        const BatchItem& it = items[i];
+        const int end = i + 1 < B ? items[i + 1].start[pass] : total;
+        const int local = w - it.start[pass], nb = end - it.start[pass];
+        __syncthreads();  // the previous item's LDS tile is no longer read
+        if (it.fused) {
+            if (pass == 0) fused_body<R, MAXS>(it.g, it.t, it.rg, it.psi, it.hpsi, local, smem);
+        } else if (pass == 0) {
+            pass1_body<R, MAXS>(it.g, it.t, it.pd, it.rg, it.psi, reinterpret_cast<cplx<R>*>(it.ws), local, nb, smem);
+        } else if (pass == 1) {
+            pass2_body<R, MAXS>(it.g, it.t, it.pd, reinterpret_cast<cplx<R>*>(it.ws), local, nb, smem);
+        } else {
+            pass3_body<R, MAXS>(it.g, it.t, it.pd, it.rg, it.psi, reinterpret_cast<const cplx<R>*>(it.ws), it.hpsi,
+                                local, nb, smem);
+        }
+    }
 }
 
 }  // namespace iwfpm

@@ -42,6 +42,13 @@ hipError_t launch_pass2(const DevGeom& g, const DevTabs& t, const PassDesc& pd, 
 template <typename R, int MAXS>
 hipError_t launch_pass3(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, const void* ws,
                         void* hpsi, int nvec, hipStream_t st);
+// persistent batched pass over the work table (head, items in device memory)
+template <typename R, int MAXS>
+hipError_t launch_batch(const void* head, const void* items, int grid, size_t lds, int pass, hipStream_t st);
+template <typename R, int MAXS>
+hipError_t prepare_batch(int lds_bytes);
+template <typename R, int MAXS>
+hipError_t occupancy_batch(size_t lds, int* blocks_per_cu);
 // raise the dynamic-LDS limit of the kernel of this translation unit (current device)
 template <typename R, int MAXS>
 hipError_t prepare_fused(int lds_bytes);

@@ -1,5 +1,6 @@
 // apply_tu.hip - one (kernel, precision) pair of the apply, selected at
-// build time by IWFPM_TU_KERNEL (0 fused, 1 pass 1, 2 pass 2, 3 pass 3) and
+// build time by IWFPM_TU_KERNEL (0 fused, 1 pass 1, 2 pass 2, 3 pass 3, 4 the
+// persistent batched pass) and
 // IWFPM_TU_REAL (float or double) and IWFPM_TU_MAXS, the largest
 // axis extent the instantiated kernels transform (16, 32 or 64).
 #include "apply_kernels.hpp"
@@ -75,6 +76,22 @@ hipError_t launch_pass3<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc
 template <>
 hipError_t prepare_pass3<R, M>(int lds_bytes) {
     return hipFuncSetAttribute((const void*)k_pass3<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+#elif IWFPM_TU_KERNEL == 4
+template <>
+hipError_t launch_batch<R, M>(const void* head, const void* items, int grid, size_t lds, int pass, hipStream_t st) {
+    k_batch_pass<R, M><<<dim3(grid), dim3(256), lds, st>>>(reinterpret_cast<const BatchHead*>(head),
+                                                           reinterpret_cast<const BatchItem*>(items), pass);
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_batch<R, M>(int lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_batch_pass<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds_bytes);
+}
+template <>
+hipError_t occupancy_batch<R, M>(size_t lds, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_pass<R, M>, 256, lds);
 }
 #else
 #error "IWFPM_TU_KERNEL out of range"

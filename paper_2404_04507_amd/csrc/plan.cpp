@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 
 #include "apply_launch.hpp"
 #include "sizes.hpp"
@@ -32,6 +33,7 @@ static bool extent_supported(int e) {
 }
 
 static int extent_class(int e) { return e <= 16 ? 16 : (e <= 32 ? 32 : 64); }
+int extent_class_of(int e) { return extent_class(e); }
 
 int dev_alloc(DeviceBuf& b, size_t bytes) {
     dev_free(b);
@@ -311,6 +313,7 @@ static const size_t kLdsDefault = 64 * 1024;
 static const size_t kLdsMax = 160 * 1024;
 
 static int round64(int x) { return ((x + 63) / 64) * 64; }
+static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc);
 
 static int choose_schedule(iwfpm_plan_s* p, int prec) {
     Schedule& sc = p->sched[prec];
@@ -392,20 +395,72 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
     }
     pd.slabs_per_wg = G;
     if (lds_slabs(g, pd, esz) > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
+    finalize_threepass(p, sc);
+    return IWFPM_OK;
+}
+
+// threads and extent classes of a three-pass schedule whose split, tile and
+// slabs per workgroup are set
+static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc) {
+    const DevGeom& g = p->geom;
+    PassDesc& pd = sc.pd;
     int maxpi = 0, maxpo = 0, mi = 0, mo = 0;
-    for (int ax = split; ax < n; ++ax) {
-        maxpi = std::max(maxpi, G * pd.s_in / g.ext[ax]);
+    for (int ax = pd.split; ax < p->n; ++ax) {
+        maxpi = std::max(maxpi, pd.slabs_per_wg * pd.s_in / g.ext[ax]);
         mi = std::max(mi, g.ext[ax]);
     }
-    for (int ax = 0; ax < split; ++ax) {
-        maxpo = std::max(maxpo, pd.s_out * T / g.ext[ax]);
+    for (int ax = 0; ax < pd.split; ++ax) {
+        maxpo = std::max(maxpo, pd.s_out * pd.tile / g.ext[ax]);
         mo = std::max(mo, g.ext[ax]);
     }
     pd.threads_inner = std::min(256, round64(maxpi));
     pd.threads_outer = std::min(256, round64(maxpo));
     sc.maxs_inner = extent_class(mi);
     sc.maxs_outer = extent_class(mo);
-    return IWFPM_OK;
+    sc.fused = false;
+    sc.ok = true;
+}
+
+// every feasible schedule for precision prec
+static std::vector<Schedule> schedule_candidates(const iwfpm_plan_s* p, int prec) {
+    std::vector<Schedule> out;
+    const DevGeom& g = p->geom;
+    const int n = p->n;
+    const size_t esz = prec == 1 ? 8 : 16;
+    if (lds_fused(g, esz) <= kLdsMax) {
+        Schedule f = p->sched[prec];
+        int maxall = 0, maxp = 0;
+        for (int ax = 0; ax < n; ++ax) {
+            maxall = std::max(maxall, g.ext[ax]);
+            maxp = std::max(maxp, g.N / g.ext[ax]);
+        }
+        f.fused = true;
+        f.ok = true;
+        f.maxs_fused = extent_class(maxall);
+        f.threads_fused = std::min(256, round64(maxp));
+        out.push_back(f);
+    }
+    if (n < 2) return out;
+    int hi = p->opts.order == IWFPM_ORDER_WINDOW ? n - p->d : n - 1;
+    for (int split = 1; split <= hi; ++split) {
+        for (int T = 1; T <= 32; T *= 2) {
+            for (int G = 1; G <= 64; G *= 2) {
+                Schedule c{};
+                PassDesc& pd = c.pd;
+                pd.split = split;
+                pd.s_in = g.stride[split - 1];
+                pd.s_out = g.N / pd.s_in;
+                pd.tile = T;
+                pd.slabs_per_wg = G;
+                pd.xcd_remap = 1;
+                if (T > pd.s_in || G > pd.s_out) continue;
+                if (lds_columns(g, pd, esz) > kLdsMax || lds_slabs(g, pd, esz) > kLdsMax) continue;
+                finalize_threepass(p, c);
+                out.push_back(c);
+            }
+        }
+    }
+    return out;
 }
 
 template <typename R>
@@ -424,6 +479,9 @@ static int prepare_kernels() {
     e = prepare_pass3<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_pass3<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_pass3<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_batch<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_batch<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_batch<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     return IWFPM_OK;
 }
 
@@ -532,6 +590,18 @@ static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTa
 }
 
 static const size_t kWorkspaceCap = (size_t)4 << 30;
+
+int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st) {
+    const Schedule& sc = p->sched[prec];
+    if (!sc.ok) return IWFPM_ERR_UNSUPPORTED;
+    if (sc.fused) return IWFPM_OK;
+    size_t need = (size_t)p->geom.N * (prec ? 8 : 16) * nvec;
+    if (p->d_ws.bytes < need) {
+        if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
+        if (dev_alloc(p->d_ws, need) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+    }
+    return IWFPM_OK;
+}
 
 int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st) {
     if (nvec == 0) return IWFPM_OK;
@@ -765,6 +835,137 @@ int iwfpm_profile_read(iwfpm_plan_t p, double* ms, int64_t* launches, int64_t* p
         launches[k] = p->prof.launches[k];
         points[k] = p->prof.points[k];
     }
+    return IWFPM_OK;
+}
+
+static std::string tune_key(const iwfpm_plan_s* p, int prec, int nvec) {
+    std::string k = "prec=" + std::to_string(prec) + ";order=" + std::to_string(p->opts.order) +
+                    ";vmode=" + std::to_string(p->geom.vmode) + ";d=" + std::to_string(p->d) +
+                    ";nvec=" + std::to_string(nvec) + ";ext=";
+    for (int ax = 0; ax < p->n; ++ax) k += std::to_string(p->geom.ext[ax]) + (ax + 1 < p->n ? "x" : "");
+    return k;
+}
+
+static bool tune_cache_lookup(const char* path, const std::string& key, Schedule& sc, const iwfpm_plan_s* p) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[512];
+        int fused, split, tile, G;
+        if (std::sscanf(line, "%511s %d %d %d %d", k, &fused, &split, &tile, &G) != 5) continue;
+        if (key != k) continue;
+        if (fused) {
+            found = false;  // re-derive below
+            sc.fused = true;
+            found = true;
+        } else {
+            Schedule c{};
+            c.pd.split = split;
+            c.pd.s_in = p->geom.stride[split - 1];
+            c.pd.s_out = p->geom.N / c.pd.s_in;
+            c.pd.tile = tile;
+            c.pd.slabs_per_wg = G;
+            c.pd.xcd_remap = 1;
+            finalize_threepass(p, c);
+            sc = c;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+int iwfpm_tune(iwfpm_plan_t p, int nvec, int precision, void* stream, double* best_us) {
+    if (!p || nvec < 1) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    const int prec = precision < 0 ? p->opts.precision : (precision == IWFPM_PREC_FP32 ? 1 : 0);
+    DeviceGuard guard(p->opts.device);
+    if (!guard.ok) return IWFPM_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<Schedule> cands = schedule_candidates(p, prec);
+    if (cands.empty()) return IWFPM_ERR_UNSUPPORTED;
+    const std::string key = tune_key(p, prec, nvec);
+    const char* cache = std::getenv("IWFPM_TUNE_CACHE");
+    if (cache && cache[0]) {
+        Schedule sc{};
+        if (tune_cache_lookup(cache, key, sc, p)) {
+            if (sc.fused) {
+                for (auto& c : cands)
+                    if (c.fused) sc = c;
+            }
+            if (sc.ok) {
+                p->sched[prec] = sc;
+                if (best_us) *best_us = -1.0;
+                return IWFPM_OK;
+            }
+        }
+    }
+    DeviceBuf x, y;
+    const size_t bytes = (size_t)nvec * p->geom.N * 16;
+    if (dev_alloc(x, bytes) != IWFPM_OK || dev_alloc(y, bytes) != IWFPM_OK) {
+        dev_free(x);
+        dev_free(y);
+        return IWFPM_ERR_ALLOC;
+    }
+    if (hipMemsetAsync(x.ptr, 0, bytes, st) != hipSuccess) return IWFPM_ERR_DEVICE;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const Schedule keep = p->sched[prec];
+    const bool prof = p->prof.on;
+    p->prof.on = false;
+    double best = 1e300;
+    Schedule best_sc = keep;
+    int rc = IWFPM_OK;
+    for (const Schedule& c : cands) {
+        p->sched[prec] = c;
+        if ((rc = plan_apply(p, x.ptr, y.ptr, nvec, prec, st)) != IWFPM_OK) break;
+        (void)hipEventRecord(e0, st);
+        const int reps = 3;
+        for (int r = 0; r < reps && rc == IWFPM_OK; ++r) rc = plan_apply(p, x.ptr, y.ptr, nvec, prec, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = IWFPM_ERR_DEVICE;
+        if (rc != IWFPM_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        double us = 1e3 * ms / reps;
+        if (us < best) {
+            best = us;
+            best_sc = c;
+        }
+    }
+    p->prof.on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free(x);
+    dev_free(y);
+    if (rc != IWFPM_OK) {
+        p->sched[prec] = keep;
+        return rc;
+    }
+    p->sched[prec] = best_sc;
+    if (best_us) *best_us = best;
+    if (cache && cache[0]) {
+        if (FILE* f = std::fopen(cache, "a")) {
+            std::fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), best_sc.fused ? 1 : 0, best_sc.pd.split,
+                         best_sc.pd.tile, best_sc.pd.slabs_per_wg, best);
+            std::fclose(f);
+        }
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_schedule(iwfpm_plan_t p, int precision, int32_t* out) {
+    if (!p || !out) return IWFPM_ERR_ARG;
+    const int prec = precision < 0 ? p->opts.precision : (precision == IWFPM_PREC_FP32 ? 1 : 0);
+    const Schedule& sc = p->sched[prec];
+    if (!sc.ok) return IWFPM_ERR_UNSUPPORTED;
+    out[0] = sc.fused ? 1 : 0;
+    out[1] = sc.pd.split;
+    out[2] = sc.pd.tile;
+    out[3] = sc.pd.slabs_per_wg;
     return IWFPM_OK;
 }
 

@@ -97,6 +97,10 @@ struct DeviceGuard {
 int dev_alloc(DeviceBuf& b, size_t bytes);
 void dev_free(DeviceBuf& b);
 
+// grow the plan's apply workspace for nvec vectors of precision prec
+int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st);
+int extent_class_of(int e);
+
 // apply on a plan (precision 0 = float64 convolution, 1 = float32)
 int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st);
 
