@@ -237,6 +237,23 @@ int iwfpm_eigs(iwfpm_plan_t plan, const iwfpm_eigs_opts* opts, const void* x0,
                double* evals, void* evecs, double* eta, iwfpm_stats* stats, void* stream);
 
 /*
+ * iwfpm_eigs_batched - lowest nev eigenpairs of B plans at once (e.g. a sweep
+ * of couplings whose windows differ), by block LOBPCG run in lock step: every
+ * tall operation of an iteration runs for all unconverged plans in one launch,
+ * the applies in one persistent batched launch replayed from a hipGraph, and
+ * each plan's small Rayleigh-Ritz problem on a host thread.  Same options,
+ * convergence test and float32 -> float64 policy as iwfpm_eigs (block size at
+ * most 21 here); start blocks are seeded with opts->seed + i.
+ * evals, eta: host, B x nev (row i = plan i); stats: B entries or NULL.
+ * Plans must be distinct and on one device.  Blocking.
+ * Errors: as iwfpm_eigs; the first plan's failure status is returned
+ * (ERR_NOCONV if any plan hit maxit), results are written for every plan;
+ * ERR_UNSUPPORTED for the learned preconditioner.
+ */
+int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* opts, double* evals, double* eta,
+                       iwfpm_stats* stats, void* stream);
+
+/*
  * Host-side small dense solvers used by iwfpm_eigs's Rayleigh-Ritz step,
  * exported so that they can be checked on their own (no device needed).
  * Matrices are complex float64, column-major, interleaved (re, im), n x n.

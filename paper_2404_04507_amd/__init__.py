@@ -26,7 +26,7 @@ EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_de
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
             "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
             "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb", "iwfpm_tune", "iwfpm_schedule",
-            "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy"]
+            "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy", "iwfpm_eigs_batched"]
 
 PREC = {"fp64": 0, "fp32": 1}
 WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
@@ -94,6 +94,8 @@ def load_library():
     lib.iwfpm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
     lib.iwfpm_batch_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int), vp]
     lib.iwfpm_batch_destroy.argtypes = [vp]
+    lib.iwfpm_eigs_batched.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(_EigsOpts), dp, dp,
+                                       ctypes.POINTER(_Stats), vp]
     lib.iwfpm_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, dp]
     lib.iwfpm_schedule.argtypes = [vp, ctypes.c_int, ip]
     lib.iwfpm_dense_geneig.argtypes = [ctypes.c_int, dp, dp, dp, dp]
@@ -199,6 +201,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def eigs_batched(plans, nev, tol=1e-8, maxit=500, block=0, precond="plain", seed=2404045070, polish=True,
+                 stream=None, allow_noconv=False):
+    """Lowest nev eigenpairs of every plan, solved in lock step (iwfpm_eigs_batched)."""
+    lib = _lib()
+    B = len(plans)
+    o = _EigsOpts()
+    lib.iwfpm_default_eigs_opts(ctypes.byref(o))
+    o.nev, o.block, o.tol, o.maxit = int(nev), int(block), float(tol), int(maxit)
+    o.precond, o.seed, o.polish = PRECOND[precond], int(seed), int(bool(polish))
+    evals = np.zeros((B, nev))
+    eta = np.zeros((B, nev))
+    stats = (_Stats * B)()
+    arr = (ctypes.c_void_p * B)(*[p._h.value for p in plans])
+    st = lib.iwfpm_eigs_batched(B, arr, ctypes.byref(o), _ptr(evals, ctypes.c_double), _ptr(eta, ctypes.c_double),
+                                stats, _stream_handle(stream))
+    if st != 0 and not (allow_noconv and st == -8):
+        raise IwfpmError(st, "iwfpm_eigs_batched")
+    return evals, eta, [{"iterations": s.iterations, "matvecs": s.matvecs, "converged": s.converged,
+                         "polished": s.polished, "t_total": s.t_total} for s in stats], st
 
 
 @dataclass

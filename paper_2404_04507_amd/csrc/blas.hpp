@@ -34,4 +34,42 @@ hipError_t residual_norm(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, 
 hipError_t precond(const ColPtrs& R, const ColPtrs& W, int m, const double* M, long long N, hipStream_t st);
 hipError_t randn(double2* out, long long count, unsigned long long seed, hipStream_t st);
 
+// batched jobs (device-resident tables); job j owns grid blocks [start, start + nb)
+struct GramJob {
+    ColPtrs L, R;
+    int p, q;
+    long long N, rows_per_block;
+    int rows, nb, start, out_start;
+    long long part_off;  // offset of this job's partials (entries)
+};
+struct LinJob {
+    ColPtrs A, Y;
+    const double2* C;  // p x q coefficients (device)
+    double beta;
+    long long N;
+    int p, q, nb, start;
+};
+struct ResJob {
+    ColPtrs HX, X, R;
+    Reals theta;
+    long long N, rows_per_block;
+    int m, nb, start, out_start;
+    long long part_off;
+};
+struct PreJob {
+    ColPtrs R, W;
+    const double* M;
+    long long N;
+    int m, nb, start;
+};
+
+// blocks, rows per block, staged rows and LDS bytes of one gram job
+int gram_job_blocks(int p, int q, long long N, int max_blocks, long long* rows_per_block, int* rows, size_t* lds);
+hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, size_t lds,
+                        double2* partial, double2* C, hipStream_t st);
+hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st);
+hipError_t residual_norm_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,
+                                 double* out, hipStream_t st);
+hipError_t precond_batched(const PreJob* jobs, int njobs, int total_blocks, hipStream_t st);
+
 }  // namespace iwfpm

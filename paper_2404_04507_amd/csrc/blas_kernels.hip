@@ -31,9 +31,9 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // staged through LDS `rows` at a time (as many as fit); at the end the row
 // groups are summed in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long rows_per_block,
-                                              int rows, double2* __restrict__ partial) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
+                                          long long rows_per_block, int rows, double2* __restrict__ partial, int bid,
+                                          unsigned char* smem) {
     const int pl = p | 1, pr = q | 1;  // odd pitches
     double2* sL = reinterpret_cast<double2*>(smem);
     double2* sR = sL + rows * pl;
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    const long long r0 = (long long)blockIdx.x * rows_per_block;
+    const long long r0 = (long long)bid * rows_per_block;
     const long long r1 = min(N, r0 + rows_per_block);
     for (long long rb = r0; rb < r1; rb += rows) {
         const int nr = (int)min((long long)rows, r1 - rb);
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
             for (int b = 0; b < 4; ++b) red[((size_t)grp * ntile + tile) * 16 + a * 4 + b] = acc[a][b];
     }
     __syncthreads();
-    double2* out = partial + (size_t)blockIdx.x * p * q;
+    double2* out = partial + (size_t)bid * p * q;
     for (int e = tid; e < ntile * 16; e += 256) {
         int t = e >> 4, ab = e & 15;
         int i = 4 * (t % TP) + (ab >> 2), j = 4 * (t / TP) + (ab & 3);
@@ -107,6 +107,12 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
         }
         out[(size_t)j * p + i] = sum;
     }
+}
+
+__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long rows_per_block,
+                                              int rows, double2* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gram_body(L, p, R, q, N, rows_per_block, rows, partial, blockIdx.x, smem);
 }
 
 // C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
@@ -136,12 +142,12 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restri
 // lincomb: Y_j = beta Y_j + sum_i A_i C[j*p + i]   (q <= QB <= 48)
 // ---------------------------------------------------------------------------
 template <int QB>
-__global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, int q, const double2* __restrict__ C,
-                                                 double beta, long long N) {
-    __shared__ double2 sC[kMaxCols * 48];
+__device__ __forceinline__ void lincomb_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
+                                             const double2* __restrict__ C, double beta, long long N, int bid, int nb,
+                                             double2* sC) {
     for (int e = threadIdx.x; e < p * q; e += blockDim.x) sC[e] = C[e];
     __syncthreads();
-    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
+    for (long long r = (long long)bid * blockDim.x + threadIdx.x; r < N; r += (long long)nb * blockDim.x) {
         double2 acc[QB];
 #pragma unroll
         for (int j = 0; j < QB; ++j) {
@@ -167,6 +173,13 @@ __global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, in
         for (int j = 0; j < QB; ++j)
             if (j < q) Y.p[j][r] = acc[j];
     }
+}
+
+template <int QB>
+__global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, int q, const double2* __restrict__ C,
+                                                 double beta, long long N) {
+    __shared__ double2 sC[kMaxCols * 48];
+    lincomb_body<QB>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sC);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,11 +233,10 @@ __global__ void __launch_bounds__(256) k_reduce_real(const double* __restrict__ 
 }
 
 // R_j = HX_j - theta_j X_j and the block's partial sums of ||R_j||^2
-__global__ void __launch_bounds__(256) k_residual_norm(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
-                                                       long long N, long long rows_per_block,
-                                                       double* __restrict__ partial) {
-    __shared__ double red[256];
-    const long long r0 = (long long)blockIdx.x * rows_per_block;
+__device__ __forceinline__ void residual_norm_body(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& Rout,
+                                                   const Reals& theta, int m, long long N, long long rows_per_block,
+                                                   double* __restrict__ partial, int bid, double* red) {
+    const long long r0 = (long long)bid * rows_per_block;
     const long long r1 = min(N, r0 + rows_per_block);
     for (int j = 0; j < m; ++j) {
         double s = 0.0;
@@ -241,9 +253,16 @@ __global__ void __launch_bounds__(256) k_residual_norm(ColPtrs HX, ColPtrs X, Co
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * m + j] = red[0];
+        if (threadIdx.x == 0) partial[(size_t)bid * m + j] = red[0];
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(256) k_residual_norm(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
+                                                       long long N, long long rows_per_block,
+                                                       double* __restrict__ partial) {
+    __shared__ double red[256];
+    residual_norm_body(HX, X, Rout, theta, m, N, rows_per_block, partial, blockIdx.x, red);
 }
 
 __global__ void k_precond(ColPtrs R, ColPtrs W, int m, const double* __restrict__ M, long long N) {
@@ -276,6 +295,118 @@ __global__ void k_randn(double2* __restrict__ out, long long count, unsigned lon
         double s, c;
         sincospi(2.0 * u2, &s, &c);
         out[e] = make_double2(rad * c, rad * s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched forms: many independent jobs (one per eigenproblem of a sweep) in
+// one launch; job j owns blocks [start, start + nb) of the grid
+// ---------------------------------------------------------------------------
+
+template <typename J>
+__device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_gram_batched(const GramJob* __restrict__ jobs, int njobs,
+                                                      double2* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const GramJob& jb = jobs[j];
+    gram_body(jb.L, jb.p, jb.R, jb.q, jb.N, jb.rows_per_block, jb.rows, partial + jb.part_off, blockIdx.x - jb.start,
+              smem);
+}
+
+// one workgroup per output entry over all jobs (job j's entries start at out_start)
+__global__ void __launch_bounds__(256) k_reduce_batched(const GramJob* __restrict__ jobs, int njobs,
+                                                        const double2* __restrict__ partial,
+                                                        double2* __restrict__ C) {
+    __shared__ double2 red[256];
+    const int e = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].out_start <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const GramJob& jb = jobs[lo];
+    const int le = e - jb.out_start, cnt = jb.p * jb.q;
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < jb.nb; b += 256) {
+        double2 v = partial[jb.part_off + (size_t)b * cnt + le];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[threadIdx.x].x += red[threadIdx.x + w].x;
+            red[threadIdx.x].y += red[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C[e] = red[0];
+}
+
+template <int QB>
+__global__ void __launch_bounds__(256) k_lincomb_batched(const LinJob* __restrict__ jobs, int njobs) {
+    __shared__ double2 sC[kMaxCols * 48];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const LinJob& jb = jobs[j];
+    lincomb_body<QB>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sC);
+}
+
+__global__ void __launch_bounds__(256) k_residual_norm_batched(const ResJob* __restrict__ jobs, int njobs,
+                                                               double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const ResJob& jb = jobs[j];
+    residual_norm_body(jb.HX, jb.X, jb.R, jb.theta, jb.m, jb.N, jb.rows_per_block, partial + jb.part_off,
+                       blockIdx.x - jb.start, red);
+}
+
+// out[j's entries] = sums of the residual-norm partials
+__global__ void __launch_bounds__(256) k_reduce_res_batched(const ResJob* __restrict__ jobs, int njobs,
+                                                            const double* __restrict__ partial,
+                                                            double* __restrict__ out) {
+    __shared__ double red[256];
+    const int e = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].out_start <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const ResJob& jb = jobs[lo];
+    const int le = e - jb.out_start;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < jb.nb; b += 256) s += partial[jb.part_off + (size_t)b * jb.m + le];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_precond_batched(const PreJob* __restrict__ jobs, int njobs) {
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const PreJob& jb = jobs[j];
+    const int bid = blockIdx.x - jb.start;
+    for (long long r = (long long)bid * blockDim.x + threadIdx.x; r < jb.N; r += (long long)jb.nb * blockDim.x) {
+        double mm = jb.M[r];
+        for (int c = 0; c < jb.m; ++c) {
+            double2 v = jb.R.p[c][r];
+            jb.W.p[c][r] = make_double2(mm * v.x, mm * v.y);
+        }
     }
 }
 
@@ -344,6 +475,50 @@ hipError_t residual_norm(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, 
 
 hipError_t precond(const ColPtrs& R, const ColPtrs& W, int m, const double* M, long long N, hipStream_t st) {
     k_precond<<<grid_for(N, 256), 256, 0, st>>>(R, W, m, M, N);
+    return hipGetLastError();
+}
+
+int gram_job_blocks(int p, int q, long long N, int max_blocks, long long* rows_per_block, int* rows, size_t* lds) {
+    const int pl = p | 1, pr = q | 1;
+    int r = (int)std::min<long long>(128, (48 * 1024) / ((pl + pr) * (long long)sizeof(double2)));
+    r = std::max(r, 8);
+    long long rpb = (N + max_blocks - 1) / max_blocks;
+    rpb = ((rpb + r - 1) / r) * r;
+    int ntile = ((p + 3) / 4) * ((q + 3) / 4);
+    *rows_per_block = rpb;
+    *rows = r;
+    *lds = std::max((size_t)r * (pl + pr) * sizeof(double2), (size_t)(256 / ntile) * ntile * 16 * sizeof(double2));
+    return (int)((N + rpb - 1) / rpb);
+}
+
+hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, size_t lds,
+                        double2* partial, double2* C, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    k_gram_batched<<<total_blocks, 256, lds, st>>>(jobs, njobs, partial);
+    k_reduce_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, C);
+    return hipGetLastError();
+}
+
+hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    if (maxq <= 8) k_lincomb_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (maxq <= 16) k_lincomb_batched<16><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (maxq <= 32) k_lincomb_batched<32><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else k_lincomb_batched<48><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t residual_norm_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,
+                                 double* out, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    k_residual_norm_batched<<<total_blocks, 256, 0, st>>>(jobs, njobs, partial);
+    k_reduce_res_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t precond_batched(const PreJob* jobs, int njobs, int total_blocks, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    k_precond_batched<<<total_blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

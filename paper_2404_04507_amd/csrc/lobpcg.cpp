@@ -28,12 +28,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "blas.hpp"
@@ -478,23 +480,26 @@ static int dev_lincomb(Ctx& c, const std::vector<double2*>& A, const std::vector
     }
     for (int j0 = 0; j0 < q; j0 += 48) {
         int qj = std::min(48, q - j0);
-        if (c.s->ring_since_sync >= kRingSlots - 1)
-            if (int rc = sync(c)) return rc;
-        int slot = c.s->ring_next;
-        c.s->ring_next = (slot + 1) % kRingSlots;
-        c.s->ring_since_sync++;
-        double2* h = c.s->hring + (size_t)slot * kSlot;
-        double2* dC = (double2*)c.s->dring.ptr + (size_t)slot * kSlot;
-        for (int j = 0; j < qj; ++j)
-            for (int i = 0; i < p; ++i) {
-                cd v = Cm[(size_t)(r0 + i) + (size_t)(j0 + j) * ldc];
-                h[(size_t)j * p + i] = make_double2(v.real(), v.imag());
-            }
-        CHECK_HIP(hipMemcpyAsync(dC, h, (size_t)p * qj * sizeof(double2), hipMemcpyHostToDevice, c.st));
-        ColPtrs a{}, y{};
-        for (int i = 0; i < p; ++i) a.p[i] = A[i];
-        for (int j = 0; j < qj; ++j) y.p[j] = Y[j0 + j];
-        CHECK_HIP(lincomb(a, p, y, qj, dC, beta, c.N, c.st));
+        for (int i0 = 0; i0 < p; i0 += kMaxCols) {  // later input chunks accumulate
+            int pi = std::min(kMaxCols, p - i0);
+            if (c.s->ring_since_sync >= kRingSlots - 1)
+                if (int rc = sync(c)) return rc;
+            int slot = c.s->ring_next;
+            c.s->ring_next = (slot + 1) % kRingSlots;
+            c.s->ring_since_sync++;
+            double2* h = c.s->hring + (size_t)slot * kSlot;
+            double2* dC = (double2*)c.s->dring.ptr + (size_t)slot * kSlot;
+            for (int j = 0; j < qj; ++j)
+                for (int i = 0; i < pi; ++i) {
+                    cd v = Cm[(size_t)(r0 + i0 + i) + (size_t)(j0 + j) * ldc];
+                    h[(size_t)j * pi + i] = make_double2(v.real(), v.imag());
+                }
+            CHECK_HIP(hipMemcpyAsync(dC, h, (size_t)pi * qj * sizeof(double2), hipMemcpyHostToDevice, c.st));
+            ColPtrs a{}, y{};
+            for (int i = 0; i < pi; ++i) a.p[i] = A[i0 + i];
+            for (int j = 0; j < qj; ++j) y.p[j] = Y[j0 + j];
+            CHECK_HIP(lincomb(a, pi, y, qj, dC, i0 == 0 ? beta : 1.0, c.N, c.st));
+        }
     }
     return IWFPM_OK;
 }
@@ -536,6 +541,71 @@ static int apply_block(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats
     int rc = plan_apply(c.p, c.col(bin, 0), c.col(bout, 0), cnt, prec, c.st);
     if (stats) stats->matvecs += cnt;
     return rc;
+}
+
+// Rayleigh-Ritz in the coefficient space of the orthonormal basis
+// S = [X W P] (ns columns, the first m are X): G = S^H [HW HP] (ns x (ns - m)),
+// X^H H X = diag(theta).  Returns the Ritz values th (ascending, ns) and U =
+// [C_x | Z T] (ns x 2m): the m lowest Ritz vectors, then the next P as the
+// non-X part of the active Ritz vectors, orthogonalised against C_x and
+// orthonormalised; the return value is the number of P columns.
+static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& theta, int m, int ns,
+                           const std::vector<int>& act, std::vector<double>& th, std::vector<cd>& U) {
+    const int ma = (int)act.size();
+    std::vector<cd> A((size_t)ns * ns, 0.0);
+    const int nr = ns - m;
+    for (int j = 0; j < nr; ++j)
+        for (int i = 0; i < ns; ++i) {
+            A[i + (size_t)(m + j) * ns] = G[i + (size_t)j * ns];
+            if (i < m) A[(m + j) + (size_t)i * ns] = std::conj(G[i + (size_t)j * ns]);
+        }
+    for (int j = 0; j < m; ++j) A[j + (size_t)j * ns] = theta[j];
+    hermitian_part(A, ns);
+    std::vector<cd> Cfull;
+    heev(A, ns, th, Cfull);
+    std::vector<cd> Z((size_t)ns * m, 0.0);
+    for (int a = 0; a < ma; ++a)
+        for (int i = m; i < ns; ++i) Z[i + (size_t)a * ns] = Cfull[i + (size_t)act[a] * ns];
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<cd> Gx((size_t)m * m, 0.0);  // C_x^H Z
+        for (int j = 0; j < ma; ++j)
+            for (int i = 0; i < m; ++i) {
+                cd acc = 0.0;
+                for (int k = 0; k < ns; ++k) acc += std::conj(Cfull[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                Gx[i + (size_t)j * m] = acc;
+            }
+        for (int j = 0; j < ma; ++j)
+            for (int k = 0; k < ns; ++k) {
+                cd acc = 0.0;
+                for (int i = 0; i < m; ++i) acc += Cfull[k + (size_t)i * ns] * Gx[i + (size_t)j * m];
+                Z[k + (size_t)j * ns] -= acc;
+            }
+    }
+    int mpn = 0;
+    U.assign((size_t)ns * (2 * m), 0.0);
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < ns; ++i) U[i + (size_t)j * ns] = Cfull[i + (size_t)j * ns];
+    if (ns > m && ma > 0) {
+        std::vector<cd> Gz((size_t)ma * ma, 0.0), T;
+        for (int j = 0; j < ma; ++j)
+            for (int i = 0; i < ma; ++i) {
+                cd acc = 0.0;
+                for (int k = 0; k < ns; ++k) acc += std::conj(Z[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                Gz[i + (size_t)j * ma] = acc;
+            }
+        double gmax = 0.0;
+        for (int j = 0; j < ma; ++j) gmax = std::max(gmax, Gz[j + (size_t)j * ma].real());
+        if (gmax > 1e-28) {
+            mpn = svqb(Gz, ma, T, 1e-12);
+            for (int j = 0; j < mpn; ++j)
+                for (int i = 0; i < ns; ++i) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < ma; ++k) acc += Z[i + (size_t)k * ns] * T[k + (size_t)j * ma];
+                    U[i + (size_t)(m + j) * ns] = acc;
+                }
+        }
+    }
+    return mpn;
 }
 
 static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
@@ -707,66 +777,14 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         }
         S.insert(S.end(), Pa.begin(), Pa.end());
         HS.insert(HS.end(), HPa.begin(), HPa.end());
-        std::vector<cd> A((size_t)ns * ns, 0.0);
+        std::vector<double> th;
+        std::vector<cd> U;
+        int mpn = 0;
         {
             std::vector<double2*> HR(HS.begin() + m, HS.end());
             std::vector<cd> G;
             if ((rc = host_gram(c, S, HR, G))) return rc;
-            const int nr = ns - m;
-            for (int j = 0; j < nr; ++j)
-                for (int i = 0; i < ns; ++i) {
-                    A[i + (size_t)(m + j) * ns] = G[i + (size_t)j * ns];
-                    if (i < m) A[(m + j) + (size_t)i * ns] = std::conj(G[i + (size_t)j * ns]);
-                }
-            for (int j = 0; j < m; ++j) A[j + (size_t)j * ns] = theta[j];
-            hermitian_part(A, ns);
-        }
-        std::vector<double> th;
-        std::vector<cd> Cfull;
-        heev(A, ns, th, Cfull);
-        // next P: the non-X part of the new Ritz vectors, orthogonalised against
-        // them and orthonormalised, all in the ns-dimensional coefficient space
-        std::vector<cd> Z((size_t)ns * m, 0.0);
-        for (int a = 0; a < ma; ++a)
-            for (int i = m; i < ns; ++i) Z[i + (size_t)a * ns] = Cfull[i + (size_t)act[a] * ns];
-        for (int pass = 0; pass < 2; ++pass) {
-            std::vector<cd> G((size_t)m * m, 0.0);  // C_x^H Z
-            for (int j = 0; j < ma; ++j)
-                for (int i = 0; i < m; ++i) {
-                    cd acc = 0.0;
-                    for (int k = 0; k < ns; ++k) acc += std::conj(Cfull[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
-                    G[i + (size_t)j * m] = acc;
-                }
-            for (int j = 0; j < ma; ++j)
-                for (int k = 0; k < ns; ++k) {
-                    cd acc = 0.0;
-                    for (int i = 0; i < m; ++i) acc += Cfull[k + (size_t)i * ns] * G[i + (size_t)j * m];
-                    Z[k + (size_t)j * ns] -= acc;
-                }
-        }
-        int mpn = 0;
-        std::vector<cd> U((size_t)ns * (2 * m), 0.0);  // [C_x | Z T]
-        for (int j = 0; j < m; ++j)
-            for (int i = 0; i < ns; ++i) U[i + (size_t)j * ns] = Cfull[i + (size_t)j * ns];
-        if (ns > m && ma > 0) {
-            std::vector<cd> G((size_t)ma * ma, 0.0), T;
-            for (int j = 0; j < ma; ++j)
-                for (int i = 0; i < ma; ++i) {
-                    cd acc = 0.0;
-                    for (int k = 0; k < ns; ++k) acc += std::conj(Z[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
-                    G[i + (size_t)j * ma] = acc;
-                }
-            double gmax = 0.0;
-            for (int j = 0; j < ma; ++j) gmax = std::max(gmax, G[j + (size_t)j * ma].real());
-            if (gmax > 1e-28) {
-                mpn = svqb(G, ma, T, 1e-12);
-                for (int j = 0; j < mpn; ++j)
-                    for (int i = 0; i < ns; ++i) {
-                        cd acc = 0.0;
-                        for (int k = 0; k < ma; ++k) acc += Z[i + (size_t)k * ns] * T[k + (size_t)j * ma];
-                        U[i + (size_t)(m + j) * ns] = acc;
-                    }
-            }
+            mpn = rr_coefficients(G, theta, m, ns, act, th, U);
         }
         // [X_new | P_new] = S U,  [HX_new | HP_new] = HS U
         {
@@ -804,6 +822,602 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     return status;
 }
 
+
+// ---------------------------------------------------------------------------
+// lock-step block LOBPCG for a batch of plans (e.g. a sweep of couplings):
+// every tall operation of one phase runs for all live instances in a single
+// launch (job tables), the applies go through one persistent batched launch
+// (replayed from a hipGraph), and the per-instance small problems run on
+// host threads.
+// ---------------------------------------------------------------------------
+
+template <class F>
+static void parallel_for(int n, F&& f) {
+    int nt = std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (int i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+struct BatchOps {
+    hipStream_t st = nullptr;
+    DeviceBuf d_jobs, d_coef, d_partial, d_out;
+    unsigned char* h_jobs = nullptr;
+    double2* h_coef = nullptr;
+    double2* h_out = nullptr;
+    size_t jobs_cap = 0, coef_cap = 0, partial_cap = 0, out_cap = 0;
+    hipEvent_t staged = nullptr;
+    ~BatchOps() {
+        if (staged) {
+            (void)hipEventSynchronize(staged);
+            (void)hipEventDestroy(staged);
+        }
+        dev_free(d_jobs);
+        dev_free(d_coef);
+        dev_free(d_partial);
+        dev_free(d_out);
+        if (h_jobs) (void)hipHostFree(h_jobs);
+        if (h_coef) (void)hipHostFree(h_coef);
+        if (h_out) (void)hipHostFree(h_out);
+    }
+    int reserve_host(void** h, size_t& cap, size_t need) {
+        if (need <= cap) return IWFPM_OK;
+        if (staged) (void)hipEventSynchronize(staged);
+        if (*h) (void)hipHostFree(*h);
+        *h = nullptr;
+        cap = 0;
+        if (hipHostMalloc(h, need) != hipSuccess) return IWFPM_ERR_ALLOC;
+        cap = need;
+        return IWFPM_OK;
+    }
+    int reserve_dev(DeviceBuf& b, size_t need) {
+        if (b.bytes >= need) return IWFPM_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
+        return dev_alloc(b, need);
+    }
+    // the host staging buffers may be rewritten once the last upload is done
+    int wait_staged() { return staged && hipEventSynchronize(staged) != hipSuccess ? IWFPM_ERR_DEVICE : IWFPM_OK; }
+};
+
+struct GramReq {
+    std::vector<double2*> L, R;
+    long long N;
+};
+
+// C_k = L_k^H R_k for every request, one launch (two with the reduction)
+static int batch_gram(BatchOps& bo, const std::vector<GramReq>& reqs, std::vector<std::vector<cd>>& out) {
+    struct Sub {
+        int req, i0, j0;
+    };
+    std::vector<GramJob> jobs;
+    std::vector<Sub> subs;
+    long long part = 0;
+    int blocks = 0, outs = 0;
+    size_t lds = 0;
+    for (int r = 0; r < (int)reqs.size(); ++r) {
+        const int p = (int)reqs[r].L.size(), q = (int)reqs[r].R.size();
+        for (int i0 = 0; i0 < p; i0 += kMaxCols)
+            for (int j0 = 0; j0 < q; j0 += kMaxCols) {
+                GramJob jb{};
+                jb.p = std::min(kMaxCols, p - i0);
+                jb.q = std::min(kMaxCols, q - j0);
+                for (int i = 0; i < jb.p; ++i) jb.L.p[i] = reqs[r].L[i0 + i];
+                for (int j = 0; j < jb.q; ++j) jb.R.p[j] = reqs[r].R[j0 + j];
+                jb.N = reqs[r].N;
+                size_t l = 0;
+                jb.nb = gram_job_blocks(jb.p, jb.q, jb.N, 256, &jb.rows_per_block, &jb.rows, &l);
+                lds = std::max(lds, l);
+                jb.start = blocks;
+                jb.out_start = outs;
+                jb.part_off = part;
+                blocks += jb.nb;
+                outs += jb.p * jb.q;
+                part += (long long)jb.nb * jb.p * jb.q;
+                jobs.push_back(jb);
+                subs.push_back({r, i0, j0});
+            }
+    }
+    out.assign(reqs.size(), {});
+    for (size_t r = 0; r < reqs.size(); ++r) out[r].assign(reqs[r].L.size() * reqs[r].R.size(), 0.0);
+    if (jobs.empty()) return IWFPM_OK;
+    int rc;
+    if ((rc = bo.wait_staged())) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(GramJob)))) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(GramJob)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
+    std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GramJob));
+    CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GramJob), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(gram_batched((const GramJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs, lds,
+                           (double2*)bo.d_partial.ptr, (double2*)bo.d_out.ptr, bo.st));
+    CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, (size_t)outs * sizeof(double2), hipMemcpyDeviceToHost, bo.st));
+    CHECK_HIP(hipStreamSynchronize(bo.st));
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        const GramJob& jb = jobs[k];
+        const Sub& sb = subs[k];
+        const int p = (int)reqs[sb.req].L.size();
+        for (int j = 0; j < jb.q; ++j)
+            for (int i = 0; i < jb.p; ++i) {
+                double2 v = bo.h_out[jb.out_start + (size_t)j * jb.p + i];
+                out[sb.req][(size_t)(sb.i0 + i) + (size_t)(sb.j0 + j) * p] = cd(v.x, v.y);
+            }
+    }
+    return IWFPM_OK;
+}
+
+struct LinReq {
+    std::vector<double2*> A, Y;
+    const std::vector<cd>* C;
+    int ldc, r0;
+    double beta;
+    long long N;
+};
+
+// Y_k = beta Y_k + A_k C_k for every request, one launch (inputs <= 64)
+static int batch_lincomb(BatchOps& bo, const std::vector<LinReq>& reqs) {
+    std::vector<LinJob> jobs;
+    std::vector<size_t> coef_off;
+    size_t coefs = 0;
+    int blocks = 0, maxq = 1;
+    for (const LinReq& r : reqs) {
+        const int p = (int)r.A.size(), q = (int)r.Y.size();
+        if (q == 0) continue;
+        if (p > kMaxCols) return IWFPM_ERR_ARG;
+        for (int j0 = 0; j0 < q; j0 += 48) {
+            LinJob jb{};
+            jb.p = p;
+            jb.q = std::min(48, q - j0);
+            for (int i = 0; i < p; ++i) jb.A.p[i] = r.A[i];
+            for (int j = 0; j < jb.q; ++j) jb.Y.p[j] = r.Y[j0 + j];
+            jb.beta = r.beta;
+            jb.N = r.N;
+            jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (r.N + 255) / 256));
+            jb.start = blocks;
+            blocks += jb.nb;
+            maxq = std::max(maxq, jb.q);
+            coef_off.push_back(coefs);
+            coefs += (size_t)p * jb.q;
+            jobs.push_back(jb);
+        }
+    }
+    if (jobs.empty()) return IWFPM_OK;
+    int rc;
+    if ((rc = bo.wait_staged())) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(LinJob)))) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_coef, bo.coef_cap, std::max<size_t>(1, coefs) * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(LinJob)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_coef, std::max<size_t>(1, coefs) * sizeof(double2)))) return rc;
+    size_t k = 0;
+    for (const LinReq& r : reqs) {
+        const int p = (int)r.A.size(), q = (int)r.Y.size();
+        if (q == 0) continue;
+        for (int j0 = 0; j0 < q; j0 += 48, ++k) {
+            LinJob& jb = jobs[k];
+            double2* h = bo.h_coef + coef_off[k];
+            for (int j = 0; j < jb.q; ++j)
+                for (int i = 0; i < p; ++i) {
+                    cd v = (*r.C)[(size_t)(r.r0 + i) + (size_t)(j0 + j) * r.ldc];
+                    h[(size_t)j * p + i] = make_double2(v.real(), v.imag());
+                }
+            jb.C = (const double2*)bo.d_coef.ptr + coef_off[k];
+        }
+    }
+    std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(LinJob));
+    CHECK_HIP(hipMemcpyAsync(bo.d_coef.ptr, bo.h_coef, coefs * sizeof(double2), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(LinJob), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(hipEventRecord(bo.staged, bo.st));
+    CHECK_HIP(lincomb_batched((const LinJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, maxq, bo.st));
+    return IWFPM_OK;
+}
+
+struct BInst {
+    iwfpm_plan_s* p = nullptr;
+    Solver* s = nullptr;
+    Ctx c{};
+    int prec = 0;
+    bool can64 = false;
+    bool done = false;
+    int status = IWFPM_OK;
+    std::vector<double> theta, eta;
+    int mp = 0, it = 0, polished = 0;
+    long long matvecs = 0;
+    double best_eta = 1e300, floor32 = 0.0, hnorm = 0.0;
+    int best_it = 0;
+    // per-iteration
+    bool active = false;
+    std::vector<int> act;
+    int ma = 0, mq = 0, mw = 0, ns = 0;
+    std::vector<cd> T, U;
+    std::vector<double> th;
+    int mpn = 0;
+};
+
+static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, double* evals, double* eta_out,
+                       iwfpm_stats* stats, hipStream_t st) {
+    const int nev = o.nev;
+    const int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
+    if (m < nev || 3 * m > kMaxCols) return IWFPM_ERR_ARG;
+    std::vector<BInst> in(B);
+    int rc;
+    for (int i = 0; i < B; ++i) {
+        BInst& b = in[i];
+        b.p = plans[i];
+        if (m > b.p->geom.N) return IWFPM_ERR_ARG;
+        if ((rc = solver_ensure(b.p, m))) return rc;
+        int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
+        if ((rc = solver_precond(b.p, pk))) return rc;
+        b.s = (Solver*)b.p->solver;
+        b.c = Ctx{b.p, b.s, st, b.p->geom.N};
+        b.prec = b.p->opts.precision;
+        if (!b.p->sched[b.prec].ok) b.prec = 1 - b.prec;
+        if (!b.p->sched[b.prec].ok) return IWFPM_ERR_UNSUPPORTED;
+        b.can64 = b.p->sched[0].ok;
+        b.hnorm = b.p->lam_max + b.p->vsum_abs;
+        b.floor32 = 30.0 * 6e-8 * b.p->vsum_abs / b.hnorm;
+        b.eta.assign(m, 1.0);
+    }
+    BatchOps bo;
+    bo.st = st;
+    CHECK_HIP(hipEventCreateWithFlags(&bo.staged, hipEventDisableTiming));
+    // batched applies, one batch object per convolution precision
+    std::vector<iwfpm_plan_t> pl(plans, plans + B);
+    iwfpm_batch_t bat[2] = {nullptr, nullptr};
+    struct BatchGuard {
+        iwfpm_batch_t* b;
+        ~BatchGuard() {
+            for (int k = 0; k < 2; ++k)
+                if (b[k]) iwfpm_batch_destroy(b[k]);
+        }
+    } bguard{bat};
+    for (int k = 0; k < 2; ++k) {
+        bool ok = true;
+        for (auto* p : pl) ok = ok && p->sched[k].ok;
+        if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
+            return rc;
+    }
+    // apply H to `cnt[i]` columns of buffer bin into bout for every instance, by precision
+    auto apply_all = [&](int bin, int bout, const std::vector<int>& cnt, const std::vector<int>& precs) -> int {
+        for (int k = 0; k < 2; ++k) {
+            std::vector<const void*> x(B, nullptr);
+            std::vector<void*> y(B, nullptr);
+            std::vector<int> nv(B, 0);
+            bool any = false;
+            for (int i = 0; i < B; ++i)
+                if (cnt[i] > 0 && precs[i] == k) {
+                    x[i] = in[i].c.col(bin, 0);
+                    y[i] = in[i].c.col(bout, 0);
+                    nv[i] = cnt[i];
+                    in[i].matvecs += cnt[i];
+                    any = true;
+                }
+            if (!any) continue;
+            if (!bat[k]) {
+                for (int i = 0; i < B; ++i)
+                    if (nv[i] && (rc = plan_apply(in[i].p, x[i], y[i], nv[i], k, st))) return rc;
+                continue;
+            }
+            if ((rc = iwfpm_batch_apply(bat[k], x.data(), y.data(), nv.data(), st))) return rc;
+        }
+        return IWFPM_OK;
+    };
+    // start blocks, orthonormalised
+    for (int i = 0; i < B; ++i) CHECK_HIP(randn(in[i].c.col(B_X, 0), in[i].c.N * m, o.seed + (unsigned long long)i, st));
+    {
+        std::vector<GramReq> g(B);
+        for (int i = 0; i < B; ++i) g[i] = {cols(in[i].c, B_X, 0, m), cols(in[i].c, B_X, 0, m), in[i].c.N};
+        std::vector<std::vector<cd>> G;
+        if ((rc = batch_gram(bo, g, G))) return rc;
+        std::vector<int> bad(B, 0);
+        parallel_for(B, [&](int i) { bad[i] = svqb(G[i], m, in[i].T) < m; });
+        for (int i = 0; i < B; ++i)
+            if (bad[i]) return IWFPM_ERR_NUMERIC;
+        std::vector<LinReq> l(B);
+        for (int i = 0; i < B; ++i) l[i] = {cols(in[i].c, B_X, 0, m), cols(in[i].c, B_XN, 0, m), &in[i].T, m, 0, 0.0, in[i].c.N};
+        if ((rc = batch_lincomb(bo, l))) return rc;
+        for (auto& b : in) std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
+    }
+    std::vector<int> all_m(B, m), precs(B);
+    for (int i = 0; i < B; ++i) precs[i] = in[i].prec;
+    if ((rc = apply_all(B_X, B_HX, all_m, precs))) return rc;
+    // Rayleigh-Ritz of the start blocks (and of blocks switched to float64 below)
+    auto rr_blocks = [&](const std::vector<int>& which) -> int {
+        if (which.empty()) return IWFPM_OK;
+        std::vector<GramReq> g;
+        for (int i : which) g.push_back({cols(in[i].c, B_X, 0, m), cols(in[i].c, B_HX, 0, m), in[i].c.N});
+        std::vector<std::vector<cd>> G;
+        if ((rc = batch_gram(bo, g, G))) return rc;
+        std::vector<std::vector<cd>> C(which.size());
+        parallel_for((int)which.size(), [&](int k) {
+            hermitian_part(G[k], m);
+            heev(G[k], m, in[which[k]].theta, C[k]);
+        });
+        std::vector<LinReq> l;
+        for (size_t k = 0; k < which.size(); ++k) {
+            BInst& b = in[which[k]];
+            l.push_back({cols(b.c, B_X, 0, m), cols(b.c, B_XN, 0, m), &C[k], m, 0, 0.0, b.c.N});
+            l.push_back({cols(b.c, B_HX, 0, m), cols(b.c, B_HXN, 0, m), &C[k], m, 0, 0.0, b.c.N});
+        }
+        if ((rc = batch_lincomb(bo, l))) return rc;
+        for (int i : which) {
+            std::swap(in[i].s->buf[B_X], in[i].s->buf[B_XN]);
+            std::swap(in[i].s->buf[B_HX], in[i].s->buf[B_HXN]);
+        }
+        return IWFPM_OK;
+    };
+    {
+        std::vector<int> allidx(B);
+        for (int i = 0; i < B; ++i) allidx[i] = i;
+        if ((rc = rr_blocks(allidx))) return rc;
+    }
+    for (;;) {
+        std::vector<int> live;
+        for (int i = 0; i < B; ++i)
+            if (!in[i].done) live.push_back(i);
+        if (live.empty()) break;
+        // residuals and their norms, one launch for all live instances
+        {
+            std::vector<ResJob> jobs;
+            int blocks = 0, outs = 0;
+            long long part = 0;
+            for (int i : live) {
+                BInst& b = in[i];
+                ResJob jb{};
+                for (int j = 0; j < m; ++j) {
+                    jb.HX.p[j] = b.c.col(B_HX, j);
+                    jb.X.p[j] = b.c.col(B_X, j);
+                    jb.R.p[j] = b.c.col(B_T1, j);
+                    jb.theta.v[j] = b.theta[j];
+                }
+                jb.m = m;
+                jb.N = b.c.N;
+                jb.nb = (int)std::min<long long>(256, std::max<long long>(1, (jb.N + 1023) / 1024));
+                jb.rows_per_block = (jb.N + jb.nb - 1) / jb.nb;
+                jb.start = blocks;
+                jb.out_start = outs;
+                jb.part_off = part;
+                blocks += jb.nb;
+                outs += m;
+                part += (long long)jb.nb * m;
+                jobs.push_back(jb);
+            }
+            if ((rc = bo.wait_staged())) return rc;
+            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(ResJob)))) return rc;
+            if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(ResJob)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
+            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(ResJob));
+            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
+            CHECK_HIP(residual_norm_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
+                                            (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, st));
+            CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, outs * sizeof(double), hipMemcpyDeviceToHost, st));
+            CHECK_HIP(hipStreamSynchronize(st));
+            const double* h = (const double*)bo.h_out;
+            for (size_t k = 0; k < live.size(); ++k) {
+                BInst& b = in[live[k]];
+                for (int j = 0; j < m; ++j) {
+                    b.eta[j] = std::sqrt(std::max(0.0, h[k * m + j])) / (b.hnorm + std::fabs(b.theta[j]));
+                    if (!std::isfinite(b.eta[j])) {
+                        b.done = true;
+                        b.status = IWFPM_ERR_NUMERIC;
+                    }
+                }
+            }
+        }
+        // per-instance decisions
+        std::vector<int> to64, iter;
+        for (int i : live) {
+            BInst& b = in[i];
+            if (b.done) continue;
+            int conv = 0;
+            double worst = 0.0;
+            for (int j = 0; j < nev; ++j) {
+                conv += b.eta[j] <= o.tol;
+                worst = std::max(worst, b.eta[j]);
+            }
+            if (conv == nev) {
+                if (b.prec == 0 || !b.can64) b.done = true;
+                else to64.push_back(i);  // confirm with float64 applies
+                continue;
+            }
+            if (b.it >= o.maxit) {
+                b.done = true;
+                b.status = IWFPM_ERR_NOCONV;
+                continue;
+            }
+            bool stalled = false;
+            if (worst < 0.5 * b.best_eta) {
+                b.best_eta = worst;
+                b.best_it = b.it;
+            } else {
+                stalled = worst < 1e-5 && b.it - b.best_it >= 20;
+            }
+            if (b.prec == 1 && o.polish && b.can64 && (worst < b.floor32 || stalled)) {
+                to64.push_back(i);
+                continue;
+            }
+            iter.push_back(i);
+        }
+        if (!to64.empty()) {
+            std::vector<int> cx(B, 0), cp(B, 0), p0(B, 0);
+            for (int i : to64) {
+                in[i].prec = 0;
+                in[i].best_eta = 1e300;
+                cx[i] = m;
+                cp[i] = in[i].mp;
+            }
+            if ((rc = apply_all(B_X, B_HX, cx, p0))) return rc;
+            if ((rc = apply_all(B_P, B_HP, cp, p0))) return rc;
+            if ((rc = rr_blocks(to64))) return rc;
+        }
+        if (iter.empty()) continue;
+        for (int i : iter) {
+            BInst& b = in[i];
+            ++b.it;
+            if (b.prec == 0 && b.p->opts.precision == 1) ++b.polished;
+            b.act.clear();
+            for (int j = 0; j < m; ++j)
+                if (b.eta[j] > o.tol) b.act.push_back(j);
+            b.ma = (int)b.act.size();
+            b.mq = b.mp;
+        }
+        // W = M R_A
+        {
+            std::vector<PreJob> jobs;
+            int blocks = 0;
+            for (int i : iter) {
+                BInst& b = in[i];
+                PreJob jb{};
+                for (int a = 0; a < b.ma; ++a) {
+                    jb.R.p[a] = b.c.col(B_T1, b.act[a]);
+                    jb.W.p[a] = b.c.col(B_W, a);
+                }
+                jb.m = b.ma;
+                jb.M = (const double*)b.s->M.ptr;
+                jb.N = b.c.N;
+                jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
+                jb.start = blocks;
+                blocks += jb.nb;
+                jobs.push_back(jb);
+            }
+            if ((rc = bo.wait_staged())) return rc;
+            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(PreJob)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(PreJob)))) return rc;
+            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(PreJob));
+            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(PreJob), hipMemcpyHostToDevice, st));
+            CHECK_HIP(hipEventRecord(bo.staged, st));
+            CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
+        }
+        // W <- W - [X P] ([X P]^H W), twice
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<GramReq> g;
+            std::vector<std::vector<double2*>> XP(iter.size());
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                XP[k] = cols(b.c, B_X, 0, m);
+                auto P = cols(b.c, B_P, 0, b.mq);
+                XP[k].insert(XP[k].end(), P.begin(), P.end());
+                g.push_back({XP[k], cols(b.c, B_W, 0, b.ma), b.c.N});
+            }
+            std::vector<std::vector<cd>> G;
+            if ((rc = batch_gram(bo, g, G))) return rc;
+            std::vector<LinReq> l;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                for (auto& v : G[k]) v = -v;
+                BInst& b = in[iter[k]];
+                l.push_back({XP[k], cols(b.c, B_W, 0, b.ma), &G[k], (int)XP[k].size(), 0, 1.0, b.c.N});
+            }
+            if ((rc = batch_lincomb(bo, l))) return rc;
+        }
+        // SVQB of W into T1
+        {
+            std::vector<GramReq> g;
+            for (int i : iter) g.push_back({cols(in[i].c, B_W, 0, in[i].ma), cols(in[i].c, B_W, 0, in[i].ma), in[i].c.N});
+            std::vector<std::vector<cd>> G;
+            if ((rc = batch_gram(bo, g, G))) return rc;
+            parallel_for((int)iter.size(), [&](int k) {
+                BInst& b = in[iter[k]];
+                b.mw = svqb(G[k], b.ma, b.T, 1e-10);
+            });
+            std::vector<LinReq> l;
+            for (int i : iter) {
+                BInst& b = in[i];
+                l.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
+            }
+            if ((rc = batch_lincomb(bo, l))) return rc;
+            for (int i : iter) std::swap(in[i].s->buf[B_W], in[i].s->buf[B_T1]);
+        }
+        // HW = H W
+        {
+            std::vector<int> cnt(B, 0), pr(B, 0);
+            for (int i : iter) {
+                cnt[i] = in[i].mw;
+                pr[i] = in[i].prec;
+            }
+            if ((rc = apply_all(B_W, B_HW, cnt, pr))) return rc;
+        }
+        // Rayleigh-Ritz: G = [X W P]^H [HW HP] for all, small problems on host threads
+        std::vector<std::vector<double2*>> S(iter.size()), HS(iter.size());
+        {
+            std::vector<GramReq> g;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                S[k] = cols(b.c, B_X, 0, m);
+                HS[k] = cols(b.c, B_HX, 0, m);
+                for (int j = 0; j < b.mw; ++j) {
+                    S[k].push_back(b.c.col(B_W, j));
+                    HS[k].push_back(b.c.col(B_HW, j));
+                }
+                for (int j = 0; j < b.mq; ++j) {
+                    S[k].push_back(b.c.col(B_P, j));
+                    HS[k].push_back(b.c.col(B_HP, j));
+                }
+                b.ns = (int)S[k].size();
+                g.push_back({S[k], std::vector<double2*>(HS[k].begin() + m, HS[k].end()), b.c.N});
+            }
+            std::vector<std::vector<cd>> G;
+            if ((rc = batch_gram(bo, g, G))) return rc;
+            parallel_for((int)iter.size(), [&](int k) {
+                BInst& b = in[iter[k]];
+                b.mpn = rr_coefficients(G[k], b.theta, m, b.ns, b.act, b.th, b.U);
+            });
+        }
+        // [X_new | P_new] = S U, [HX_new | HP_new] = HS U
+        {
+            std::vector<LinReq> l;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                std::vector<double2*> out = cols(b.c, B_XN, 0, m), hout = cols(b.c, B_HXN, 0, m);
+                for (int j = 0; j < b.mpn; ++j) {
+                    out.push_back(b.c.col(B_PN, j));
+                    hout.push_back(b.c.col(B_HPN, j));
+                }
+                l.push_back({S[k], out, &b.U, b.ns, 0, 0.0, b.c.N});
+                l.push_back({HS[k], hout, &b.U, b.ns, 0, 0.0, b.c.N});
+            }
+            if ((rc = batch_lincomb(bo, l))) return rc;
+            for (int i : iter) {
+                BInst& b = in[i];
+                std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
+                std::swap(b.s->buf[B_HX], b.s->buf[B_HXN]);
+                std::swap(b.s->buf[B_P], b.s->buf[B_PN]);
+                std::swap(b.s->buf[B_HP], b.s->buf[B_HPN]);
+                b.mp = b.mpn;
+                b.theta.assign(b.th.begin(), b.th.begin() + m);
+            }
+        }
+    }
+    CHECK_HIP(hipStreamSynchronize(st));
+    int worst_status = IWFPM_OK;
+    for (int i = 0; i < B; ++i) {
+        BInst& b = in[i];
+        for (int j = 0; j < nev; ++j) {
+            evals[(size_t)i * nev + j] = b.theta[j];
+            if (eta_out) eta_out[(size_t)i * nev + j] = b.eta[j];
+        }
+        if (stats) {
+            iwfpm_stats& s = stats[i];
+            s.iterations = b.it;
+            s.matvecs = b.matvecs;
+            s.polished = b.polished;
+            int conv = 0;
+            for (int j = 0; j < nev; ++j) conv += b.eta[j] <= o.tol;
+            s.converged = conv;
+        }
+        if (b.status != IWFPM_OK && worst_status == IWFPM_OK) worst_status = b.status;
+    }
+    return worst_status;
+}
 }  // namespace iwfpm
 
 using namespace iwfpm;
@@ -833,6 +1447,32 @@ int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, doub
     auto t0 = std::chrono::steady_clock::now();
     int rc = run(p, *opts, x0, evals, evecs, eta, stats, (hipStream_t)stream);
     if (stats) stats->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* opts, double* evals, double* eta,
+                       iwfpm_stats* stats, void* stream) {
+    if (B < 1 || !plans || !opts || !evals) return IWFPM_ERR_ARG;
+    if (opts->nev < 1 || !(opts->tol > 0.0) || opts->maxit < 0) return IWFPM_ERR_ARG;
+    if (opts->precond == IWFPM_PRECOND_LEARNED) return IWFPM_ERR_UNSUPPORTED;
+    int dev = -1;
+    for (int i = 0; i < B; ++i) {
+        if (!plans[i]) return IWFPM_ERR_ARG;
+        if (plans[i]->host_only) return IWFPM_ERR_NODEVICE;
+        if (dev < 0) dev = plans[i]->opts.device;
+        if (plans[i]->opts.device != dev) return IWFPM_ERR_ARG;
+        if (opts->nev > plans[i]->geom.N) return IWFPM_ERR_ARG;
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return IWFPM_ERR_ARG;
+    }
+    DeviceGuard guard(dev);
+    if (!guard.ok) return IWFPM_ERR_DEVICE;
+    if (stats) std::memset(stats, 0, sizeof(iwfpm_stats) * B);
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = run_batched(B, plans, *opts, evals, eta, stats, (hipStream_t)stream);
+    double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+        for (int i = 0; i < B; ++i) stats[i].t_total = t;
     return rc;
 }
 
