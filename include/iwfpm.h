@@ -142,6 +142,11 @@ int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* 
 int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
                      int precision, void* stream);
 
+/* The potential block alone, out = F V F^{-1} psi (Sec. 4.1), same arguments
+ * as iwfpm_apply_prec (used by the learned preconditioner's convolution
+ * layers). */
+int iwfpm_conv(iwfpm_plan_t plan, const void* psi, void* out, int nvec, int precision, void* stream);
+
 /*
  * Ragged batches: many plans (for example a sweep of couplings whose windows,
  * and so grid sizes, differ) applied together, Sec. 4.1's H~ psi per plan.
@@ -268,6 +273,119 @@ int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* 
  */
 int iwfpm_dense_geneig(int n, const double* A, const double* B, double* w, double* C);
 int iwfpm_dense_svqb(int k, const double* G, double* T, int* rank);
+
+/*
+ * Learned preconditioner.  The paper preconditions LOBPCG with the diagonal
+ * M of eq:precond (Sec. 4.1).  This adds a trained alternative that keeps M as
+ * its starting point and its fallback:
+ *     W = D0 .* R + b1 (C E + a)^H E (C E + a) R
+ *       = (D0 + b1 a^2 E) .* R + 2 a b1 E .* C(E .* R) + b1 E .* C(E .* C(E .* R)),
+ * with a = beta0 and b1 = max(beta1, 0), so that the two convolution layers
+ * add a positive semidefinite term and W stays Hermitian positive definite,
+ * with C = F V F^{-1} the potential block (the convolution of iwfpm_conv, run
+ * in the plan's precision), D0 = M .* (1 + exp(o0)) / 2 (never below M/2) and
+ * E = M .* exp(o1), where
+ * (o0, o1) are the outputs of an MLP (IWFPM_LEARNED_FEATURES inputs, 3 hidden
+ * layers of IWFPM_LEARNED_HIDDEN, exact GELU, 2 linear outputs) evaluated on
+ * each kinetic-energy shell of the plan.  Shell of grid point k:
+ *     s(k) = min(S - 1, floor(S sqrt(e_k / e_max))),  e_k = 1/2 |2 pi P k|^2,
+ * e_max = max e_k (s = 0 everywhere when e_max = 0).  Features of shell s,
+ * with c = (s + 1/2)/S, e = e_max c^2, nu = sum_{m != 0} |Vhat_m|,
+ * v0 = Re Vhat_0, sigma = max(0, nu - v0), S2 = sum_{m != 0} |Vhat_m|^2,
+ * h = e + v0 + sigma:
+ *     f0 = c, f1 = log(1 + e)/8, f2 = e/(e + nu), f3 = log(1 + nu)/4,
+ *     f4 = h^2/(h^2 + S2), f5 = nu/h, f6 = log(1 + e_max)/8,
+ *     f7 = sqrt(e)/(sqrt(e) + sqrt(nu))       (0/0 read as 0).
+ * Weight matrices are stored in bfloat16 (round to nearest even from the
+ * float32 masters) and multiplied with float32 accumulation; biases, beta and
+ * the optimiser state (Adam) are float32.  A new network reproduces M exactly
+ * (last layer zero, beta = 0).
+ *
+ * Parameter vector (float32, iwfpm_learned_nparams entries), in order: for
+ * layers l = 1..4 with (in, out) = (F, H), (H, H), (H, H), (H, 2): W_l
+ * (in x out, row-major, W[i*out + o]) then b_l (out); then beta0, beta1.
+ * (Where beta1 < 0 the gradient reported for it is that of its positive side.)
+ *
+ * Training loss of an iterate block X (m columns) given the exact lowest m
+ * eigenvalues lam: with (Y, theta) the Ritz pairs of span(X), R = H~ Y - Y theta
+ * and theta' the lowest m Ritz values of span([Y, W(R)]),
+ *     loss = sum_j (theta'_j - lam_j) / sum_j (theta_j - lam_j),
+ * the share of eigenvalue error left after one Rayleigh-Ritz step with the
+ * preconditioned residuals (0 = the step finds the eigenvalues, 1 = no gain).
+ * H~ is applied in float64 here (when the plan has a float64 schedule).
+ * iwfpm_learned_train takes its blocks from the method's own solves: a
+ * plain-preconditioned LOBPCG run per plan records the first nev columns of
+ * its iterate X every `stride` iterations, and its converged eigenvalues are
+ * lam (records whose columns had all converged are left out).
+ */
+#define IWFPM_LEARNED_FEATURES 8
+#define IWFPM_LEARNED_HIDDEN 256
+
+typedef struct iwfpm_learned_s* iwfpm_learned_t;
+
+typedef struct {
+    int device;         /* HIP device of the weights */
+    int shells;         /* S, kinetic-energy shells per plan, 1..65536 */
+    uint64_t seed;      /* initialisation of the hidden layers (uniform +-1/sqrt(fan_in)) */
+} iwfpm_learned_opts;
+
+typedef struct {
+    int steps;          /* Adam steps */
+    double lr;          /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+    int nev;            /* eigenpairs of the data-producing solves (columns per sample) */
+    int block;          /* their LOBPCG block size (0 = default) */
+    double tol;         /* their tolerance (backward error) */
+    int maxit;
+    int snapshots;      /* recorded iterates per plan, 1..64 */
+    int stride;         /* iterations between recorded iterates, >= 1 */
+    uint64_t seed;      /* sample order and the solves' start blocks */
+} iwfpm_train_opts;
+
+void iwfpm_default_learned_opts(iwfpm_learned_opts* opts);   /* device 0, 1024 shells */
+void iwfpm_default_train_opts(iwfpm_train_opts* opts);       /* 600 steps, lr 2e-3, nev 8, tol 1e-8,
+                                                                maxit 1000, 8 snapshots, stride 8 */
+
+/* Create / destroy a network.  Destroying a network detaches it from every
+ * plan it is attached to (their LEARNED solves then return ERR_WEIGHTS). */
+int iwfpm_learned_create(const iwfpm_learned_opts* opts, iwfpm_learned_t* out);
+int iwfpm_learned_destroy(iwfpm_learned_t net);
+int iwfpm_learned_nparams(iwfpm_learned_t net, int64_t* n);
+/* Copy the float32 parameters out / in (host arrays of nparams floats).
+ * set: ERR_WEIGHTS if any value is not finite (the network is unchanged);
+ * it also resets the optimiser state. */
+int iwfpm_learned_get(iwfpm_learned_t net, float* params);
+int iwfpm_learned_set(iwfpm_learned_t net, const float* params);
+
+/* Attach net to a plan (net = NULL detaches): builds the plan's shell map and
+ * features; iwfpm_eigs with IWFPM_PRECOND_LEARNED then uses it.  One network
+ * may serve many plans; the plan and the net must be on one device. */
+int iwfpm_learned_attach(iwfpm_plan_t plan, iwfpm_learned_t net);
+/* The attached plan's shell of each vector entry (host, N int32) and the
+ * shell features (host, S x IWFPM_LEARNED_FEATURES float32, row-major);
+ * either may be NULL. */
+int iwfpm_learned_shells(iwfpm_plan_t plan, int32_t* shell, float* features);
+
+/* T = W(R) for nvec columns (device blocks in the plan's vector layout). */
+int iwfpm_learned_forward(iwfpm_plan_t plan, const void* r, void* t, int nvec, void* stream);
+/* Training loss of the iterate block x (device, nvec columns, 2 nvec <= 64)
+ * with exact eigenvalues lam (host, nvec, ascending) in *loss and, if
+ * grad != NULL, its gradient with respect to the parameter vector (host,
+ * nparams floats; weight entries are derivatives at the bfloat16-rounded
+ * weights).  No update.  Blocking.  ERR_NUMERIC when the block carries no
+ * signal (dependent columns, or Ritz values already at lam). */
+int iwfpm_learned_grad(iwfpm_plan_t plan, const void* x, int nvec, const double* lam, double* loss, float* grad,
+                       void* stream);
+/* One Adam step (step size lr) of the attached network on (x, lam); the loss
+ * before the step in *loss.  A step whose loss or gradient is not finite, or
+ * whose block carries no signal, is skipped (ERR_NUMERIC).  Blocking. */
+int iwfpm_learned_step(iwfpm_plan_t plan, const void* x, int nvec, const double* lam, double lr, double* loss,
+                       void* stream);
+/* Train net on data from B plans (see above); the net is attached to each
+ * plan.  loss: host, opts->steps entries or NULL.  Blocking.
+ * Errors: ERR_ARG, ERR_ALLOC, ERR_DEVICE, the solves' errors (ERR_NOCONV is
+ * tolerated), ERR_NUMERIC when no usable sample was recorded. */
+int iwfpm_learned_train(iwfpm_learned_t net, int B, const iwfpm_plan_t* plans, const iwfpm_train_opts* opts,
+                        double* loss, void* stream);
 
 #ifdef __cplusplus
 }

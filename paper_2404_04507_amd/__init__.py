@@ -17,7 +17,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Plan", "IwfpmError", "load_library", "library_path", "EXPORTED"]
+__all__ = ["Plan", "Learned", "IwfpmError", "load_library", "library_path", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -26,7 +26,16 @@ EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_de
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
             "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
             "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb", "iwfpm_tune", "iwfpm_schedule",
-            "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy", "iwfpm_eigs_batched"]
+            "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy", "iwfpm_eigs_batched",
+            "iwfpm_conv", "iwfpm_default_learned_opts", "iwfpm_default_train_opts", "iwfpm_learned_create",
+            "iwfpm_learned_destroy", "iwfpm_learned_nparams", "iwfpm_learned_get", "iwfpm_learned_set",
+            "iwfpm_learned_attach", "iwfpm_learned_shells", "iwfpm_learned_forward", "iwfpm_learned_grad",
+            "iwfpm_learned_step", "iwfpm_learned_train"]
+
+_VOID_FUNCS = ("iwfpm_default_opts", "iwfpm_status_string", "iwfpm_default_eigs_opts",
+               "iwfpm_default_learned_opts", "iwfpm_default_train_opts")
+LEARNED_FEATURES = 8
+LEARNED_HIDDEN = 256
 
 PREC = {"fp64": 0, "fp32": 1}
 WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
@@ -52,6 +61,16 @@ class _EigsOpts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("precond", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("polish", ctypes.c_int)]
+
+
+class _LearnedOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("shells", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("lr", ctypes.c_double), ("nev", ctypes.c_int), ("block", ctypes.c_int),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("snapshots", ctypes.c_int),
+                ("stride", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
 class _Stats(ctypes.Structure):
@@ -103,8 +122,25 @@ def load_library():
     lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
     lib.iwfpm_default_eigs_opts.restype = None
     lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
+    lib.iwfpm_conv.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.iwfpm_default_learned_opts.argtypes = [ctypes.POINTER(_LearnedOpts)]
+    lib.iwfpm_default_learned_opts.restype = None
+    lib.iwfpm_default_train_opts.argtypes = [ctypes.POINTER(_TrainOpts)]
+    lib.iwfpm_default_train_opts.restype = None
+    lib.iwfpm_learned_create.argtypes = [ctypes.POINTER(_LearnedOpts), ctypes.POINTER(vp)]
+    lib.iwfpm_learned_destroy.argtypes = [vp]
+    lib.iwfpm_learned_nparams.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.iwfpm_learned_get.argtypes = [vp, fp]
+    lib.iwfpm_learned_set.argtypes = [vp, fp]
+    lib.iwfpm_learned_attach.argtypes = [vp, vp]
+    lib.iwfpm_learned_shells.argtypes = [vp, ip, fp]
+    lib.iwfpm_learned_forward.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.iwfpm_learned_grad.argtypes = [vp, vp, ctypes.c_int, dp, dp, fp, vp]
+    lib.iwfpm_learned_step.argtypes = [vp, vp, ctypes.c_int, dp, ctypes.c_double, dp, vp]
+    lib.iwfpm_learned_train.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(_TrainOpts), dp, vp]
     for name in EXPORTED:
-        if name not in ("iwfpm_default_opts", "iwfpm_status_string", "iwfpm_default_eigs_opts"):
+        if name not in _VOID_FUNCS:
             getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -240,6 +276,89 @@ class EigsResult:
     status: int
 
 
+class Learned:
+    """The learned preconditioner's network (wraps iwfpm_learned_t)."""
+
+    def __init__(self, shells=1024, seed=2404045070, device=0):
+        lib = _lib()
+        o = _LearnedOpts()
+        lib.iwfpm_default_learned_opts(ctypes.byref(o))
+        o.device, o.shells, o.seed = int(device), int(shells), int(seed)
+        h = ctypes.c_void_p()
+        _check(lib.iwfpm_learned_create(ctypes.byref(o), ctypes.byref(h)), "iwfpm_learned_create")
+        self._h = h
+        self.shells = int(shells)
+        self.device = int(device)
+        n = ctypes.c_int64()
+        _check(lib.iwfpm_learned_nparams(h, ctypes.byref(n)), "iwfpm_learned_nparams")
+        self.nparams = int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().iwfpm_learned_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(_lib().iwfpm_learned_get(self._h, _ptr(out, ctypes.c_float)), "iwfpm_learned_get")
+        return out
+
+    def set(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if a.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {a.size}")
+        _check(_lib().iwfpm_learned_set(self._h, _ptr(a, ctypes.c_float)), "iwfpm_learned_set")
+
+    def layout(self) -> list:
+        """[(name, offset, shape)] of the parameter vector."""
+        dims = [LEARNED_FEATURES, LEARNED_HIDDEN, LEARNED_HIDDEN, LEARNED_HIDDEN, 2]
+        out, off = [], 0
+        for l in range(4):
+            out.append((f"W{l + 1}", off, (dims[l], dims[l + 1])))
+            off += dims[l] * dims[l + 1]
+            out.append((f"b{l + 1}", off, (dims[l + 1],)))
+            off += dims[l + 1]
+        out.append(("beta", off, (2,)))
+        return out
+
+    def save(self, path: str):
+        np.savez(path, params=self.get(), shells=np.int64(self.shells))
+
+    def load(self, path: str):
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["shells"]) != self.shells:
+                raise ValueError("shell count of the saved network differs")
+            self.set(z["params"])
+
+    def train(self, plans, steps=600, lr=2e-3, nev=8, block=0, tol=1e-8, maxit=1000, snapshots=8, stride=8,
+              seed=2404045070, stream=None) -> np.ndarray:
+        """Train on data from plain solves of `plans` (iwfpm_learned_train); returns the loss per step."""
+        lib = _lib()
+        o = _TrainOpts()
+        lib.iwfpm_default_train_opts(ctypes.byref(o))
+        o.steps, o.lr, o.nev, o.block, o.tol = int(steps), float(lr), int(nev), int(block), float(tol)
+        o.maxit, o.snapshots, o.stride, o.seed = int(maxit), int(snapshots), int(stride), int(seed)
+        arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+        loss = np.zeros(max(1, steps))
+        _check(lib.iwfpm_learned_train(self._h, len(plans), arr, ctypes.byref(o), _ptr(loss, ctypes.c_double),
+                                       _stream_handle(stream)), "iwfpm_learned_train")
+        for p in plans:
+            p._net = self
+        return loss[:steps]
+
+
 class Plan:
     """An IWFPM plan (wraps iwfpm_plan_t).
 
@@ -341,6 +460,64 @@ class Plan:
                                      nvec, prec, _stream_handle(stream))
         _check(st, "iwfpm_apply")
         return out
+
+    def conv(self, psi, out=None, precision=None, stream=None):
+        """The potential block alone, F V F^{-1} psi (iwfpm_conv)."""
+        import torch
+        nvec = self._check_block(psi)
+        if out is None:
+            out = torch.empty_like(psi)
+        else:
+            self._check_block(out)
+        prec = PREC[precision] if precision is not None else PREC[self.precision]
+        st = _lib().iwfpm_conv(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               nvec, prec, _stream_handle(stream))
+        _check(st, "iwfpm_conv")
+        return out
+
+    # -- learned preconditioner ----------------------------------------------
+    def attach(self, net):
+        """Attach a Learned network (None detaches)."""
+        _check(_lib().iwfpm_learned_attach(self._h, net._h if net is not None else None), "iwfpm_learned_attach")
+        self._net = net
+
+    def learned_shells(self, shells: int):
+        """(shell index per vector entry, S x features) of the attached network."""
+        sh = np.zeros(self.N, dtype=np.int32)
+        ft = np.zeros((shells, LEARNED_FEATURES), dtype=np.float32)
+        _check(_lib().iwfpm_learned_shells(self._h, _ptr(sh, ctypes.c_int32), _ptr(ft, ctypes.c_float)),
+               "iwfpm_learned_shells")
+        return sh, ft
+
+    def learned_forward(self, r, out=None, stream=None):
+        import torch
+        nvec = self._check_block(r)
+        if out is None:
+            out = torch.empty_like(r)
+        _check(_lib().iwfpm_learned_forward(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            nvec, _stream_handle(stream)), "iwfpm_learned_forward")
+        return out
+
+    def learned_grad(self, x, lam, want_grad=True, stream=None):
+        """(loss, gradient over the parameter vector or None) of the attached
+        network on the iterate block x with exact eigenvalues lam."""
+        nvec = self._check_block(x)
+        lam = _f64(lam)
+        loss = ctypes.c_double()
+        g = np.zeros(self._net.nparams, dtype=np.float32) if want_grad else None
+        _check(_lib().iwfpm_learned_grad(self._h, ctypes.c_void_p(x.data_ptr()), nvec, _ptr(lam, ctypes.c_double),
+                                         ctypes.byref(loss), _ptr(g, ctypes.c_float) if g is not None else None,
+                                         _stream_handle(stream)), "iwfpm_learned_grad")
+        return loss.value, g
+
+    def learned_step(self, x, lam, lr=2e-3, stream=None) -> float:
+        nvec = self._check_block(x)
+        lam = _f64(lam)
+        loss = ctypes.c_double()
+        _check(_lib().iwfpm_learned_step(self._h, ctypes.c_void_p(x.data_ptr()), nvec, _ptr(lam, ctypes.c_double),
+                                         float(lr), ctypes.byref(loss), _stream_handle(stream)),
+               "iwfpm_learned_step")
+        return loss.value
 
     def tune(self, nvec=16, precision=None, stream=None) -> float:
         """Autotune the apply schedule on the device; returns the best microseconds per apply."""

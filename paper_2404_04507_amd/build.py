@@ -34,7 +34,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", f"-
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 HOST_SOURCES = ["plan.cpp", "batch.cpp", "lobpcg.cpp", "learned.cpp"]
-DEVICE_SOURCES = ["blas_kernels.hip"]
+DEVICE_SOURCES = ["blas_kernels.hip", "learned_kernels.hip"]
 APPLY_TUS = [(k, r, m) for k in range(5) for r in ("float", "double") for m in (16, 32, 64)]
 
 

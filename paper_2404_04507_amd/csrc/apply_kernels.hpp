@@ -397,7 +397,7 @@ __device__ __forceinline__ void kinetic_scatter(const DevGeom& g, const DevTabs&
         for (int u = 0; u < kBatch; ++u) {
             if (j.e < count) {
                 lam[u] = row_kinetic(g, tab, j.row, j.col, &vpos[u]);
-                xv[u] = x[vpos[u]];
+                xv[u] = g.kin ? x[vpos[u]] : make_double2(0.0, 0.0);
             }
             j.next(nt);
         }

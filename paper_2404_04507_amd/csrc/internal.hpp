@@ -13,6 +13,7 @@ struct DevGeom {
     int n, d;
     int order;                      // 0 grid order, 1 window order
     int vmode;                      // 0 per-axis potential tables, 1 potential grid
+    int kin;                        // 1: add the kinetic term, 0: potential block only
     int ext[kMaxAxes];              // extents 2L..., 2K...
     int stride[kMaxAxes];           // row-major element strides
     int N;                          // grid points per vector (< 2^31)

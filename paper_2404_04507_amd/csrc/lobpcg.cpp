@@ -255,13 +255,13 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
 }
 
 // Hermitian eigensolver used throughout: Householder + QL, Jacobi as fallback
-static void heev(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) {
+void heev(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) {
     if (!householder_ql(A, n, w, V)) jacobi_eigh(A, n, w, V);
 }
 
 // SVQB: T (k x r) with (B T)^H (B T) = I for the Gram matrix G = B^H B (k x k);
 // directions whose scaled eigenvalue is below eps are dropped.  Returns r.
-static int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps = 1e-12) {
+int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps) {
     std::vector<double> dsc(k);
     for (int i = 0; i < k; ++i) {
         double g = G[i + i * k].real();
@@ -396,27 +396,31 @@ static int solver_ensure(iwfpm_plan_s* p, int m) {
 }
 
 // diagonal of eq:precond for H~ + sigma I (closed form for non-aliasing modes)
+void precond_diagonal(const iwfpm_plan_s* p, std::vector<double>& M) {
+    const long long N = p->geom.N;
+    M.assign(N, 1.0);
+    double sigma = std::max(0.0, p->vsum_nonzero - p->vhat0);
+    double S = 0.0;
+    const int n = p->n;
+    for (size_t i = 0; i < p->vre.size(); ++i) {
+        bool zero = true;
+        for (int j = 0; j < n; ++j) zero = zero && p->modes[i * n + j] == 0;
+        if (!zero) S += p->vre[i] * p->vre[i] + p->vim[i] * p->vim[i];
+    }
+    std::vector<int> k(n);
+    for (long long gp = 0; gp < N; ++gp) {
+        host_label(p, gp, k.data());
+        double h = host_kinetic(p, k.data()) + p->vhat0 + sigma;
+        M[host_grid_to_vec(p, gp)] = h / (h * h + S);
+    }
+}
+
 static int solver_precond(iwfpm_plan_s* p, int kind) {
     Solver* s = (Solver*)p->solver;
     if (s->Mkind == kind && s->M.ptr) return IWFPM_OK;
     const long long N = p->geom.N;
     std::vector<double> M(N, 1.0);
-    if (kind == IWFPM_PRECOND_PLAIN) {
-        double sigma = std::max(0.0, p->vsum_nonzero - p->vhat0);
-        double S = 0.0;
-        const int n = p->n;
-        for (size_t i = 0; i < p->vre.size(); ++i) {
-            bool zero = true;
-            for (int j = 0; j < n; ++j) zero = zero && p->modes[i * n + j] == 0;
-            if (!zero) S += p->vre[i] * p->vre[i] + p->vim[i] * p->vim[i];
-        }
-        std::vector<int> k(n);
-        for (long long gp = 0; gp < N; ++gp) {
-            host_label(p, gp, k.data());
-            double h = host_kinetic(p, k.data()) + p->vhat0 + sigma;
-            M[host_grid_to_vec(p, gp)] = h / (h * h + S);
-        }
-    }
+    if (kind == IWFPM_PRECOND_PLAIN) precond_diagonal(p, M);
     if (dev_alloc(s->M, N * sizeof(double)) != IWFPM_OK) return IWFPM_ERR_ALLOC;
     if (hipMemcpy(s->M.ptr, M.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return IWFPM_ERR_DEVICE;
@@ -609,7 +613,7 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
 }
 
 static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
-               iwfpm_stats* stats, hipStream_t st) {
+               iwfpm_stats* stats, hipStream_t st, Capture* cap = nullptr) {
     const int nev = o.nev;
     int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
     if (m < nev || m > 32) return IWFPM_ERR_ARG;
@@ -681,6 +685,15 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
                 if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
             }
         }
+        if (cap && it > 0 && it % cap->stride == 0 && it != cap->last_it && cap->got < (int)cap->X.size()) {
+            const size_t bytes = (size_t)N * cap->ncol * sizeof(double2);
+            CHECK_HIP(hipMemcpyAsync(cap->X[cap->got], c.col(B_X, 0), bytes, hipMemcpyDeviceToDevice, st));
+            if (!cap->R.empty())
+                CHECK_HIP(hipMemcpyAsync(cap->R[cap->got], c.col(B_T1, 0), bytes, hipMemcpyDeviceToDevice, st));
+            cap->eta.emplace_back(eta.begin(), eta.begin() + cap->ncol);
+            cap->last_it = it;
+            ++cap->got;
+        }
         int conv = 0;
         double worst = 0.0;
         for (int j = 0; j < nev; ++j) {
@@ -711,6 +724,12 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             best_it = it;
         } else {
             stalled = worst < 1e-5 && it - best_it >= 20;
+        }
+        if (lp && it - best_it >= 50) {
+            // learned preconditioner stagnating: continue with M
+            fallback = 1;
+            lp = nullptr;
+            best_it = it;
         }
         if (prec == 1 && o.polish && can64 && (worst < floor32 || stalled)) {
             prec = 0;
@@ -744,6 +763,18 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
                 }
             }
             if (!used_learned) CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
+            if (used_learned) {
+                // a non-finite learned direction falls back to M for the rest of the solve
+                std::vector<cd> G;
+                if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
+                bool finite = true;
+                for (int j = 0; j < ma; ++j) finite = finite && std::isfinite(G[j + (size_t)j * ma].real());
+                if (!finite) {
+                    fallback = 1;
+                    lp = nullptr;
+                    CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
+                }
+            }
         }
         // P: built last iteration from the then-active Ritz vectors only,
         // orthonormal and orthogonal to X
@@ -822,6 +853,12 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     return status;
 }
 
+
+int eigs_capture(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, Capture* cap, double* evals, void* evecs,
+                 hipStream_t st) {
+    if (o.nev < 1 || o.nev > p->geom.N || !cap || cap->ncol > o.nev) return IWFPM_ERR_ARG;
+    return run(p, o, nullptr, evals, evecs, nullptr, nullptr, st, cap);
+}
 
 // ---------------------------------------------------------------------------
 // lock-step block LOBPCG for a batch of plans (e.g. a sweep of couplings):

@@ -158,6 +158,7 @@ static int build_geometry(iwfpm_plan_s* p) {
     g.n = n;
     g.d = d;
     g.order = p->opts.order;
+    g.kin = 1;
     for (int ax = 0; ax < n; ++ax) {
         int e = ax < n - d ? 2 * p->L[ax] : 2 * p->K[ax - (n - d)];
         g.ext[ax] = e;
@@ -603,7 +604,7 @@ int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st) {
     return IWFPM_OK;
 }
 
-int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st) {
+int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st, int kinetic) {
     if (nvec == 0) return IWFPM_OK;
     const int prec = precision == IWFPM_PREC_FP32 ? 1 : 0;
     const Schedule& sc = p->sched[prec];
@@ -624,10 +625,12 @@ int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int preci
     double2* y = reinterpret_cast<double2*>(hpsi);
     for (int v0 = 0; v0 < nvec; v0 += chunk) {
         int nv = std::min(chunk, nvec - v0);
-        hipError_t e = prec ? launch_sched<float>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                  p->d_ws.ptr, nv, st, &p->prof)
-                            : launch_sched<double>(sc, p->geom, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                   p->d_ws.ptr, nv, st, &p->prof);
+        DevGeom g = p->geom;
+        g.kin = kinetic ? 1 : 0;
+        hipError_t e = prec ? launch_sched<float>(sc, g, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
+                                                  p->d_ws.ptr, nv, st, kinetic ? &p->prof : nullptr)
+                            : launch_sched<double>(sc, g, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
+                                                   p->d_ws.ptr, nv, st, kinetic ? &p->prof : nullptr);
         if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     }
     return IWFPM_OK;
@@ -800,6 +803,21 @@ int iwfpm_apply_prec(iwfpm_plan_t p, const void* psi, void* hpsi, int nvec, int 
     DeviceGuard guard(p->opts.device);
     if (!guard.ok) return IWFPM_ERR_DEVICE;
     return plan_apply(p, psi, hpsi, nvec, precision, (hipStream_t)stream);
+}
+
+int iwfpm_conv(iwfpm_plan_t p, const void* psi, void* out, int nvec, int precision, void* stream) {
+    if (!p || nvec < 0) return IWFPM_ERR_ARG;
+    if (precision != IWFPM_PREC_FP64 && precision != IWFPM_PREC_FP32) return IWFPM_ERR_ARG;
+    if (nvec > 0 && (!psi || !out)) return IWFPM_ERR_ARG;
+    if (p->host_only) return IWFPM_ERR_NODEVICE;
+    if (nvec == 0) return IWFPM_OK;
+    const char* a = (const char*)psi;
+    const char* b = (const char*)out;
+    size_t bytes = (size_t)nvec * (size_t)p->geom.N * 16;
+    if (a < b + bytes && b < a + bytes) return IWFPM_ERR_ARG;
+    DeviceGuard guard(p->opts.device);
+    if (!guard.ok) return IWFPM_ERR_DEVICE;
+    return plan_apply(p, psi, out, nvec, precision, (hipStream_t)stream, 0);
 }
 
 int iwfpm_profile(iwfpm_plan_t p, int enable) {

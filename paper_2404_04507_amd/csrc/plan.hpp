@@ -102,7 +102,7 @@ int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st);
 int extent_class_of(int e);
 
 // apply on a plan (precision 0 = float64 convolution, 1 = float32)
-int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st);
+int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st, int kinetic = 1);
 
 // grid position -> true label k (paper order) and vector position
 void host_label(const iwfpm_plan_s* p, long long gpos, int* k_out);

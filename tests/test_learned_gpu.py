@@ -1,0 +1,229 @@
+"""Learned preconditioner on the GPU against its CPU reference (oracle/learned_oracle.py).
+
+* the potential-only convolution plus the kinetic diagonal is the apply;
+* shell map (exact) and features (float32 rounding) match the reference;
+* a fresh network is exactly eq:precond's M;
+* forward output, the training loss and its full parameter gradient for random
+  networks match the float64 reference evaluated with the same
+  bfloat16-rounded weights;
+* Adam steps lower the loss; training on the method's own solves works; the
+  eigenvalues of LEARNED solves equal the plain solves'; corrupted weights
+  fall back to M; a destroyed network is refused.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import oracle.learned_oracle as LO
+import paper_2404_04507_amd as lib
+from paper_2404_04507_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(X, dtype=np.complex128).T)).to(DEV)
+
+
+def to_host(T):
+    return T.cpu().numpy().T
+
+
+def reference_parts(prob, S):
+    H = O.hamiltonian_sparse(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat)
+    kin = O.kinetic(prob.P, O.grid_labels(prob.P, prob.d, prob.K, prob.L))
+    nu, v0, S2 = LO.potential_scalars(prob.modes, prob.vhat)
+    sigma = max(0.0, nu - v0)
+    M = O.preconditioner_sparse(H + sigma * sp.identity(H.shape[0]))
+    C = LO.potential_block(H, kin)
+    shell, amb = LO.shell_map(kin, S)
+    X = LO.shell_features(S, float(kin.max()), nu, v0, S2)
+    return H, kin, C, M, shell, amb, X
+
+
+def random_params(seed, scale_last=0.3, beta=(-0.4, 0.6)):
+    p = LO.init_params(seed, zero_last=False)
+    lay, off_beta = LO.layout()
+    ow, shp, ob, nb = lay[3]
+    p[ow:ow + shp[0] * shp[1]] *= scale_last
+    p[ob:ob + nb] = [0.1, -0.2]
+    p[off_beta:off_beta + 2] = beta
+    return p.astype(np.float32)
+
+
+PROBLEMS = {
+    "1d_lifted_2d": lambda: W.c1_1d(lam=1.0, K=8, L=16),
+    "2d_lifted_4d_small": lambda: W.c2_2d(lam=2.0, K=4, L=4),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(PROBLEMS))
+def case(request):
+    prob = PROBLEMS[request.param]()
+    S = 64
+    net = lib.Learned(shells=S, seed=11)
+    plan = lib.Plan.from_problem(prob, precision="fp64")
+    plan.attach(net)
+    H, kin, C, M, shell, amb, X = reference_parts(prob, S)
+    # entries whose S sqrt(e/e_max) is an integer up to rounding (labels that are
+    # rational multiples of the maximum-energy label) may sit in either adjacent
+    # shell: check the library's choice is one of the two, then share it
+    lib_shell, _ = plan.learned_shells(S)
+    x = S * np.sqrt(kin / kin.max())
+    ok = (lib_shell == np.minimum(np.round(x), S - 1)) | (lib_shell == np.round(x) - 1)
+    assert ok[amb].all()
+    shell = np.where(amb, lib_shell, shell)
+    yield prob, plan, net, S, (H, kin, C, M, shell, amb, X)
+    plan.close()
+    net.close()
+
+
+def test_conv_plus_kinetic_is_apply(case):
+    prob, plan, net, S, ref = case
+    X = W.random_block(plan.N, 3, seed=5)
+    x = to_dev(X)
+    y = plan.apply(x)
+    c = plan.conv(x)
+    kin = torch.from_numpy(plan.kinetic()).to(DEV)
+    err = (c + kin[None, :] * x - y).abs().max().item()
+    assert err <= 1e-13 * y.abs().max().item()
+    H, kin_ref, C, *_ = ref
+    assert np.max(np.abs(to_host(c) - C @ X)) <= 1e-12 * np.max(np.abs(C @ X))
+
+
+def test_shells_and_features_match_reference(case):
+    prob, plan, net, S, ref = case
+    H, kin, C, M, shell, amb, X = ref
+    sh, ft = plan.learned_shells(S)
+    bad = (sh != shell) & ~amb
+    assert not bad.any(), np.flatnonzero(bad)[:10]
+    assert np.allclose(ft, X, rtol=1e-6, atol=1e-7)
+
+
+def test_fresh_network_is_plain_preconditioner(case):
+    prob, plan, net, S, ref = case
+    H, kin, C, M, shell, amb, X = ref
+    net.set(LO.init_params(3))  # last layer and beta zero
+    R = W.random_block(plan.N, 4, seed=8)
+    T = to_host(plan.learned_forward(to_dev(R)))
+    assert np.max(np.abs(T - M[:, None] * R)) <= 1e-13 * np.max(np.abs(M[:, None] * R))
+
+
+def test_forward_matches_reference(case):
+    prob, plan, net, S, ref = case
+    H, kin, C, M, shell, amb, X = ref
+    p = random_params(21)
+    net.set(p)
+    layers, beta = LO.unpack(p, round_weights=True)
+    Oout, _ = LO.mlp_forward(layers, X)
+    R = W.random_block(plan.N, 5, seed=9)
+    T_ref, _, _ = LO.precond_apply(C, M, shell, Oout, beta, R)
+    T = to_host(plan.learned_forward(to_dev(R)))
+    rel = np.linalg.norm(T - T_ref) / np.linalg.norm(T_ref)
+    # float32 MLP activations: o carries ~1e-6 absolute error, so D0 and E ~1e-6 relative
+    assert rel <= 2e-5, rel
+
+
+def iterate_block(H, m=4, noise=0.05, seed=13):
+    """Exact lowest eigenvectors (scipy) plus noise: an iterate block and its eigenvalues."""
+    w, V = spla.eigsh(H, k=m, which="SA", tol=1e-12)
+    order = np.argsort(w)
+    w, V = w[order], V[:, order]
+    rng = np.random.default_rng(seed)
+    X = V + noise * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape)) / np.sqrt(V.shape[0])
+    return X, w
+
+
+def test_gradient_matches_reference(case):
+    prob, plan, net, S, ref = case
+    H, kin, C, M, shell, amb, X = ref
+    p = random_params(33, beta=(0.35, 0.45))
+    net.set(p)
+    Xb, lam = iterate_block(H)
+    L_ref, g_ref = LO.rr_loss_and_grad(p, H, C, M, shell, X, Xb, lam, round_weights=True)
+    L, g = plan.learned_grad(to_dev(Xb), lam)
+    assert 0.0 < L_ref < 1.0
+    assert abs(L - L_ref) <= 1e-5 * abs(L_ref), (L, L_ref)
+    g = g.astype(np.float64)
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
+    assert rel <= 2e-3 and cos >= 0.99999, (rel, cos)
+    lay, off_beta = LO.layout()
+    assert np.allclose(g[off_beta:], g_ref[off_beta:], rtol=1e-3, atol=0)
+
+
+def test_adam_steps_lower_the_loss(case):
+    prob, plan, net, S, ref = case
+    H, kin, C, M, shell, amb, X = ref
+    net.set(LO.init_params(4))
+    Xb, lam = iterate_block(H, noise=0.2, seed=3)
+    x = to_dev(Xb)
+    first = plan.learned_step(x, lam, lr=5e-3)
+    for _ in range(30):
+        last = plan.learned_step(x, lam, lr=5e-3)
+    assert last < first, (first, last)
+
+
+def test_save_and_load_roundtrip(case, tmp_path):
+    prob, plan, net, S, ref = case
+    p = random_params(44)
+    net.set(p)
+    f = str(tmp_path / "net.npz")
+    net.save(f)
+    other = lib.Learned(shells=S, seed=99)
+    other.load(f)
+    assert np.array_equal(other.get(), p)
+    other.close()
+    with pytest.raises(lib.IwfpmError):
+        bad = p.copy()
+        bad[5] = np.nan
+        net.set(bad)
+
+
+def test_train_then_learned_solve_matches_plain():
+    train = [lib.Plan.from_problem(W.c2_2d(lam=lam, K=4, L=4), precision="fp32") for lam in (0.8, 3.0, 6.0)]
+    net = lib.Learned(shells=128, seed=5)
+    loss = net.train(train, steps=120, lr=2e-3, nev=8, tol=1e-8, snapshots=6, stride=4)
+    assert np.all(np.isfinite(loss))
+    k = len(loss) // 4
+    assert np.mean(loss[-k:]) < np.mean(loss[:k]), (loss[:k].mean(), loss[-k:].mean())
+    prob = W.c2_2d(lam=4.5, K=4, L=4)
+    with lib.Plan.from_problem(prob, precision="fp32") as plan:
+        plain = plan.eigs(8, tol=1e-8, want_vectors=False)
+        plan.attach(net)
+        learned = plan.eigs(8, tol=1e-8, precond="learned", want_vectors=False)
+    hn = O.norm_bound(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat)
+    assert np.max(np.abs(learned.evals - plain.evals)) <= 1e-7 * hn
+    assert np.all(learned.eta <= 1e-8)
+    print(f"held-out lam 4.5: plain {plain.iterations} its, learned {learned.iterations} its "
+          f"(fallback {learned.fallback})")
+    for p in train:
+        p.close()
+    net.close()
+
+
+def test_overflowing_weights_fall_back_to_plain():
+    prob = W.c1_1d(lam=1.0, K=8, L=16)
+    net = lib.Learned(shells=32, seed=1)
+    p = LO.init_params(2)
+    lay, _ = LO.layout()
+    p[lay[3][2]] = 1000.0  # o0 = 1000 everywhere: D0 = M exp(1000) overflows
+    net.set(p)
+    with lib.Plan.from_problem(prob) as plan:
+        plain = plan.eigs(8, tol=1e-10, want_vectors=False)
+        plan.attach(net)
+        res = plan.eigs(8, tol=1e-10, precond="learned", want_vectors=False)
+        assert res.fallback == 1
+        assert np.max(np.abs(res.evals - plain.evals)) <= 1e-9
+        net.close()
+        with pytest.raises(lib.IwfpmError) as ei:
+            plan.eigs(8, tol=1e-10, precond="learned", want_vectors=False)
+        assert ei.value.status == -9
