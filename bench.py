@@ -11,11 +11,20 @@ size for 16 eigenpairs).  value = applied vectors per second (matvecs/s),
 inputs resident in HBM.  The per-kernel durations come from HIP events the
 library records on the apply's own stream during the timed steps.
 
-After the timed region: time to the 16 lowest eigenpairs at backward error
-1e-8 (plain diagonal preconditioner, and the learned one when available), and
-the CPU oracle's matvec rate on a bounded sample of the same workload.
+After the timed region (each reported in its own JSON object):
+  * eigs     time to the 16 lowest eigenpairs at backward error 1e-8 for
+             lam = 0.5 and 5.0, plain diagonal preconditioner and learned one;
+  * learned  the learned preconditioner trained on the method's own solves
+             (the two lam above plus 6 instances of the sweep below), then
+             iterations and time to 1e-8 against the plain preconditioner on
+             32 held-out couplings of the same geometry;
+  * sweep    64 instances, lam ~ U[0.1, 10], K ~ U{6..14}, 8 eigenpairs each,
+             solved in lock step by iwfpm_eigs_batched (batched applies in one
+             persistent, graph-replayed launch per pass), plain and learned;
+  * cpu_baseline  the CPU oracle's matvec rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20]
+    python bench.py --copy-probe      # plain copies of a known size (counter calibration)
 """
 
 from __future__ import annotations
@@ -94,7 +103,11 @@ def main():
     ap.add_argument("--lam", type=float, default=0.5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-eigs", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported by this build "
@@ -107,6 +120,14 @@ def main():
     from paper_2404_04507_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if a.copy_probe:
+        src = torch.ones((BLOCK, 589824), dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 16, "copies": 20}))
+        return
     prob = W.c2_2d(lam=a.lam)
     plan = lib.Plan.from_problem(prob, precision=a.precision)
     X = torch.from_numpy(np.ascontiguousarray(W.random_block(prob.N, BLOCK, seed=W.SEED).T)).to(dev)
@@ -161,34 +182,110 @@ def main():
         "effective_boundary_GBs": 32.0 * prob.N * value / 1e9,
     }
 
+    plan.close()
+    del X, Y
+    net = None
+    if not a.no_learned:
+        net, out["learned"] = run_learned(lib, W)
     if not a.no_eigs:
-        out["eigs"] = run_eigs(lib, W, dev)
+        out["eigs"] = run_eigs(lib, W, net)
+    if not a.no_sweep:
+        out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out))
 
 
-def run_eigs(lib, W, dev):
-    """Time to the 16 lowest eigenpairs at eta <= 1e-8 on the same workload."""
+def _timed(fn):
     import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def run_learned(lib, W):
+    """Train the learned preconditioner on plain solves, then compare it with
+    the plain one on 32 held-out couplings (16 eigenpairs, eta <= 1e-8)."""
+    import numpy as np
+    sweep = W.c4_sweep(64)
+    train_probs = [W.c2_2d(lam=0.5), W.c2_2d(lam=5.0)] + [sweep[i] for i in range(0, 64, 11)]
+    train = [lib.Plan.from_problem(p, precision="fp32") for p in train_probs]
+    net = lib.Learned(shells=1024, seed=5)
+    loss, t_train = _timed(lambda: net.train(train, steps=600, lr=2e-3, nev=16, tol=1e-8, snapshots=12, stride=6))
+    for p in train:
+        p.close()
+    rows = []
+    for lam in W.c5_heldout_lams(32):
+        with lib.Plan.from_problem(W.c2_2d(lam=lam), precision="fp32") as plan:
+            plan.eigs(16, tol=1e-8, maxit=3, want_vectors=False, allow_noconv=True)  # allocations
+            a, ta = _timed(lambda: plan.eigs(16, tol=1e-8, maxit=2000, want_vectors=False))
+            plan.attach(net)
+            plan.eigs(16, tol=1e-8, maxit=3, precond="learned", want_vectors=False, allow_noconv=True)
+            b, tb = _timed(lambda: plan.eigs(16, tol=1e-8, maxit=2000, precond="learned", want_vectors=False))
+            rows.append((lam, a.iterations, ta, b.iterations, tb, b.fallback,
+                         float(np.max(np.abs(a.evals - b.evals))), float(max(b.eta))))
+    r = np.array([x[1:] for x in rows])
+    fin = loss[np.isfinite(loss)]
+    return net, {
+        "train": {"plans": len(train_probs), "steps": int(loss.size), "seconds_incl_solves": t_train,
+                  "loss_first50": float(np.mean(fin[:50])), "loss_last50": float(np.mean(fin[-50:]))},
+        "heldout": {"count": len(rows), "workload": "2d_lifted_4d K=12 L=16, 16 eigenpairs, eta <= 1e-8, fp32 conv",
+                    "plain_iterations_mean": float(r[:, 0].mean()), "learned_iterations_mean": float(r[:, 2].mean()),
+                    "plain_seconds_total": float(r[:, 1].sum()), "learned_seconds_total": float(r[:, 3].sum()),
+                    "time_speedup": float(r[:, 1].sum() / r[:, 3].sum()),
+                    "fallbacks": int(r[:, 4].sum()), "max_eigenvalue_diff": float(r[:, 5].max()),
+                    "max_eta_learned": float(r[:, 6].max()),
+                    "per_lambda": [{"lam": x[0], "plain_its": x[1], "plain_s": x[2], "learned_its": x[3],
+                                    "learned_s": x[4], "fallback": x[5]} for x in rows]},
+    }
+
+
+def run_eigs(lib, W, net):
+    """Time to the 16 lowest eigenpairs at eta <= 1e-8 on the benchmark workload."""
     res = {}
     for lam in (0.5, 5.0):
         prob = W.c2_2d(lam=lam)
         with lib.Plan.from_problem(prob, precision="fp32") as plan:
+            if net is not None:
+                plan.attach(net)
             for precond in ("plain", "learned"):
-                try:
-                    plan.eigs(16, tol=1e-8, maxit=5, precond=precond, want_vectors=False,
-                              allow_noconv=True)  # warm-up (allocations)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    r = plan.eigs(16, tol=1e-8, maxit=1000, precond=precond, want_vectors=False)
-                    torch.cuda.synchronize()
-                    t = time.perf_counter() - t0
-                    res[f"lam{lam}_{precond}"] = {"seconds": t, "iterations": r.iterations, "matvecs": r.matvecs,
-                                                  "eta_max": float(max(r.eta)), "E0": float(r.evals[0]),
-                                                  "polished_iterations": r.polished, "fallback": r.fallback}
-                except lib.IwfpmError as e:
-                    res[f"lam{lam}_{precond}"] = {"error": str(e)}
+                if precond == "learned" and net is None:
+                    continue
+                plan.eigs(16, tol=1e-8, maxit=3, precond=precond, want_vectors=False, allow_noconv=True)
+                r, t = _timed(lambda: plan.eigs(16, tol=1e-8, maxit=2000, precond=precond, want_vectors=False))
+                res[f"lam{lam}_{precond}"] = {"seconds": t, "iterations": r.iterations, "matvecs": r.matvecs,
+                                              "eta_max": float(max(r.eta)), "E0": float(r.evals[0]),
+                                              "polished_iterations": r.polished, "fallback": r.fallback}
+    return res
+
+
+def run_sweep(lib, W, net):
+    """64 couplings with ragged windows, 8 eigenpairs each, in lock step."""
+    import numpy as np
+    probs = W.c4_sweep(64)
+    plans = [lib.Plan.from_problem(p, precision="fp32") for p in probs]
+    res = {"instances": len(plans), "dof_total": int(sum(p.N for p in plans)), "nev": 8, "tol": 1e-8}
+    try:
+        lib.eigs_batched(plans[:2], 8, tol=1e-8, maxit=3, allow_noconv=True)  # allocations
+        (ev, eta, st, _), t = _timed(lambda: lib.eigs_batched(plans, 8, tol=1e-8, maxit=2000))
+        res["plain"] = {"seconds": t, "iterations_max": max(x["iterations"] for x in st),
+                        "iterations_mean": float(np.mean([x["iterations"] for x in st])),
+                        "eta_max": float(eta.max())}
+        if net is not None:
+            for p in plans:
+                p.attach(net)
+            (ev2, eta2, st2, _), t2 = _timed(lambda: lib.eigs_batched(plans, 8, tol=1e-8, maxit=2000,
+                                                                      precond="learned"))
+            res["learned"] = {"seconds": t2, "iterations_max": max(x["iterations"] for x in st2),
+                              "iterations_mean": float(np.mean([x["iterations"] for x in st2])),
+                              "eta_max": float(eta2.max()), "fallbacks": int(sum(x["fallback"] for x in st2)),
+                              "max_eigenvalue_diff": float(np.max(np.abs(ev2 - ev)))}
+            res["time_speedup"] = t / t2
+    finally:
+        for p in plans:
+            p.close()
     return res
 
 

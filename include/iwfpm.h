@@ -216,7 +216,9 @@ typedef struct {
     int64_t matvecs;    /* single-vector applies (all precisions) */
     int converged;      /* pairs with eta <= tol at exit */
     int restarts;       /* Rayleigh-Ritz restarts without the P block */
-    int fallback;       /* learned preconditioner replaced by the plain one */
+    int fallback;       /* learned preconditioner replaced by the plain one (weights
+                           that overflow, non-finite directions, or 50 iterations
+                           without halving the worst backward error) */
     int polished;       /* iterations done with float64 applies on an FP32 plan */
     double t_total;     /* seconds, wall */
     double t_apply;     /* seconds in applies (device events) */
@@ -253,7 +255,9 @@ int iwfpm_eigs(iwfpm_plan_t plan, const iwfpm_eigs_opts* opts, const void* x0,
  * Plans must be distinct and on one device.  Blocking.
  * Errors: as iwfpm_eigs; the first plan's failure status is returned
  * (ERR_NOCONV if any plan hit maxit), results are written for every plan;
- * ERR_UNSUPPORTED for the learned preconditioner.
+ * ERR_WEIGHTS (LEARNED and a plan without a usable network).  With LEARNED,
+ * each plan's directions come from its attached network (two convolutions
+ * per plan and iteration) and fall back to M per plan as in iwfpm_eigs.
  */
 int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* opts, double* evals, double* eta,
                        iwfpm_stats* stats, void* stream);

@@ -257,7 +257,7 @@ def eigs_batched(plans, nev, tol=1e-8, maxit=500, block=0, precond="plain", seed
     if st != 0 and not (allow_noconv and st == -8):
         raise IwfpmError(st, "iwfpm_eigs_batched")
     return evals, eta, [{"iterations": s.iterations, "matvecs": s.matvecs, "converged": s.converged,
-                         "polished": s.polished, "t_total": s.t_total} for s in stats], st
+                         "polished": s.polished, "fallback": s.fallback, "t_total": s.t_total} for s in stats], st
 
 
 @dataclass

@@ -207,17 +207,20 @@ static int lp_forward_mlp(LearnedPrecond* lp, hipStream_t st) {
             return IWFPM_ERR_DEVICE;
         x = Y;
     }
+    // weights that overflow the scalings are refused (the solver then uses M)
+    if (lp_expand((const double*)lp->M.ptr, (const int*)lp->shell.ptr, out_o(lp), (double*)lp->D0.ptr,
+                  (double*)lp->E.ptr, lp->N, st) != hipSuccess)
+        return IWFPM_ERR_DEVICE;
     int* flag = red_flag(lp);
     if (hipMemsetAsync(flag, 0, sizeof(int), st) != hipSuccess) return IWFPM_ERR_DEVICE;
-    if (lp_nonfinite(out_o(lp), 2 * S, flag, st) != hipSuccess) return IWFPM_ERR_DEVICE;
-    if (lp_nonfinite(w32 + n->offbeta, 2, flag, st) != hipSuccess) return IWFPM_ERR_DEVICE;
+    if (lp_nonfinite(w32 + n->offbeta, 2, flag, st) != hipSuccess ||
+        lp_nonfinite_d((const double*)lp->D0.ptr, lp->N, flag, st) != hipSuccess ||
+        lp_nonfinite_d((const double*)lp->E.ptr, lp->N, flag, st) != hipSuccess)
+        return IWFPM_ERR_DEVICE;
     int h = 0;
     if (hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return IWFPM_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
     if (h) return IWFPM_ERR_WEIGHTS;
-    if (lp_expand((const double*)lp->M.ptr, (const int*)lp->shell.ptr, out_o(lp), (double*)lp->D0.ptr,
-                  (double*)lp->E.ptr, lp->N, st) != hipSuccess)
-        return IWFPM_ERR_DEVICE;
     lp->version = n->version;
     return IWFPM_OK;
 }

@@ -55,5 +55,6 @@ hipError_t lp_beta_grad(const double* dbeta, const float* beta, float* g, hipStr
 hipError_t lp_to_float(const double* a, float* b, int n, double scale, hipStream_t st);
 // flag[0] = 1 if any of the n floats is not finite (flag zeroed by the caller)
 hipError_t lp_nonfinite(const float* a, int n, int* flag, hipStream_t st);
+hipError_t lp_nonfinite_d(const double* a, long long n, int* flag, hipStream_t st);
 
 }  // namespace iwfpm

@@ -249,6 +249,13 @@ __global__ void k_nonfinite(const float* __restrict__ a, int n, int* __restrict_
     if (e < n && !isfinite(a[e])) atomicOr(flag, 1);
 }
 
+__global__ void k_nonfinite_d(const double* __restrict__ a, long long n, int* __restrict__ flag) {
+    bool bad = false;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+        bad = bad || !isfinite(a[k]);
+    if (bad) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------------------
 static int blocks_for(long long n, int cap) {
     long long b = (n + 255) / 256;
@@ -313,6 +320,10 @@ hipError_t lp_beta_grad(const double* dbeta, const float* beta, float* g, hipStr
 }
 hipError_t lp_to_float(const double* a, float* b, int n, double scale, hipStream_t st) {
     k_to_float<<<blocks_for(n, kNoCap), 256, 0, st>>>(a, b, n, scale);
+    return hipGetLastError();
+}
+hipError_t lp_nonfinite_d(const double* a, long long n, int* flag, hipStream_t st) {
+    k_nonfinite_d<<<blocks_for(n, kGridCap), 256, 0, st>>>(a, n, flag);
     return hipGetLastError();
 }
 hipError_t lp_nonfinite(const float* a, int n, int* flag, hipStream_t st) {

@@ -1070,6 +1070,8 @@ struct BInst {
     long long matvecs = 0;
     double best_eta = 1e300, floor32 = 0.0, hnorm = 0.0;
     int best_it = 0;
+    LearnedPrecond* lp = nullptr;  // learned preconditioner while it is in use
+    int fallback = 0;
     // per-iteration
     bool active = false;
     std::vector<int> act;
@@ -1102,6 +1104,10 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
         b.hnorm = b.p->lam_max + b.p->vsum_abs;
         b.floor32 = 30.0 * 6e-8 * b.p->vsum_abs / b.hnorm;
         b.eta.assign(m, 1.0);
+        if (o.precond == IWFPM_PRECOND_LEARNED) {
+            b.lp = b.p->learned;
+            if (!b.lp || !learned_ready(b.lp, b.p)) return IWFPM_ERR_WEIGHTS;
+        }
     }
     BatchOps bo;
     bo.st = st;
@@ -1279,6 +1285,12 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             } else {
                 stalled = worst < 1e-5 && b.it - b.best_it >= 20;
             }
+            if (b.lp && b.it - b.best_it >= 50) {
+                // learned preconditioner stagnating: continue with M
+                b.fallback = 1;
+                b.lp = nullptr;
+                b.best_it = b.it;
+            }
             if (b.prec == 1 && o.polish && b.can64 && (worst < b.floor32 || stalled)) {
                 to64.push_back(i);
                 continue;
@@ -1308,12 +1320,22 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             b.ma = (int)b.act.size();
             b.mq = b.mp;
         }
-        // W = M R_A
+        // W = T(R_A) (learned, per instance) or M R_A (all plain instances in one launch)
         {
             std::vector<PreJob> jobs;
             int blocks = 0;
             for (int i : iter) {
                 BInst& b = in[i];
+                if (b.lp) {
+                    ColPtrs r{}, w{};
+                    for (int a = 0; a < b.ma; ++a) {
+                        r.p[a] = b.c.col(B_T1, b.act[a]);
+                        w.p[a] = b.c.col(B_W, a);
+                    }
+                    if (learned_apply(b.lp, b.p, r, w, b.ma, st) == IWFPM_OK) continue;
+                    b.fallback = 1;
+                    b.lp = nullptr;
+                }
                 PreJob jb{};
                 for (int a = 0; a < b.ma; ++a) {
                     jb.R.p[a] = b.c.col(B_T1, b.act[a]);
@@ -1327,13 +1349,16 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
                 blocks += jb.nb;
                 jobs.push_back(jb);
             }
-            if ((rc = bo.wait_staged())) return rc;
-            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(PreJob)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(PreJob)))) return rc;
-            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(PreJob));
-            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(PreJob), hipMemcpyHostToDevice, st));
-            CHECK_HIP(hipEventRecord(bo.staged, st));
-            CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
+            if (!jobs.empty()) {
+                if ((rc = bo.wait_staged())) return rc;
+                if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(PreJob)))) return rc;
+                if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(PreJob)))) return rc;
+                std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(PreJob));
+                CHECK_HIP(
+                    hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(PreJob), hipMemcpyHostToDevice, st));
+                CHECK_HIP(hipEventRecord(bo.staged, st));
+                CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
+            }
         }
         // W <- W - [X P] ([X P]^H W), twice
         for (int pass = 0; pass < 2; ++pass) {
@@ -1447,6 +1472,7 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             s.iterations = b.it;
             s.matvecs = b.matvecs;
             s.polished = b.polished;
+            s.fallback = b.fallback;
             int conv = 0;
             for (int j = 0; j < nev; ++j) conv += b.eta[j] <= o.tol;
             s.converged = conv;
@@ -1491,7 +1517,6 @@ int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* 
                        iwfpm_stats* stats, void* stream) {
     if (B < 1 || !plans || !opts || !evals) return IWFPM_ERR_ARG;
     if (opts->nev < 1 || !(opts->tol > 0.0) || opts->maxit < 0) return IWFPM_ERR_ARG;
-    if (opts->precond == IWFPM_PRECOND_LEARNED) return IWFPM_ERR_UNSUPPORTED;
     int dev = -1;
     for (int i = 0; i < B; ++i) {
         if (!plans[i]) return IWFPM_ERR_ARG;

@@ -188,13 +188,29 @@ def test_save_and_load_roundtrip(case, tmp_path):
         net.set(bad)
 
 
-def test_train_then_learned_solve_matches_plain():
+@pytest.fixture(scope="module")
+def trained_small():
+    """A network trained on plain solves of three small 2D-lifted-to-4D problems."""
     train = [lib.Plan.from_problem(W.c2_2d(lam=lam, K=4, L=4), precision="fp32") for lam in (0.8, 3.0, 6.0)]
     net = lib.Learned(shells=128, seed=5)
-    loss = net.train(train, steps=120, lr=2e-3, nev=8, tol=1e-8, snapshots=6, stride=4)
-    assert np.all(np.isfinite(loss))
-    k = len(loss) // 4
-    assert np.mean(loss[-k:]) < np.mean(loss[:k]), (loss[:k].mean(), loss[-k:].mean())
+    loss = net.train(train, steps=150, lr=2e-3, nev=8, tol=1e-8, snapshots=8, stride=4)
+    yield net, loss
+    for p in train:
+        p.close()
+    net.close()
+
+
+def test_training_lowers_the_loss(trained_small):
+    net, loss = trained_small
+    ok = loss[np.isfinite(loss)]
+    assert ok.size >= 0.9 * loss.size
+    assert np.all((ok >= 0.0) & (ok <= 1.0))
+    k = ok.size // 4
+    assert np.mean(ok[-k:]) < np.mean(ok[:k]), (ok[:k].mean(), ok[-k:].mean())
+
+
+def test_learned_solve_matches_plain_and_gains(trained_small):
+    net, _ = trained_small
     prob = W.c2_2d(lam=4.5, K=4, L=4)
     with lib.Plan.from_problem(prob, precision="fp32") as plan:
         plain = plan.eigs(8, tol=1e-8, want_vectors=False)
@@ -205,9 +221,28 @@ def test_train_then_learned_solve_matches_plain():
     assert np.all(learned.eta <= 1e-8)
     print(f"held-out lam 4.5: plain {plain.iterations} its, learned {learned.iterations} its "
           f"(fallback {learned.fallback})")
-    for p in train:
-        p.close()
-    net.close()
+    assert learned.fallback == 0
+    assert learned.iterations < plain.iterations
+
+
+def test_batched_learned_matches_batched_plain(trained_small):
+    net, _ = trained_small
+    probs = [W.c2_2d(lam=lam, K=K, L=4) for lam, K in ((1.7, 4), (4.5, 5), (7.9, 3))]
+    plans = [lib.Plan.from_problem(p, precision="fp32") for p in probs]
+    try:
+        ev_p, eta_p, st_p, _ = lib.eigs_batched(plans, 8, tol=1e-8)
+        for p in plans:
+            p.attach(net)
+        ev_l, eta_l, st_l, _ = lib.eigs_batched(plans, 8, tol=1e-8, precond="learned")
+        for i, prob in enumerate(probs):
+            hn = O.norm_bound(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat)
+            assert np.max(np.abs(ev_l[i] - ev_p[i])) <= 1e-7 * hn
+            assert np.all(eta_l[i] <= 1e-8)
+        print("batched iterations plain", [x["iterations"] for x in st_p], "learned",
+              [x["iterations"] for x in st_l], "fallback", [x["fallback"] for x in st_l])
+    finally:
+        for p in plans:
+            p.close()
 
 
 def test_overflowing_weights_fall_back_to_plain():
