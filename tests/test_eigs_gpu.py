@@ -97,9 +97,12 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("L,printed", [(20, 5.64e-08), (40, 2.11e-11)])
+@pytest.mark.parametrize("L,printed", [(20, 5.64e-08)])
 def test_table2_on_gpu(L, printed):
-    """Table 2 end to end on the GPU: IWFPM K = 5 reaches the printed E_v."""
+    """Table 2 end to end on the GPU: IWFPM K = 5 reaches the printed E_v.
+    (The L = 40 row needs a 2L = 80-point axis, above this build's 64-point
+    limit; iwfpm_plan refuses it, see tests/test_host_plan.py, and the row is
+    pinned on the oracle in tests/test_oracle_pins.py.)"""
     e0s = _golden("ex1_reference.json")["E0"]
     prob = W.paper_example_1d(2.5, 5, L)
     print(f"case: Table 2 K=5 L={L}", flush=True)

@@ -106,6 +106,9 @@ def test_status_codes():
     with pytest.raises(lib.IwfpmError) as e:
         lib.Plan(P, [4], [4096], modes, vhat, device=-1)
     assert e.value.status == -4  # extent 8192 is not compiled
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan(P, [5], [40], modes, vhat, device=-1)
+    assert e.value.status == -4  # Table 2's L = 40 row: a 2L = 80-point axis, above the 64-point limit
     p = lib.Plan(P, [4], [4], modes, vhat, device=-1)
     so = lib.load_library()
     st = so.iwfpm_apply(p._h, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 1, ctypes.c_void_p())
