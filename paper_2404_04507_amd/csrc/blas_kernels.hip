@@ -4,9 +4,11 @@
 // vector; kernels take lists of column pointers so that any subset of the
 // X / W / P blocks can be combined without copies.
 //
-//   gram      C = L^H R            tall-skinny (p, q <= 64), two-stage
-//                                  deterministic reduction
-//   lincomb   Y = beta Y + A C     (p <= 64 inputs, q <= 32 outputs per call)
+//   gram      C = L^H R            tall-skinny (p, q <= 64), wide ones on the
+//                                  matrix cores; two-stage deterministic
+//                                  reduction
+//   lincomb   Y = beta Y + A C     (p <= 64 inputs, q <= 48 outputs per call);
+//                                  outputs beyond 32 on the matrix cores
 //   residual  R_j = HX_j - theta_j X_j
 //   colnorm2  ||R_j||^2           two-stage deterministic reduction
 //   precond   W_j = M .* R_j       diagonal preconditioner (eq:precond)
@@ -23,15 +25,13 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// gram: partial[b][j*p + i] = sum over the rows of block b of conj(L_i[r]) R_j[r]
-//
-// The p x q output is cut into 4 x 4 tiles; with ntile tiles, the 256 threads
-// form 256 / ntile row groups, each summing its own subset of the staged rows
-// for its tile, so that small Grams still keep every thread busy.  Rows are
-// staged through LDS `rows` at a time (as many as fit); at the end the row
-// groups are summed in a fixed order (deterministic).
+// gram for small blocks (p + q < 48, and every batched call): the p x q output
+// is cut into 4 x 4 tiles; with ntile tiles, the 256 threads form 256 / ntile
+// row groups, each summing its own subset of the staged rows for its tile.
+// Rows are staged through LDS `rows` at a time; the row groups are summed in a
+// fixed order at the end (deterministic).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
+__device__ __forceinline__ void gram_vec_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
                                           long long rows_per_block, int rows, double2* __restrict__ partial, int bid,
                                           unsigned char* smem) {
     const int pl = p | 1, pr = q | 1;  // odd pitches
@@ -109,10 +109,116 @@ __device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs
     }
 }
 
+// ---------------------------------------------------------------------------
+// gram for wide blocks: partial[b][j*p + i] = sum over the rows of block b of
+// conj(L_i[r]) R_j[r], on the matrix cores (v_mfma_f64_16x16x4f64).  With the K index running over
+// (row, re/im) pairs, Re C = sum_k Lx[k][i] Rx[k][j] and Im C = sum_k Lx[k][i]
+// Ry[k][j], where Lx, Rx hold (re, im) of each row and Ry holds (im, -re): two
+// real 16x16x4 products per 16x16 complex output tile and K step of two rows,
+// sharing the A operand.  Lane l of a wave holds A[l%16][l/16], B[l/16][l%16]
+// and result v in D[l/16 + 4v][l%16], so each lane ends with whole complex
+// entries.  Rows are staged through LDS kGramRows at a time (odd pitches);
+// the 4 wavefronts split the output tiles.  Reduction over blocks as before.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kGramRows = 24;   // rows staged per chunk (12 K steps)
+constexpr int kGramTilesPerWave = 4;
+constexpr int kGramBatch = 6;   // staging loads in flight per thread
+
+// stage kGramRows rows of the columns of X (zero beyond nr rows and p columns)
+// into s[row * pitch + column]; each thread issues kGramBatch loads before its
+// first LDS store, so a chunk costs a few memory round trips, not one per entry
+__device__ __forceinline__ void stage_rows(const ColPtrs& X, int p, int pitch, long long rb, int nr,
+                                           double2* __restrict__ s, int tid) {
+    const int total = kGramRows * (pitch - 1);
+    for (int e0 = 0; e0 < total; e0 += kGramBatch * 256) {
+        double2 v[kGramBatch];
+#pragma unroll
+        for (int u = 0; u < kGramBatch; ++u) {
+            const int e = e0 + tid + u * 256;
+            const int c = e / kGramRows, rr = e - c * kGramRows;
+            v[u] = (e < total && rr < nr && c < p) ? X.p[c][rb + rr] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGramBatch; ++u) {
+            const int e = e0 + tid + u * 256;
+            const int c = e / kGramRows, rr = e - c * kGramRows;
+            if (e < total) s[rr * pitch + c] = v[u];
+        }
+    }
+}
+
+__device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
+                                          long long rows_per_block, double2* __restrict__ partial, int bid,
+                                          unsigned char* smem) {
+    const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4, ntile = TP * TQ;
+    const int pl = 16 * TP + 1, pr = 16 * TQ + 1;  // odd pitches (complex entries)
+    double2* sL = reinterpret_cast<double2*>(smem);
+    double2* sR = sL + kGramRows * pl;
+    const double* dL = reinterpret_cast<const double*>(sL);
+    const double* dR = reinterpret_cast<const double*>(sR);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;  // A row / B column, and K index 0..3
+    const int half = lk >> 1, part = lk & 1;   // staged row within the K step, re/im
+    dbl4 accr[kGramTilesPerWave], acci[kGramTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kGramTilesPerWave; ++t) {
+        accr[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acci[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    const long long r0 = (long long)bid * rows_per_block;
+    const long long r1 = min(N, r0 + rows_per_block);
+    for (long long rb = r0; rb < r1; rb += kGramRows) {
+        const int nr = (int)min((long long)kGramRows, r1 - rb);
+        stage_rows(L, p, pl, rb, nr, sL, tid);
+        stage_rows(R, q, pr, rb, nr, sR, tid);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kGramTilesPerWave; ++t) {
+            const int tile = wave + 4 * t;
+            if (tile < ntile) {  // uniform across the wave
+                const int ti = tile % TP, tj = tile / TP;
+#pragma unroll 4
+                for (int ks = 0; ks < kGramRows / 2; ++ks) {
+                    const int row = 2 * ks + half;
+                    const double a = dL[2 * (row * pl + 16 * ti + li) + part];
+                    const double2 rv = sR[row * pr + 16 * tj + li];
+                    const double br = part ? rv.y : rv.x;
+                    const double bi = part ? -rv.x : rv.y;
+                    accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, accr[t], 0, 0, 0);
+                    acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, acci[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    (void)dR;
+    double2* out = partial + (size_t)bid * p * q;
+#pragma unroll
+    for (int t = 0; t < kGramTilesPerWave; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile < ntile) {
+            const int ti = tile % TP, tj = tile / TP;
+            const int j = 16 * tj + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * ti + lk + 4 * v;
+                if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[t][v], acci[t][v]);
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long rows_per_block,
-                                              int rows, double2* __restrict__ partial) {
+                                              double2* __restrict__ partial) {
     extern __shared__ __align__(16) unsigned char smem[];
-    gram_body(L, p, R, q, N, rows_per_block, rows, partial, blockIdx.x, smem);
+    gram_body(L, p, R, q, N, rows_per_block, partial, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(256) k_gram_vec(ColPtrs L, int p, ColPtrs R, int q, long long N,
+                                                  long long rows_per_block, int rows, double2* __restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gram_vec_body(L, p, R, q, N, rows_per_block, rows, partial, blockIdx.x, smem);
 }
 
 // C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
@@ -139,10 +245,11 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restri
 }
 
 // ---------------------------------------------------------------------------
-// lincomb: Y_j = beta Y_j + sum_i A_i C[j*p + i]   (q <= QB <= 48)
+// lincomb, q <= 32: one row per thread, all q outputs in registers, C in LDS
+// (broadcast reads); wider outputs go to the matrix-core version below.
 // ---------------------------------------------------------------------------
 template <int QB>
-__device__ __forceinline__ void lincomb_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
+__device__ __forceinline__ void lincomb_vec_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
                                              const double2* __restrict__ C, double beta, long long N, int bid, int nb,
                                              double2* sC) {
     for (int e = threadIdx.x; e < p * q; e += blockDim.x) sC[e] = C[e];
@@ -175,11 +282,90 @@ __device__ __forceinline__ void lincomb_body(const ColPtrs& A, int p, const ColP
     }
 }
 
-template <int QB>
+// ---------------------------------------------------------------------------
+// lincomb, 32 < q <= 48: Y_j = beta Y_j + sum_i A_i C[j*p + i]
+//
+// On the matrix cores, like gram: with the K index over (input column i,
+// re/im), Re Y = sum_k Ax[r][k] Bre[k][j] and Im Y = sum_k Ax[r][k] Bim[k][j],
+// Bre = (Re C, -Im C), Bim = (Im C, Re C) interleaved by (i, re/im).  Each
+// wavefront owns 16-row tiles (grid-stride); its A operand is read straight
+// from HBM (lanes 0-31 cover 16 rows of one input column, 256 contiguous
+// bytes) exactly once, C is staged transposed in LDS, and each lane ends with
+// whole complex outputs: rows lk + 4v of the tile, column 16 tq + li.
+// ---------------------------------------------------------------------------
+template <int TQ>
+__device__ __forceinline__ void lincomb_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
+                                             const double2* __restrict__ C, double beta, long long N, int bid, int nb,
+                                             double2* sCt) {
+    const int ldq = 16 * TQ;
+    for (int e = threadIdx.x; e < p * ldq; e += blockDim.x) {
+        const int i = e / ldq, j = e - i * ldq;
+        sCt[e] = j < q ? C[(size_t)j * p + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4, half = lk >> 1, part = lk & 1;
+    const int ksteps = (p + 1) >> 1;
+    const long long ntiles = (N + 15) >> 4;
+    for (long long t = (long long)bid * nw + wave; t < ntiles; t += (long long)nb * nw) {
+        const long long r0 = t << 4;
+        const long long ra = r0 + li;
+        const bool rok = ra < N;
+        dbl4 yr[TQ], yi[TQ];
+#pragma unroll
+        for (int c = 0; c < TQ; ++c) {
+            yr[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+            yi[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll 4
+        for (int ks = 0; ks < ksteps; ++ks) {
+            const int i = 2 * ks + half;
+            const bool iok = i < p;
+            const double a = (iok && rok) ? reinterpret_cast<const double*>(A.p[i])[2 * ra + part] : 0.0;
+            const int ic = iok ? i : 0;
+#pragma unroll
+            for (int c = 0; c < TQ; ++c) {
+                double2 cv = sCt[ic * ldq + 16 * c + li];
+                if (!iok) cv = make_double2(0.0, 0.0);
+                const double br = part ? -cv.y : cv.x;
+                const double bi = part ? cv.x : cv.y;
+                yr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, yr[c], 0, 0, 0);
+                yi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, yi[c], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < TQ; ++c) {
+            const int j = 16 * c + li;
+            if (j >= q) continue;
+            double2* yc = Y.p[j];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long long row = r0 + lk + 4 * v;
+                if (row >= N) continue;
+                double2 y = make_double2(yr[c][v], yi[c][v]);
+                if (beta != 0.0) {
+                    const double2 old = yc[row];
+                    y.x += beta * old.x;
+                    y.y += beta * old.y;
+                }
+                yc[row] = y;
+            }
+        }
+    }
+}
+
+template <int TQ>
 __global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, int q, const double2* __restrict__ C,
                                                  double beta, long long N) {
-    __shared__ double2 sC[kMaxCols * 48];
-    lincomb_body<QB>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sC);
+    __shared__ double2 sCt[kMaxCols * 48];
+    lincomb_body<TQ>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sCt);
+}
+
+template <int QB>
+__global__ void __launch_bounds__(256) k_lincomb_vec(ColPtrs A, int p, ColPtrs Y, int q,
+                                                     const double2* __restrict__ C, double beta, long long N) {
+    __shared__ double2 sC[kMaxCols * 32];
+    lincomb_vec_body<QB>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sC);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,8 +505,8 @@ __global__ void __launch_bounds__(256) k_gram_batched(const GramJob* __restrict_
     extern __shared__ __align__(16) unsigned char smem[];
     const int j = find_job(jobs, njobs, blockIdx.x);
     const GramJob& jb = jobs[j];
-    gram_body(jb.L, jb.p, jb.R, jb.q, jb.N, jb.rows_per_block, jb.rows, partial + jb.part_off, blockIdx.x - jb.start,
-              smem);
+    gram_vec_body(jb.L, jb.p, jb.R, jb.q, jb.N, jb.rows_per_block, jb.rows, partial + jb.part_off,
+                  blockIdx.x - jb.start, smem);
 }
 
 // one workgroup per output entry over all jobs (job j's entries start at out_start)
@@ -355,12 +541,20 @@ __global__ void __launch_bounds__(256) k_reduce_batched(const GramJob* __restric
     if (threadIdx.x == 0) C[e] = red[0];
 }
 
-template <int QB>
+template <int TQ>
 __global__ void __launch_bounds__(256) k_lincomb_batched(const LinJob* __restrict__ jobs, int njobs) {
-    __shared__ double2 sC[kMaxCols * 48];
+    __shared__ double2 sCt[kMaxCols * 48];
     const int j = find_job(jobs, njobs, blockIdx.x);
     const LinJob& jb = jobs[j];
-    lincomb_body<QB>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sC);
+    lincomb_body<TQ>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sCt);
+}
+
+template <int QB>
+__global__ void __launch_bounds__(256) k_lincomb_vec_batched(const LinJob* __restrict__ jobs, int njobs) {
+    __shared__ double2 sC[kMaxCols * 32];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const LinJob& jb = jobs[j];
+    lincomb_vec_body<QB>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sC);
 }
 
 __global__ void __launch_bounds__(256) k_residual_norm_batched(const ResJob* __restrict__ jobs, int njobs,
@@ -419,18 +613,26 @@ static int grid_for(long long N, int threads, int cap = 4096) {
     return (int)std::max(1LL, std::min<long long>(b, cap));
 }
 
+static size_t gram_lds(int p, int q) {
+    return (size_t)kGramRows * (16 * ((p + 15) / 16) + 1 + 16 * ((q + 15) / 16) + 1) * sizeof(double2);
+}
+
 hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
                 double2* C, hipStream_t st) {
     if (p <= 0 || q <= 0) return hipSuccess;
-    const int pl = p | 1, pr = q | 1;
-    int rows = (int)std::min<long long>(128, (48 * 1024) / ((pl + pr) * (long long)sizeof(double2)));
-    rows = std::max(rows, 8);
-    long long rpb = (N + max_blocks - 1) / max_blocks;
-    rpb = ((rpb + rows - 1) / rows) * rows;
-    int nb = (int)((N + rpb - 1) / rpb);
-    int ntile = ((p + 3) / 4) * ((q + 3) / 4);
-    size_t lds = std::max((size_t)rows * (pl + pr) * sizeof(double2), (size_t)(256 / ntile) * ntile * 16 * sizeof(double2));
-    k_gram<<<nb, 256, lds, st>>>(L, p, R, q, N, rpb, rows, partial);
+    int nb;
+    if (p + q >= 48) {
+        long long rpb = (N + max_blocks - 1) / max_blocks;
+        rpb = ((rpb + kGramRows - 1) / kGramRows) * kGramRows;
+        nb = (int)((N + rpb - 1) / rpb);
+        k_gram<<<nb, 256, gram_lds(p, q), st>>>(L, p, R, q, N, rpb, partial);
+    } else {
+        long long rpb;
+        int rows;
+        size_t lds;
+        nb = gram_job_blocks(p, q, N, max_blocks, &rpb, &rows, &lds);
+        k_gram_vec<<<nb, 256, lds, st>>>(L, p, R, q, N, rpb, rows, partial);
+    }
     int cnt = p * q;
     k_reduce_partials<<<cnt, 256, 0, st>>>(partial, nb, cnt, C);
     return hipGetLastError();
@@ -439,11 +641,16 @@ hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, d
 hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double2* C, double beta, long long N,
                    hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    int nb = grid_for(N, 256, 2048);
-    if (q <= 8) k_lincomb<8><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-    else if (q <= 16) k_lincomb<16><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-    else if (q <= 32) k_lincomb<32><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-    else k_lincomb<48><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+    if (q <= 32) {
+        int nb = grid_for(N, 256, 2048);
+        if (q <= 8) k_lincomb_vec<8><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        else if (q <= 16) k_lincomb_vec<16><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        else k_lincomb_vec<32><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+    } else {
+        // 16-row tiles, four per workgroup per sweep
+        int nb = (int)std::min<long long>(2048, std::max<long long>(1, (N + 63) / 64));
+        k_lincomb<3><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+    }
     return hipGetLastError();
 }
 
@@ -501,10 +708,10 @@ hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int to
 
 hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    if (maxq <= 8) k_lincomb_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else if (maxq <= 16) k_lincomb_batched<16><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else if (maxq <= 32) k_lincomb_batched<32><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else k_lincomb_batched<48><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    if (maxq <= 8) k_lincomb_vec_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (maxq <= 16) k_lincomb_vec_batched<16><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (maxq <= 32) k_lincomb_vec_batched<32><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else k_lincomb_batched<3><<<total_blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 
