@@ -377,10 +377,11 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
         if (lds_columns(g, pd, esz) > kLdsMax) T = 0;  // does not fit this precision: choose here
     }
     if (T <= 0) {
+        // widest tile (<= 16 columns) of which two workgroups still fit one CU's LDS
         T = 1;
         for (;;) {
             pd.tile = 2 * T;
-            if (2 * T > 16 || lds_columns(g, pd, esz) > kLdsDefault || 2 * T > pd.s_in) break;
+            if (2 * T > 16 || lds_columns(g, pd, esz) > kLdsMax / 2 || 2 * T > pd.s_in) break;
             T *= 2;
         }
     }
