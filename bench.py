@@ -249,7 +249,7 @@ def run_learned(lib, W):
     train_probs = [W.c2_2d(lam=0.5), W.c2_2d(lam=5.0)] + [sweep[i] for i in range(0, 64, 11)]
     train = [lib.Plan.from_problem(p, precision="fp32") for p in train_probs]
     net = lib.Learned(shells=1024, seed=5)
-    loss, t_train = _timed(lambda: net.train(train, steps=600, lr=2e-3, nev=16, tol=1e-8, snapshots=12, stride=6))
+    loss, t_train = _timed(lambda: net.train(train, steps=3000, lr=1e-3, nev=16, tol=1e-8, snapshots=24, stride=4))
     for p in train:
         p.close()
     rows = []

@@ -346,8 +346,8 @@ typedef struct {
 } iwfpm_train_opts;
 
 void iwfpm_default_learned_opts(iwfpm_learned_opts* opts);   /* device 0, 1024 shells */
-void iwfpm_default_train_opts(iwfpm_train_opts* opts);       /* 600 steps, lr 2e-3, nev 8, tol 1e-8,
-                                                                maxit 1000, 8 snapshots, stride 8 */
+void iwfpm_default_train_opts(iwfpm_train_opts* opts);       /* 3000 steps, lr 1e-3, nev 8, tol 1e-8,
+                                                                maxit 1000, 24 snapshots, stride 4 */
 
 /* Create / destroy a network.  Destroying a network detaches it from every
  * plan it is attached to (their LEARNED solves then return ERR_WEIGHTS). */

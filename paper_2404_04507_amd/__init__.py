@@ -342,7 +342,7 @@ class Learned:
                 raise ValueError("shell count of the saved network differs")
             self.set(z["params"])
 
-    def train(self, plans, steps=600, lr=2e-3, nev=8, block=0, tol=1e-8, maxit=1000, snapshots=8, stride=8,
+    def train(self, plans, steps=3000, lr=1e-3, nev=8, block=0, tol=1e-8, maxit=1000, snapshots=24, stride=4,
               seed=2404045070, stream=None) -> np.ndarray:
         """Train on data from plain solves of `plans` (iwfpm_learned_train); returns the loss per step."""
         lib = _lib()

@@ -548,14 +548,14 @@ void iwfpm_default_learned_opts(iwfpm_learned_opts* o) {
 
 void iwfpm_default_train_opts(iwfpm_train_opts* o) {
     if (!o) return;
-    o->steps = 600;
-    o->lr = 2e-3;
+    o->steps = 3000;
+    o->lr = 1e-3;
     o->nev = 8;
     o->block = 0;
     o->tol = 1e-8;
     o->maxit = 1000;
-    o->snapshots = 8;
-    o->stride = 8;
+    o->snapshots = 24;
+    o->stride = 4;
     o->seed = 2404045070ull;
 }
 
