@@ -19,9 +19,10 @@ After the timed region (each reported in its own JSON object):
              (the two lam above plus 6 instances of the sweep below), then
              iterations and time to 1e-8 against the plain preconditioner on
              32 held-out couplings of the same geometry;
-  * sweep    64 instances, lam ~ U[0.1, 10], K ~ U{6..14}, 8 eigenpairs each,
-             solved in lock step by iwfpm_eigs_batched (batched applies in one
-             persistent, graph-replayed launch per pass), plain and learned;
+  * sweep    64 instances, lam ~ U[0.1, 10], K ~ U{6..14}, 8 eigenpairs each:
+             one ragged batched apply (persistent, graph-replayed launch) against
+             per-plan applies, and the solves in lock step by iwfpm_eigs_batched,
+             plain and learned, against plain solves one plan at a time;
   * cpu_baseline  the CPU oracle's matvec rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 300] [--warmup 20]
@@ -297,6 +298,30 @@ def run_eigs(lib, W, net):
     return res
 
 
+def sweep_apply(lib, W, plans, probs, reps=20):
+    """One ragged batched apply of 8 vectors per instance: the persistent,
+    graph-replayed launch against one apply call per plan."""
+    import numpy as np
+    import torch
+    X = [torch.from_numpy(np.ascontiguousarray(W.random_block(p.N, 8, seed=W.SEED + i).T)).to("cuda:0")
+         for i, p in enumerate(probs)]
+    Y = [torch.empty_like(x) for x in X]
+    batch = lib.Batch(plans, precision="fp32", graph=True)
+    out = {}
+    try:
+        for name, fn in (("batched_graph", lambda: batch.apply(X, Y)),
+                         ("per_plan", lambda: [pl.apply(x, out=y) for pl, x, y in zip(plans, X, Y)])):
+            for _ in range(3):
+                fn()
+            _, t = _timed(lambda: [fn() for _ in range(reps)])
+            out[name + "_ms"] = t / reps * 1e3
+        out["matvecs_per_s_batched"] = 8 * len(plans) / (out["batched_graph_ms"] / 1e3)
+        out["all_passes_GBs_batched"] = 80.0 * 8 * sum(p.N for p in probs) / (out["batched_graph_ms"] / 1e3) / 1e9
+    finally:
+        batch.close()
+    return out
+
+
 def run_sweep(lib, W, net):
     """64 couplings with ragged windows, 8 eigenpairs each, in lock step."""
     import numpy as np
@@ -304,11 +329,15 @@ def run_sweep(lib, W, net):
     plans = [lib.Plan.from_problem(p, precision="fp32") for p in probs]
     res = {"instances": len(plans), "dof_total": int(sum(p.N for p in plans)), "nev": 8, "tol": 1e-8}
     try:
+        res["apply"] = sweep_apply(lib, W, plans, probs)
         lib.eigs_batched(plans[:2], 8, tol=1e-8, maxit=3, allow_noconv=True)  # allocations
         (ev, eta, st, _), t = _timed(lambda: lib.eigs_batched(plans, 8, tol=1e-8, maxit=2000))
         res["plain"] = {"seconds": t, "iterations_max": max(x["iterations"] for x in st),
                         "iterations_mean": float(np.mean([x["iterations"] for x in st])),
                         "eta_max": float(eta.max())}
+        # the same 64 solves one plan at a time (iwfpm_eigs), for comparison
+        _, ts = _timed(lambda: [pl.eigs(8, tol=1e-8, maxit=2000, want_vectors=False) for pl in plans])
+        res["plain_one_by_one_seconds"] = ts
         if net is not None:
             for p in plans:
                 p.attach(net)
