@@ -117,34 +117,38 @@ __device__ __forceinline__ void gram_vec_body(const ColPtrs& L, int p, const Col
 // real 16x16x4 products per 16x16 complex output tile and K step of two rows,
 // sharing the A operand.  Lane l of a wave holds A[l%16][l/16], B[l/16][l%16]
 // and result v in D[l/16 + 4v][l%16], so each lane ends with whole complex
-// entries.  Rows are staged through LDS kGramRows at a time (odd pitches);
-// the 4 wavefronts split the output tiles.  Reduction over blocks as before.
+// entries.  Rows are staged through LDS kGramRows at a time (odd pitches),
+// the next chunk's loads in flight in registers while the current one is
+// multiplied; the 4 wavefronts split the output tiles.
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kGramRows = 24;   // rows staged per chunk (12 K steps)
 constexpr int kGramTilesPerWave = 4;
-constexpr int kGramBatch = 6;   // staging loads in flight per thread
 
-// stage kGramRows rows of the columns of X (zero beyond nr rows and p columns)
-// into s[row * pitch + column]; each thread issues kGramBatch loads before its
-// first LDS store, so a chunk costs a few memory round trips, not one per entry
-__device__ __forceinline__ void stage_rows(const ColPtrs& X, int p, int pitch, long long rb, int nr,
-                                           double2* __restrict__ s, int tid) {
+// registers of one thread's share of one staged matrix (kGramRows rows of at
+// most 64 padded columns)
+constexpr int kGramRegs = (kGramRows * 64 + 255) / 256;
+
+// load this thread's entries e = tid + 256 u of the chunk at row rb of X
+// (zero beyond nr rows and p columns)
+__device__ __forceinline__ void fetch_chunk(const ColPtrs& X, int p, int pitch, long long rb, int nr, int tid,
+                                            double2 (&v)[kGramRegs]) {
     const int total = kGramRows * (pitch - 1);
-    for (int e0 = 0; e0 < total; e0 += kGramBatch * 256) {
-        double2 v[kGramBatch];
 #pragma unroll
-        for (int u = 0; u < kGramBatch; ++u) {
-            const int e = e0 + tid + u * 256;
-            const int c = e / kGramRows, rr = e - c * kGramRows;
-            v[u] = (e < total && rr < nr && c < p) ? X.p[c][rb + rr] : make_double2(0.0, 0.0);
-        }
+    for (int u = 0; u < kGramRegs; ++u) {
+        const int e = tid + 256 * u;
+        const int c = e / kGramRows, rr = e - c * kGramRows;
+        v[u] = (e < total && rr < nr && c < p) ? X.p[c][rb + rr] : make_double2(0.0, 0.0);
+    }
+}
+
+__device__ __forceinline__ void put_chunk(int pitch, double2* __restrict__ s, int tid, const double2 (&v)[kGramRegs]) {
+    const int total = kGramRows * (pitch - 1);
 #pragma unroll
-        for (int u = 0; u < kGramBatch; ++u) {
-            const int e = e0 + tid + u * 256;
-            const int c = e / kGramRows, rr = e - c * kGramRows;
-            if (e < total) s[rr * pitch + c] = v[u];
-        }
+    for (int u = 0; u < kGramRegs; ++u) {
+        const int e = tid + 256 * u;
+        const int c = e / kGramRows, rr = e - c * kGramRows;
+        if (e < total) s[rr * pitch + c] = v[u];
     }
 }
 
@@ -168,11 +172,24 @@ __device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs
     }
     const long long r0 = (long long)bid * rows_per_block;
     const long long r1 = min(N, r0 + rows_per_block);
+    // software pipeline: the next chunk's loads are in flight while the
+    // matrix cores work on the staged one
+    double2 nL[kGramRegs], nR[kGramRegs];
+    if (r0 < r1) {
+        const int nr0 = (int)min((long long)kGramRows, r1 - r0);
+        fetch_chunk(L, p, pl, r0, nr0, tid, nL);
+        fetch_chunk(R, q, pr, r0, nr0, tid, nR);
+    }
     for (long long rb = r0; rb < r1; rb += kGramRows) {
-        const int nr = (int)min((long long)kGramRows, r1 - rb);
-        stage_rows(L, p, pl, rb, nr, sL, tid);
-        stage_rows(R, q, pr, rb, nr, sR, tid);
+        put_chunk(pl, sL, tid, nL);
+        put_chunk(pr, sR, tid, nR);
         __syncthreads();
+        const long long rn = rb + kGramRows;
+        if (rn < r1) {
+            const int nrn = (int)min((long long)kGramRows, r1 - rn);
+            fetch_chunk(L, p, pl, rn, nrn, tid, nL);
+            fetch_chunk(R, q, pr, rn, nrn, tid, nR);
+        }
 #pragma unroll
         for (int t = 0; t < kGramTilesPerWave; ++t) {
             const int tile = wave + 4 * t;
