@@ -15,6 +15,8 @@ library records on the apply's own stream during the timed steps.
 After the timed region (each reported in its own JSON object):
   * eigs     time to the 16 lowest eigenpairs at backward error 1e-8 for
              lam = 0.5 and 5.0, plain diagonal preconditioner and learned one;
+             and for the 3D problem lifted to 6D (the network trained on the
+             4D problems only);
   * learned  the learned preconditioner trained on the method's own solves
              (the two lam above plus 6 instances of the sweep below), then
              iterations and time to 1e-8 against the plain preconditioner on
@@ -173,6 +175,8 @@ def main():
         net, out["learned"] = run_learned(lib, W)
     if not a.no_eigs:
         out["eigs"] = run_eigs(lib, W, net)
+        if not a.no_c3:
+            out["eigs_3d_lifted_6d"] = run_eigs_c3(lib, W, net)
     if not a.no_sweep:
         out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
@@ -320,6 +324,27 @@ def sweep_apply(lib, W, plans, probs, reps=20):
     finally:
         batch.close()
     return out
+
+
+def run_eigs_c3(lib, W, net):
+    """16 eigenpairs of the 3D problem lifted to 6D (16,777,216 points) at
+    eta <= 1e-8, plain and with the network trained on the 4D problems only."""
+    import numpy as np
+    res = {"workload": "3d_lifted_6d", "N": 16777216, "nev": 16, "tol": 1e-8}
+    with lib.Plan.from_problem(W.c3_3d(), precision="fp32") as plan:
+        plan.tune(BLOCK, "fp32")
+        plan.eigs(16, tol=1e-8, maxit=2, want_vectors=False, allow_noconv=True)
+        a, ta = _timed(lambda: plan.eigs(16, tol=1e-8, maxit=1000, want_vectors=False))
+        res["plain"] = {"seconds": ta, "iterations": a.iterations, "eta_max": float(max(a.eta)),
+                        "E0": float(a.evals[0])}
+        if net is not None:
+            plan.attach(net)
+            plan.eigs(16, tol=1e-8, maxit=2, precond="learned", want_vectors=False, allow_noconv=True)
+            b, tb = _timed(lambda: plan.eigs(16, tol=1e-8, maxit=1000, precond="learned", want_vectors=False))
+            res["learned"] = {"seconds": tb, "iterations": b.iterations, "eta_max": float(max(b.eta)),
+                              "fallback": b.fallback, "max_eigenvalue_diff": float(np.max(np.abs(a.evals - b.evals)))}
+            res["time_speedup"] = ta / tb
+    return res
 
 
 def run_sweep(lib, W, net):
