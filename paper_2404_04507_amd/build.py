@@ -34,6 +34,11 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", f"-
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 HOST_SOURCES = ["plan.cpp", "batch.cpp", "lobpcg.cpp", "learned.cpp"]
+# the eigensolver's host side (small dense Hermitian algebra): inline complex
+# products (no Annex G NaN recovery calls) and contracted multiply-adds; the
+# plan keeps exact, uncontracted arithmetic for its window ties
+HOST_FAST = {"lobpcg.cpp", "learned.cpp"}
+FAST_FLAGS = ["-O3", "-fcx-limited-range", "-ffp-contract=fast"]
 DEVICE_SOURCES = ["blas_kernels.hip", "learned_kernels.hip"]
 APPLY_TUS = [(k, r, m) for k in range(5) for r in ("float", "double") for m in (16, 32, 64)]
 
@@ -50,7 +55,8 @@ def _jobs():
         jobs.append((obj, [HIPCC, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        jobs.append((obj, [HIPCC, *HOST_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]))
+        flags = HOST_FLAGS + FAST_FLAGS if src in HOST_FAST else HOST_FLAGS
+        jobs.append((obj, [HIPCC, *flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]))
     return jobs
 
 

@@ -135,53 +135,60 @@ static void jacobi_eigh(std::vector<cd> A, int n, std::vector<double>& w, std::v
 // reduction to a real symmetric tridiagonal matrix followed by the implicit QL
 // iteration with Wilkinson shifts; false if QL does not converge.
 static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std::vector<cd>& V) {
-    V.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[i + (size_t)i * n] = 1.0;
-    std::vector<cd> v(n), pv(n);
+    // Q = H_0 H_1 ... accumulates the reflectors (column-major, column loops innermost)
+    std::vector<cd> Q((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[i + (size_t)i * n] = 1.0;
+    std::vector<cd> v(n), pv(n), acc(n);
     for (int k = 0; k + 2 < n; ++k) {
         // reflector H = I - 2 u u^H on rows/cols k+1..n-1 that zeroes A[k+2.., k]
+        cd* ak = &A[(size_t)k * n];
         double xn = 0.0;
-        for (int i = k + 1; i < n; ++i) xn += std::norm(A[i + (size_t)k * n]);
+        for (int i = k + 1; i < n; ++i) xn += std::norm(ak[i]);
         xn = std::sqrt(xn);
-        cd x0 = A[(k + 1) + (size_t)k * n];
+        cd x0 = ak[k + 1];
         double tail = xn * xn - std::norm(x0);
         if (xn == 0.0 || tail <= 1e-300) continue;
         cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
         cd alpha = -ph * xn;
         double un = 0.0;
         for (int i = k + 1; i < n; ++i) {
-            v[i] = A[i + (size_t)k * n];
+            v[i] = ak[i];
             if (i == k + 1) v[i] -= alpha;
             un += std::norm(v[i]);
         }
-        un = std::sqrt(un);
-        for (int i = k + 1; i < n; ++i) v[i] /= un;
-        // p = A u, K = u^H p, w = p - K u; A <- A - 2 (u w^H + w u^H)  (on the trailing block and row/col k)
-        for (int i = k; i < n; ++i) {
-            cd acc = 0.0;
-            for (int j = k + 1; j < n; ++j) acc += A[i + (size_t)j * n] * v[j];
-            pv[i] = acc;
+        const double inv = 1.0 / std::sqrt(un);
+        for (int i = k + 1; i < n; ++i) v[i] *= inv;
+        v[k] = 0.0;
+        // p = A u over rows k..n-1, K = u^H p, w = p - K u; A <- A - 2 (u w^H + w u^H)
+        for (int i = k; i < n; ++i) pv[i] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const cd* aj = &A[(size_t)j * n];
+            const cd vj = v[j];
+            for (int i = k; i < n; ++i) pv[i] += aj[i] * vj;
         }
         cd K = 0.0;
         for (int i = k + 1; i < n; ++i) K += std::conj(v[i]) * pv[i];
         for (int i = k + 1; i < n; ++i) pv[i] -= K.real() * v[i];
-        // row/col k: only the (i, k) and (k, i) entries change: A[i,k] <- A[i,k] - 2 u_i (u^H A[:,k])
-        // handled by the general update with u_k = 0
         for (int j = k; j < n; ++j) {
-            cd vj = j > k ? v[j] : cd(0.0);
-            for (int i = k; i < n; ++i) {
-                cd vi = i > k ? v[i] : cd(0.0);
-                A[i + (size_t)j * n] -= 2.0 * (vi * std::conj(pv[j]) + pv[i] * std::conj(vj));
-            }
+            cd* aj = &A[(size_t)j * n];
+            const cd a = 2.0 * std::conj(pv[j]), b = 2.0 * std::conj(v[j]);
+            for (int i = k; i < n; ++i) aj[i] -= v[i] * a + pv[i] * b;
         }
-        // V <- V H
-        for (int r = 0; r < n; ++r) {
-            cd acc = 0.0;
-            for (int j = k + 1; j < n; ++j) acc += V[r + (size_t)j * n] * v[j];
-            for (int j = k + 1; j < n; ++j) V[r + (size_t)j * n] -= 2.0 * acc * std::conj(v[j]);
+        // Q <- Q H
+        for (int r = 0; r < n; ++r) acc[r] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const cd* qj = &Q[(size_t)j * n];
+            const cd vj = v[j];
+            for (int r = 0; r < n; ++r) acc[r] += qj[r] * vj;
+        }
+        for (int j = k + 1; j < n; ++j) {
+            cd* qj = &Q[(size_t)j * n];
+            const cd c = 2.0 * std::conj(v[j]);
+            for (int r = 0; r < n; ++r) qj[r] -= acc[r] * c;
         }
     }
-    // real tridiagonal: d (diagonal), e (sub-diagonal made real by a diagonal phase)
+    // real tridiagonal: d (diagonal), e (sub-diagonal made real by a diagonal phase
+    // folded into the columns of Q)
     std::vector<double> d(n), e(n, 0.0);
     cd phase = 1.0;
     for (int k = 0; k < n; ++k) {
@@ -191,11 +198,14 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
             double a = std::abs(sub);
             cd next = a > 0.0 ? phase * (sub / a) : phase;
             e[k] = a;
-            for (int r = 0; r < n; ++r) V[r + (size_t)(k + 1) * n] *= next;
+            for (int r = 0; r < n; ++r) Q[r + (size_t)(k + 1) * n] *= next;
             phase = next;
         }
     }
-    // implicit QL with Wilkinson shifts (e[k] couples k and k+1)
+    // implicit QL with Wilkinson shifts (e[k] couples k and k+1); the rotations
+    // act on the real matrix Z, and V = Q Z at the end
+    std::vector<double> Z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[i + (size_t)i * n] = 1.0;
     for (int l = 0; l < n; ++l) {
         int iter = 0, m;
         do {
@@ -228,10 +238,12 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
                     pp = sn * r;
                     d[i + 1] = g + pp;
                     g = cs * r - b;
+                    double* zi = &Z[(size_t)i * n];
+                    double* zi1 = &Z[(size_t)(i + 1) * n];
                     for (int k = 0; k < n; ++k) {
-                        cd fz = V[k + (size_t)(i + 1) * n];
-                        V[k + (size_t)(i + 1) * n] = sn * V[k + (size_t)i * n] + cs * fz;
-                        V[k + (size_t)i * n] = cs * V[k + (size_t)i * n] - sn * fz;
+                        const double fz = zi1[k];
+                        zi1[k] = sn * zi[k] + cs * fz;
+                        zi[k] = cs * zi[k] - sn * fz;
                     }
                 }
                 if (deflated) continue;
@@ -244,13 +256,20 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
-    std::vector<cd> Vs((size_t)n * n);
+    // V[:, j] = Q Z[:, idx[j]]
+    V.assign((size_t)n * n, 0.0);
     w.resize(n);
     for (int j = 0; j < n; ++j) {
         w[j] = d[idx[j]];
-        for (int i = 0; i < n; ++i) Vs[i + (size_t)j * n] = V[i + (size_t)idx[j] * n];
+        const double* zj = &Z[(size_t)idx[j] * n];
+        cd* vj = &V[(size_t)j * n];
+        for (int k = 0; k < n; ++k) {
+            const double z = zj[k];
+            if (z == 0.0) continue;
+            const cd* qk = &Q[(size_t)k * n];
+            for (int i = 0; i < n; ++i) vj[i] += qk[i] * z;
+        }
     }
-    V.swap(Vs);
     return true;
 }
 
