@@ -4,11 +4,12 @@
 // vector; kernels take lists of column pointers so that any subset of the
 // X / W / P blocks can be combined without copies.
 //
-//   gram      C = L^H R            tall-skinny (p, q <= 64), wide ones on the
-//                                  matrix cores; two-stage deterministic
-//                                  reduction
+//   gram      C = L^H R            tall-skinny (p, q <= 64) on the matrix
+//                                  cores, operands straight from HBM;
+//                                  two-stage deterministic reduction
 //   lincomb   Y = beta Y + A C     (p <= 64 inputs, q <= 48 outputs per call);
-//                                  outputs beyond 32 on the matrix cores
+//                                  up to 32 outputs with vector FMAs (two rows
+//                                  per lane), wider on the matrix cores
 //   residual  R_j = HX_j - theta_j X_j
 //   colnorm2  ||R_j||^2           two-stage deterministic reduction
 //   precond   W_j = M .* R_j       diagonal preconditioner (eq:precond)
@@ -25,7 +26,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// gram for small blocks (p + q < 48, and every batched call): the p x q output
+// gram of the batched solver (one job per instance): the p x q output
 // is cut into 4 x 4 tiles; with ntile tiles, the 256 threads form 256 / ntile
 // row groups, each summing its own subset of the staged rows for its tile.
 // Rows are staged through LDS `rows` at a time; the row groups are summed in a
@@ -110,132 +111,86 @@ __device__ __forceinline__ void gram_vec_body(const ColPtrs& L, int p, const Col
 }
 
 // ---------------------------------------------------------------------------
-// gram for wide blocks: partial[b][j*p + i] = sum over the rows of block b of
-// conj(L_i[r]) R_j[r], on the matrix cores (v_mfma_f64_16x16x4f64).  With the K index running over
-// (row, re/im) pairs, Re C = sum_k Lx[k][i] Rx[k][j] and Im C = sum_k Lx[k][i]
-// Ry[k][j], where Lx, Rx hold (re, im) of each row and Ry holds (im, -re): two
-// real 16x16x4 products per 16x16 complex output tile and K step of two rows,
-// sharing the A operand.  Lane l of a wave holds A[l%16][l/16], B[l/16][l%16]
-// and result v in D[l/16 + 4v][l%16], so each lane ends with whole complex
-// entries.  Rows are staged through LDS kGramRows at a time (odd pitches),
-// the next chunk's loads in flight in registers while the current one is
-// multiplied; the 4 wavefronts split the output tiles.
+// gram, unbatched: partial[b][j*p + i] = sum over the rows of block b of
+// conj(L_i[r]) R_j[r] on the matrix cores (v_mfma_f64_16x16x4f64), operands
+// loaded straight from HBM into the MFMA register layout (no LDS staging).
+// Lane l of a wave holds A[l%16][l/16] and B[l/16][l%16] and ends with result
+// v in D[l/16 + 4v][l%16].  The K index runs over 4-row groups: lane l loads
+// the complex entry at row 4g + l/16 of column 16t + l%16, so one 16-byte load
+// feeds two products (re, then im parts):
+//   Re C += Lr Rr + Li Ri,   Im C += Lr Ri - Li Rr.
+// A workgroup has one wave per 16-column tile of L; every wave walks the same
+// rows and multiplies its tile by all TQ tiles of R (the R loads of the other
+// waves hit in L1), keeping 2 TQ accumulators.  Loads run D groups ahead.
 // ---------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-constexpr int kGramRows = 24;   // rows staged per chunk (12 K steps)
-constexpr int kGramTilesPerWave = 4;
+constexpr int kGramDepth = 8;  // 4-row groups in flight per wave
 
-// registers of one thread's share of one staged matrix (kGramRows rows of at
-// most 64 padded columns)
-constexpr int kGramRegs = (kGramRows * 64 + 255) / 256;
-
-// load this thread's entries e = tid + 256 u of the chunk at row rb of X
-// (zero beyond nr rows and p columns)
-__device__ __forceinline__ void fetch_chunk(const ColPtrs& X, int p, int pitch, long long rb, int nr, int tid,
-                                            double2 (&v)[kGramRegs]) {
-    const int total = kGramRows * (pitch - 1);
+template <int TQ>
+__device__ __forceinline__ void gram_load(const double2* lp, const double2* const (&rp)[TQ], long long g, long long g1,
+                                          long long N, int lk, double2& lv, double2 (&rv)[TQ]) {
+    const long long row = 4 * g + lk;
+    const bool ok = g < g1 && row < N;
+    lv = (ok && lp) ? lp[row] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < kGramRegs; ++u) {
-        const int e = tid + 256 * u;
-        const int c = e / kGramRows, rr = e - c * kGramRows;
-        v[u] = (e < total && rr < nr && c < p) ? X.p[c][rb + rr] : make_double2(0.0, 0.0);
-    }
+    for (int t = 0; t < TQ; ++t) rv[t] = (ok && rp[t]) ? rp[t][row] : make_double2(0.0, 0.0);
 }
 
-__device__ __forceinline__ void put_chunk(int pitch, double2* __restrict__ s, int tid, const double2 (&v)[kGramRegs]) {
-    const int total = kGramRows * (pitch - 1);
-#pragma unroll
-    for (int u = 0; u < kGramRegs; ++u) {
-        const int e = tid + 256 * u;
-        const int c = e / kGramRows, rr = e - c * kGramRows;
-        if (e < total) s[rr * pitch + c] = v[u];
-    }
-}
-
-__device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
-                                          long long rows_per_block, double2* __restrict__ partial, int bid,
-                                          unsigned char* smem) {
-    const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4, ntile = TP * TQ;
-    const int pl = 16 * TP + 1, pr = 16 * TQ + 1;  // odd pitches (complex entries)
-    double2* sL = reinterpret_cast<double2*>(smem);
-    double2* sR = sL + kGramRows * pl;
-    const double* dL = reinterpret_cast<const double*>(sL);
-    const double* dR = reinterpret_cast<const double*>(sR);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;  // A row / B column, and K index 0..3
-    const int half = lk >> 1, part = lk & 1;   // staged row within the K step, re/im
-    dbl4 accr[kGramTilesPerWave], acci[kGramTilesPerWave];
-#pragma unroll
-    for (int t = 0; t < kGramTilesPerWave; ++t) {
-        accr[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-        acci[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-    }
-    const long long r0 = (long long)bid * rows_per_block;
-    const long long r1 = min(N, r0 + rows_per_block);
-    // software pipeline: the next chunk's loads are in flight while the
-    // matrix cores work on the staged one
-    double2 nL[kGramRegs], nR[kGramRegs];
-    if (r0 < r1) {
-        const int nr0 = (int)min((long long)kGramRows, r1 - r0);
-        fetch_chunk(L, p, pl, r0, nr0, tid, nL);
-        fetch_chunk(R, q, pr, r0, nr0, tid, nR);
-    }
-    for (long long rb = r0; rb < r1; rb += kGramRows) {
-        put_chunk(pl, sL, tid, nL);
-        put_chunk(pr, sR, tid, nR);
-        __syncthreads();
-        const long long rn = rb + kGramRows;
-        if (rn < r1) {
-            const int nrn = (int)min((long long)kGramRows, r1 - rn);
-            fetch_chunk(L, p, pl, rn, nrn, tid, nL);
-            fetch_chunk(R, q, pr, rn, nrn, tid, nR);
-        }
-#pragma unroll
-        for (int t = 0; t < kGramTilesPerWave; ++t) {
-            const int tile = wave + 4 * t;
-            if (tile < ntile) {  // uniform across the wave
-                const int ti = tile % TP, tj = tile / TP;
-#pragma unroll 4
-                for (int ks = 0; ks < kGramRows / 2; ++ks) {
-                    const int row = 2 * ks + half;
-                    const double a = dL[2 * (row * pl + 16 * ti + li) + part];
-                    const double2 rv = sR[row * pr + 16 * tj + li];
-                    const double br = part ? rv.y : rv.x;
-                    const double bi = part ? -rv.x : rv.y;
-                    accr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, accr[t], 0, 0, 0);
-                    acci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, acci[t], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    (void)dR;
-    double2* out = partial + (size_t)bid * p * q;
-#pragma unroll
-    for (int t = 0; t < kGramTilesPerWave; ++t) {
-        const int tile = wave + 4 * t;
-        if (tile < ntile) {
-            const int ti = tile % TP, tj = tile / TP;
-            const int j = 16 * tj + li;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * ti + lk + 4 * v;
-                if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[t][v], acci[t][v]);
-            }
-        }
-    }
-}
-
-__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long rows_per_block,
+template <int TQ>
+__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long groups_per_block,
                                               double2* __restrict__ partial) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    gram_body(L, p, R, q, N, rows_per_block, partial, blockIdx.x, smem);
-}
-
-__global__ void __launch_bounds__(256) k_gram_vec(ColPtrs L, int p, ColPtrs R, int q, long long N,
-                                                  long long rows_per_block, int rows, double2* __restrict__ partial) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    gram_vec_body(L, p, R, q, N, rows_per_block, rows, partial, blockIdx.x, smem);
+    constexpr int D = kGramDepth;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int cl = 16 * wave + li;
+    const double2* lp = cl < p ? L.p[cl] : nullptr;
+    const double2* rp[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+        const int c = 16 * t + li;
+        rp[t] = c < q ? R.p[c] : nullptr;
+    }
+    dbl4 accr[TQ], acci[TQ];
+#pragma unroll
+    for (int b = 0; b < TQ; ++b) {
+        accr[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        acci[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    const long long G = (N + 3) >> 2;
+    const long long g0 = (long long)blockIdx.x * groups_per_block, g1 = min(G, g0 + groups_per_block);
+    double2 lb[D], rb[D][TQ];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gram_load<TQ>(lp, rp, g0 + d, g1, N, lk, lb[d], rb[d]);
+    for (long long g = g0; g < g1; g += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double2 lv = lb[d];
+            double2 rv[TQ];
+#pragma unroll
+            for (int t = 0; t < TQ; ++t) rv[t] = rb[d][t];
+            gram_load<TQ>(lp, rp, g + d + D, g1, N, lk, lb[d], rb[d]);
+#pragma unroll
+            for (int b = 0; b < TQ; ++b) {
+                accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.x, rv[b].x, accr[b], 0, 0, 0);
+                acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.x, rv[b].y, acci[b], 0, 0, 0);
+            }
+#pragma unroll
+            for (int b = 0; b < TQ; ++b) {
+                accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, rv[b].y, accr[b], 0, 0, 0);
+                acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, -rv[b].x, acci[b], 0, 0, 0);
+            }
+        }
+    }
+    double2* out = partial + (size_t)blockIdx.x * p * q;
+#pragma unroll
+    for (int b = 0; b < TQ; ++b) {
+        const int j = 16 * b + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * wave + lk + 4 * v;
+            if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[b][v], acci[b][v]);
+        }
+    }
 }
 
 // C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
@@ -262,8 +217,8 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restri
 }
 
 // ---------------------------------------------------------------------------
-// lincomb, q <= 32: one row per thread, all q outputs in registers, C in LDS
-// (broadcast reads); wider outputs go to the matrix-core version below.
+// lincomb of the batched solver, q <= 32: one row per thread,
+// all q outputs in registers, C in LDS (broadcast reads).
 // ---------------------------------------------------------------------------
 template <int QB>
 __device__ __forceinline__ void lincomb_vec_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
@@ -300,54 +255,126 @@ __device__ __forceinline__ void lincomb_vec_body(const ColPtrs& A, int p, const 
 }
 
 // ---------------------------------------------------------------------------
+// lincomb, unbatched, q <= 32: the four wavefronts of a workgroup share a pair
+// of 64-row strips (rows r and r + 64 per lane) and split the outputs, wave w
+// taking columns [w qg, w qg + qg) with qg = ceil(q / 4); C is read with
+// wave-uniform (scalar) loads, so no LDS.  Two rows per lane halve the scalar
+// loads per multiply-add and double the loads in flight.
+// ---------------------------------------------------------------------------
+template <int QG>
+__global__ void __launch_bounds__(256) k_lincomb_rows(ColPtrs A, int p, ColPtrs Y, int q,
+                                                      const double2* __restrict__ C, double beta, long long N) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int qg = (q + 3) >> 2;
+    const int j0 = wave * qg;
+    const int nj = max(0, min(qg, q - j0));
+    if (nj == 0) return;
+    for (long long r = (long long)blockIdx.x * 128 + lane; r < N; r += (long long)gridDim.x * 128) {
+        const long long r2 = r + 64;
+        const bool ok2 = r2 < N;
+        double2 acc[QG], acc2[QG];
+#pragma unroll
+        for (int j = 0; j < QG; ++j) {
+            acc[j] = make_double2(0.0, 0.0);
+            acc2[j] = make_double2(0.0, 0.0);
+            if (j < nj && beta != 0.0) {
+                const double2 y = Y.p[j0 + j][r];
+                acc[j] = make_double2(beta * y.x, beta * y.y);
+                if (ok2) {
+                    const double2 y2 = Y.p[j0 + j][r2];
+                    acc2[j] = make_double2(beta * y2.x, beta * y2.y);
+                }
+            }
+        }
+#pragma unroll 4
+        for (int i = 0; i < p; ++i) {
+            const double2 a = A.p[i][r];
+            const double2 a2 = ok2 ? A.p[i][r2] : make_double2(0.0, 0.0);
+            const double2* ci = C + (size_t)j0 * p + i;
+#pragma unroll
+            for (int j = 0; j < QG; ++j) {
+                if (j < nj) {
+                    const double2 c = ci[(size_t)j * p];
+                    acc[j].x += a.x * c.x - a.y * c.y;
+                    acc[j].y += a.x * c.y + a.y * c.x;
+                    acc2[j].x += a2.x * c.x - a2.y * c.y;
+                    acc2[j].y += a2.x * c.y + a2.y * c.x;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < QG; ++j)
+            if (j < nj) {
+                Y.p[j0 + j][r] = acc[j];
+                if (ok2) Y.p[j0 + j][r2] = acc2[j];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // lincomb, 32 < q <= 48: Y_j = beta Y_j + sum_i A_i C[j*p + i]
 //
-// On the matrix cores, like gram: with the K index over (input column i,
-// re/im), Re Y = sum_k Ax[r][k] Bre[k][j] and Im Y = sum_k Ax[r][k] Bim[k][j],
+// On the matrix cores: with the K index over (input column i, re/im),
+// Re Y = sum_k Ax[r][k] Bre[k][j] and Im Y = sum_k Ax[r][k] Bim[k][j],
 // Bre = (Re C, -Im C), Bim = (Im C, Re C) interleaved by (i, re/im).  Each
 // wavefront owns 16-row tiles (grid-stride); its A operand is read straight
 // from HBM (lanes 0-31 cover 16 rows of one input column, 256 contiguous
-// bytes) exactly once, C is staged transposed in LDS, and each lane ends with
-// whole complex outputs: rows lk + 4v of the tile, column 16 tq + li.
+// bytes) exactly once, 8 K steps (16 input columns) ahead of their use, the
+// prefetch running on into the next tile; C is staged transposed in LDS
+// (zero-padded to 64 inputs) and each lane ends with whole complex outputs:
+// rows lk + 4v of the tile, column 16 tq + li.
 // ---------------------------------------------------------------------------
 template <int TQ>
 __device__ __forceinline__ void lincomb_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
                                              const double2* __restrict__ C, double beta, long long N, int bid, int nb,
                                              double2* sCt) {
     const int ldq = 16 * TQ;
-    for (int e = threadIdx.x; e < p * ldq; e += blockDim.x) {
+    for (int e = threadIdx.x; e < kMaxCols * ldq; e += blockDim.x) {
         const int i = e / ldq, j = e - i * ldq;
-        sCt[e] = j < q ? C[(size_t)j * p + i] : make_double2(0.0, 0.0);
+        sCt[e] = (i < p && j < q) ? C[(size_t)j * p + i] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int li = lane & 15, lk = lane >> 4, half = lk >> 1, part = lk & 1;
-    const int ksteps = (p + 1) >> 1;
+    const int nchunk = (p + 15) >> 4;  // 8 K steps = 16 input columns per chunk
     const long long ntiles = (N + 15) >> 4;
-    for (long long t = (long long)bid * nw + wave; t < ntiles; t += (long long)nb * nw) {
+    const long long t0 = (long long)bid * nw + wave, ts = (long long)nb * nw;
+    auto fetch = [&](long long t, int kc, double (&a)[8]) {
+        const long long ra = (t << 4) + li;
+        const bool rok = t < ntiles && ra < N;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = 16 * kc + 2 * u + half;
+            a[u] = (rok && i < p) ? reinterpret_cast<const double*>(A.p[i])[2 * ra + part] : 0.0;
+        }
+    };
+    double an[8];
+    fetch(t0, 0, an);
+    for (long long t = t0; t < ntiles; t += ts) {
         const long long r0 = t << 4;
-        const long long ra = r0 + li;
-        const bool rok = ra < N;
         dbl4 yr[TQ], yi[TQ];
 #pragma unroll
         for (int c = 0; c < TQ; ++c) {
             yr[c] = dbl4{0.0, 0.0, 0.0, 0.0};
             yi[c] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
-#pragma unroll 4
-        for (int ks = 0; ks < ksteps; ++ks) {
-            const int i = 2 * ks + half;
-            const bool iok = i < p;
-            const double a = (iok && rok) ? reinterpret_cast<const double*>(A.p[i])[2 * ra + part] : 0.0;
-            const int ic = iok ? i : 0;
+        for (int kc = 0; kc < nchunk; ++kc) {
+            double a[8];
 #pragma unroll
-            for (int c = 0; c < TQ; ++c) {
-                double2 cv = sCt[ic * ldq + 16 * c + li];
-                if (!iok) cv = make_double2(0.0, 0.0);
-                const double br = part ? -cv.y : cv.x;
-                const double bi = part ? cv.x : cv.y;
-                yr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, yr[c], 0, 0, 0);
-                yi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, yi[c], 0, 0, 0);
+            for (int u = 0; u < 8; ++u) a[u] = an[u];
+            if (kc + 1 < nchunk) fetch(t, kc + 1, an);
+            else fetch(t + ts, 0, an);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = 16 * kc + 2 * u + half;
+#pragma unroll
+                for (int c = 0; c < TQ; ++c) {
+                    const double2 cv = sCt[i * ldq + 16 * c + li];
+                    const double br = part ? -cv.y : cv.x;
+                    const double bi = part ? cv.x : cv.y;
+                    yr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], br, yr[c], 0, 0, 0);
+                    yi[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bi, yi[c], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
@@ -376,13 +403,6 @@ __global__ void __launch_bounds__(256) k_lincomb(ColPtrs A, int p, ColPtrs Y, in
                                                  double beta, long long N) {
     __shared__ double2 sCt[kMaxCols * 48];
     lincomb_body<TQ>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sCt);
-}
-
-template <int QB>
-__global__ void __launch_bounds__(256) k_lincomb_vec(ColPtrs A, int p, ColPtrs Y, int q,
-                                                     const double2* __restrict__ C, double beta, long long N) {
-    __shared__ double2 sC[kMaxCols * 32];
-    lincomb_vec_body<QB>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x, sC);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,25 +650,22 @@ static int grid_for(long long N, int threads, int cap = 4096) {
     return (int)std::max(1LL, std::min<long long>(b, cap));
 }
 
-static size_t gram_lds(int p, int q) {
-    return (size_t)kGramRows * (16 * ((p + 15) / 16) + 1 + 16 * ((q + 15) / 16) + 1) * sizeof(double2);
-}
-
 hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
                 double2* C, hipStream_t st) {
     if (p <= 0 || q <= 0) return hipSuccess;
-    int nb;
-    if (p + q >= 48) {
-        long long rpb = (N + max_blocks - 1) / max_blocks;
-        rpb = ((rpb + kGramRows - 1) / kGramRows) * kGramRows;
-        nb = (int)((N + rpb - 1) / rpb);
-        k_gram<<<nb, 256, gram_lds(p, q), st>>>(L, p, R, q, N, rpb, partial);
-    } else {
-        long long rpb;
-        int rows;
-        size_t lds;
-        nb = gram_job_blocks(p, q, N, max_blocks, &rpb, &rows, &lds);
-        k_gram_vec<<<nb, 256, lds, st>>>(L, p, R, q, N, rpb, rows, partial);
+    // one wave per 16 columns of L; about 2048 waves in all, whole depth-sized
+    // runs of 4-row groups per block
+    const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4;
+    const long long G = (N + 3) >> 2;
+    const int want = std::min(max_blocks, (2048 + TP - 1) / TP);
+    long long gpb = (G + want - 1) / want;
+    gpb = ((gpb + kGramDepth - 1) / kGramDepth) * kGramDepth;
+    const int nb = (int)std::max<long long>(1, (G + gpb - 1) / gpb);
+    switch (TQ) {
+        case 1: k_gram<1><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        case 2: k_gram<2><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        case 3: k_gram<3><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        default: k_gram<4><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
     }
     int cnt = p * q;
     k_reduce_partials<<<cnt, 256, 0, st>>>(partial, nb, cnt, C);
@@ -658,15 +675,16 @@ hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, d
 hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double2* C, double beta, long long N,
                    hipStream_t st) {
     if (q <= 0) return hipSuccess;
+    const int nb = (int)std::min<long long>(2048, std::max<long long>(1, (N + 127) / 128));
     if (q <= 32) {
-        int nb = grid_for(N, 256, 2048);
-        if (q <= 8) k_lincomb_vec<8><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-        else if (q <= 16) k_lincomb_vec<16><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
-        else k_lincomb_vec<32><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        const int qg = (q + 3) >> 2;
+        if (qg <= 2) k_lincomb_rows<2><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        else if (qg <= 4) k_lincomb_rows<4><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        else k_lincomb_rows<8><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
     } else {
         // 16-row tiles, four per workgroup per sweep
-        int nb = (int)std::min<long long>(2048, std::max<long long>(1, (N + 63) / 64));
-        k_lincomb<3><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
+        const int nt = (int)std::min<long long>(2048, std::max<long long>(1, (N + 63) / 64));
+        k_lincomb<3><<<nt, 256, 0, st>>>(A, p, Y, q, C, beta, N);
     }
     return hipGetLastError();
 }
