@@ -38,8 +38,8 @@ hipError_t randn(double2* out, long long count, unsigned long long seed, hipStre
 struct GramJob {
     ColPtrs L, R;
     int p, q;
-    long long N, rows_per_block;
-    int rows, nb, start, out_start;
+    long long N, groups_per_block;  // 4-row groups per block
+    int nb, start, out_start;
     long long part_off;  // offset of this job's partials (entries)
 };
 struct LinJob {
@@ -63,9 +63,10 @@ struct PreJob {
     int m, nb, start;
 };
 
-// blocks, rows per block, staged rows and LDS bytes of one gram job
-int gram_job_blocks(int p, int q, long long N, int max_blocks, long long* rows_per_block, int* rows, size_t* lds);
-hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, size_t lds,
+// blocks (at most max_blocks) and 4-row groups per block of one gram over N rows with p columns on the left
+int gram_job_blocks(int p, long long N, int max_blocks, long long* groups_per_block);
+// maxp, maxq: the widest p and q over the jobs
+hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, int maxp, int maxq,
                         double2* partial, double2* C, hipStream_t st);
 hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st);
 hipError_t residual_norm_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,

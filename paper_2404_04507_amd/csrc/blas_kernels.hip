@@ -26,92 +26,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// gram of the batched solver (one job per instance): the p x q output
-// is cut into 4 x 4 tiles; with ntile tiles, the 256 threads form 256 / ntile
-// row groups, each summing its own subset of the staged rows for its tile.
-// Rows are staged through LDS `rows` at a time; the row groups are summed in a
-// fixed order at the end (deterministic).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void gram_vec_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
-                                          long long rows_per_block, int rows, double2* __restrict__ partial, int bid,
-                                          unsigned char* smem) {
-    const int pl = p | 1, pr = q | 1;  // odd pitches
-    double2* sL = reinterpret_cast<double2*>(smem);
-    double2* sR = sL + rows * pl;
-    const int tid = threadIdx.x;
-    const int TP = (p + 3) >> 2, TQ = (q + 3) >> 2, ntile = TP * TQ;
-    const int ngroups = 256 / ntile;
-    const int grp = tid / ntile, tile = tid - grp * ntile;
-    const bool active = grp < ngroups;
-    const int ti = tile % TP, tj = tile / TP;
-    double2 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    const long long r0 = (long long)bid * rows_per_block;
-    const long long r1 = min(N, r0 + rows_per_block);
-    for (long long rb = r0; rb < r1; rb += rows) {
-        const int nr = (int)min((long long)rows, r1 - rb);
-        for (int e = tid; e < rows * p; e += 256) {
-            int c = e / rows, rr = e - c * rows;
-            sL[rr * pl + c] = rr < nr ? L.p[c][rb + rr] : make_double2(0.0, 0.0);
-        }
-        for (int e = tid; e < rows * q; e += 256) {
-            int c = e / rows, rr = e - c * rows;
-            sR[rr * pr + c] = rr < nr ? R.p[c][rb + rr] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        if (active) {
-            for (int rr = grp; rr < nr; rr += ngroups) {
-                double2 l[4], r[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    int i = 4 * ti + a;
-                    l[a] = i < p ? sL[rr * pl + i] : make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    int j = 4 * tj + b;
-                    r[b] = j < q ? sR[rr * pr + j] : make_double2(0.0, 0.0);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        acc[a][b].x += l[a].x * r[b].x + l[a].y * r[b].y;
-                        acc[a][b].y += l[a].x * r[b].y - l[a].y * r[b].x;
-                    }
-            }
-        }
-        __syncthreads();
-    }
-    // sum the row groups: red[grp][tile][16]
-    double2* red = reinterpret_cast<double2*>(smem);
-    if (active) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) red[((size_t)grp * ntile + tile) * 16 + a * 4 + b] = acc[a][b];
-    }
-    __syncthreads();
-    double2* out = partial + (size_t)bid * p * q;
-    for (int e = tid; e < ntile * 16; e += 256) {
-        int t = e >> 4, ab = e & 15;
-        int i = 4 * (t % TP) + (ab >> 2), j = 4 * (t / TP) + (ab & 3);
-        if (i >= p || j >= q) continue;
-        double2 sum = make_double2(0.0, 0.0);
-        for (int g = 0; g < ngroups; ++g) {
-            double2 v = red[((size_t)g * ntile + t) * 16 + ab];
-            sum.x += v.x;
-            sum.y += v.y;
-        }
-        out[(size_t)j * p + i] = sum;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// gram, unbatched: partial[b][j*p + i] = sum over the rows of block b of
+// gram: partial[b][j*p + i] = sum over the rows of block b of
 // conj(L_i[r]) R_j[r] on the matrix cores (v_mfma_f64_16x16x4f64), operands
 // loaded straight from HBM into the MFMA register layout (no LDS staging).
 // Lane l of a wave holds A[l%16][l/16] and B[l/16][l%16] and ends with result
@@ -137,8 +52,8 @@ __device__ __forceinline__ void gram_load(const double2* lp, const double2* cons
 }
 
 template <int TQ>
-__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long groups_per_block,
-                                              double2* __restrict__ partial) {
+__device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
+                                          long long groups_per_block, double2* __restrict__ partial, int bid) {
     constexpr int D = kGramDepth;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -157,7 +72,7 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
         acci[b] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
     const long long G = (N + 3) >> 2;
-    const long long g0 = (long long)blockIdx.x * groups_per_block, g1 = min(G, g0 + groups_per_block);
+    const long long g0 = (long long)bid * groups_per_block, g1 = min(G, g0 + groups_per_block);
     double2 lb[D], rb[D][TQ];
 #pragma unroll
     for (int d = 0; d < D; ++d) gram_load<TQ>(lp, rp, g0 + d, g1, N, lk, lb[d], rb[d]);
@@ -181,7 +96,7 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
             }
         }
     }
-    double2* out = partial + (size_t)blockIdx.x * p * q;
+    double2* out = partial + (size_t)bid * p * q;
 #pragma unroll
     for (int b = 0; b < TQ; ++b) {
         const int j = 16 * b + li;
@@ -191,6 +106,13 @@ __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q
             if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[b][v], acci[b][v]);
         }
     }
+}
+
+// one wave per 16 columns of L (blockDim = 64 ceil(p / 16))
+template <int TQ>
+__global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long groups_per_block,
+                                              double2* __restrict__ partial) {
+    gram_body<TQ>(L, p, R, q, N, groups_per_block, partial, blockIdx.x);
 }
 
 // C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
@@ -217,59 +139,23 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restri
 }
 
 // ---------------------------------------------------------------------------
-// lincomb of the batched solver, q <= 32: one row per thread,
-// all q outputs in registers, C in LDS (broadcast reads).
-// ---------------------------------------------------------------------------
-template <int QB>
-__device__ __forceinline__ void lincomb_vec_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
-                                             const double2* __restrict__ C, double beta, long long N, int bid, int nb,
-                                             double2* sC) {
-    for (int e = threadIdx.x; e < p * q; e += blockDim.x) sC[e] = C[e];
-    __syncthreads();
-    for (long long r = (long long)bid * blockDim.x + threadIdx.x; r < N; r += (long long)nb * blockDim.x) {
-        double2 acc[QB];
-#pragma unroll
-        for (int j = 0; j < QB; ++j) {
-            if (j < q && beta != 0.0) {
-                double2 y = Y.p[j][r];
-                acc[j] = make_double2(beta * y.x, beta * y.y);
-            } else {
-                acc[j] = make_double2(0.0, 0.0);
-            }
-        }
-        for (int i = 0; i < p; ++i) {
-            double2 a = A.p[i][r];
-#pragma unroll
-            for (int j = 0; j < QB; ++j) {
-                if (j < q) {
-                    double2 c = sC[j * p + i];
-                    acc[j].x += a.x * c.x - a.y * c.y;
-                    acc[j].y += a.x * c.y + a.y * c.x;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < QB; ++j)
-            if (j < q) Y.p[j][r] = acc[j];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// lincomb, unbatched, q <= 32: the four wavefronts of a workgroup share a pair
-// of 64-row strips (rows r and r + 64 per lane) and split the outputs, wave w
-// taking columns [w qg, w qg + qg) with qg = ceil(q / 4); C is read with
-// wave-uniform (scalar) loads, so no LDS.  Two rows per lane halve the scalar
-// loads per multiply-add and double the loads in flight.
+// lincomb, q <= 32: the four wavefronts of a workgroup share a pair of 64-row
+// strips (rows r and r + 64 per lane) and split the outputs, wave w taking
+// columns [w qg, w qg + qg) with qg = ceil(q / 4).  C (column-major, C[j*p + i])
+// is read at wave-uniform addresses: straight from global memory by scalar
+// loads when it is a kernel argument, else from an LDS copy.  Two rows per
+// lane halve the C reads per multiply-add and double the loads in flight.
 // ---------------------------------------------------------------------------
 template <int QG>
-__global__ void __launch_bounds__(256) k_lincomb_rows(ColPtrs A, int p, ColPtrs Y, int q,
-                                                      const double2* __restrict__ C, double beta, long long N) {
+__device__ __forceinline__ void lincomb_rows_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
+                                                  const double2* __restrict__ C, double beta, long long N, int bid,
+                                                  int nb) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int qg = (q + 3) >> 2;
     const int j0 = wave * qg;
     const int nj = max(0, min(qg, q - j0));
     if (nj == 0) return;
-    for (long long r = (long long)blockIdx.x * 128 + lane; r < N; r += (long long)gridDim.x * 128) {
+    for (long long r = (long long)bid * 128 + lane; r < N; r += (long long)nb * 128) {
         const long long r2 = r + 64;
         const bool ok2 = r2 < N;
         double2 acc[QG], acc2[QG];
@@ -309,6 +195,12 @@ __global__ void __launch_bounds__(256) k_lincomb_rows(ColPtrs A, int p, ColPtrs 
                 if (ok2) Y.p[j0 + j][r2] = acc2[j];
             }
     }
+}
+
+template <int QG>
+__global__ void __launch_bounds__(256) k_lincomb_rows(ColPtrs A, int p, ColPtrs Y, int q,
+                                                      const double2* __restrict__ C, double beta, long long N) {
+    lincomb_rows_body<QG>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,13 +429,14 @@ __device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, i
     return lo;
 }
 
+// blockDim = 64 ceil(max p / 16); the waves beyond a job's own L tiles have nothing to do
+template <int TQ>
 __global__ void __launch_bounds__(256) k_gram_batched(const GramJob* __restrict__ jobs, int njobs,
                                                       double2* __restrict__ partial) {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int j = find_job(jobs, njobs, blockIdx.x);
     const GramJob& jb = jobs[j];
-    gram_vec_body(jb.L, jb.p, jb.R, jb.q, jb.N, jb.rows_per_block, jb.rows, partial + jb.part_off,
-                  blockIdx.x - jb.start, smem);
+    if ((int)(threadIdx.x >> 6) * 16 >= jb.p) return;
+    gram_body<TQ>(jb.L, jb.p, jb.R, jb.q, jb.N, jb.groups_per_block, partial + jb.part_off, blockIdx.x - jb.start);
 }
 
 // one workgroup per output entry over all jobs (job j's entries start at out_start)
@@ -586,12 +479,14 @@ __global__ void __launch_bounds__(256) k_lincomb_batched(const LinJob* __restric
     lincomb_body<TQ>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sCt);
 }
 
-template <int QB>
-__global__ void __launch_bounds__(256) k_lincomb_vec_batched(const LinJob* __restrict__ jobs, int njobs) {
+template <int QG>
+__global__ void __launch_bounds__(256) k_lincomb_rows_batched(const LinJob* __restrict__ jobs, int njobs) {
     __shared__ double2 sC[kMaxCols * 32];
     const int j = find_job(jobs, njobs, blockIdx.x);
     const LinJob& jb = jobs[j];
-    lincomb_vec_body<QB>(jb.A, jb.p, jb.Y, jb.q, jb.C, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb, sC);
+    for (int e = threadIdx.x; e < jb.p * jb.q; e += blockDim.x) sC[e] = jb.C[e];
+    __syncthreads();
+    lincomb_rows_body<QG>(jb.A, jb.p, jb.Y, jb.q, sC, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb);
 }
 
 __global__ void __launch_bounds__(256) k_residual_norm_batched(const ResJob* __restrict__ jobs, int njobs,
@@ -653,14 +548,10 @@ static int grid_for(long long N, int threads, int cap = 4096) {
 hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
                 double2* C, hipStream_t st) {
     if (p <= 0 || q <= 0) return hipSuccess;
-    // one wave per 16 columns of L; about 2048 waves in all, whole depth-sized
-    // runs of 4-row groups per block
+    // one wave per 16 columns of L, about 2048 waves in all
     const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4;
-    const long long G = (N + 3) >> 2;
-    const int want = std::min(max_blocks, (2048 + TP - 1) / TP);
-    long long gpb = (G + want - 1) / want;
-    gpb = ((gpb + kGramDepth - 1) / kGramDepth) * kGramDepth;
-    const int nb = (int)std::max<long long>(1, (G + gpb - 1) / gpb);
+    long long gpb;
+    const int nb = gram_job_blocks(p, N, max_blocks, &gpb);
     switch (TQ) {
         case 1: k_gram<1><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
         case 2: k_gram<2><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
@@ -675,7 +566,7 @@ hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, d
 hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double2* C, double beta, long long N,
                    hipStream_t st) {
     if (q <= 0) return hipSuccess;
-    const int nb = (int)std::min<long long>(2048, std::max<long long>(1, (N + 127) / 128));
+    const int nb = (int)std::min<long long>(4096, std::max<long long>(1, (N + 127) / 128));
     if (q <= 32) {
         const int qg = (q + 3) >> 2;
         if (qg <= 2) k_lincomb_rows<2><<<nb, 256, 0, st>>>(A, p, Y, q, C, beta, N);
@@ -720,33 +611,40 @@ hipError_t precond(const ColPtrs& R, const ColPtrs& W, int m, const double* M, l
     return hipGetLastError();
 }
 
-int gram_job_blocks(int p, int q, long long N, int max_blocks, long long* rows_per_block, int* rows, size_t* lds) {
-    const int pl = p | 1, pr = q | 1;
-    int r = (int)std::min<long long>(128, (48 * 1024) / ((pl + pr) * (long long)sizeof(double2)));
-    r = std::max(r, 8);
-    long long rpb = (N + max_blocks - 1) / max_blocks;
-    rpb = ((rpb + r - 1) / r) * r;
-    int ntile = ((p + 3) / 4) * ((q + 3) / 4);
-    *rows_per_block = rpb;
-    *rows = r;
-    *lds = std::max((size_t)r * (pl + pr) * sizeof(double2), (size_t)(256 / ntile) * ntile * 16 * sizeof(double2));
-    return (int)((N + rpb - 1) / rpb);
+int gram_job_blocks(int p, long long N, int max_blocks, long long* groups_per_block) {
+    const int TP = (p + 15) >> 4;
+    const long long G = (N + 3) >> 2;
+    const int want = std::max(1, std::min(max_blocks, (2048 + TP - 1) / TP));
+    long long gpb = (G + want - 1) / want;
+    gpb = std::max<long long>(kGramDepth, ((gpb + kGramDepth - 1) / kGramDepth) * kGramDepth);
+    *groups_per_block = gpb;
+    return (int)std::max<long long>(1, (G + gpb - 1) / gpb);
 }
 
-hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, size_t lds,
+hipError_t gram_batched(const GramJob* jobs, int njobs, int total_blocks, int total_out, int maxp, int maxq,
                         double2* partial, double2* C, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    k_gram_batched<<<total_blocks, 256, lds, st>>>(jobs, njobs, partial);
+    const int threads = 64 * ((maxp + 15) >> 4), TQ = (maxq + 15) >> 4;
+    switch (TQ) {
+        case 1: k_gram_batched<1><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        case 2: k_gram_batched<2><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        case 3: k_gram_batched<3><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        default: k_gram_batched<4><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+    }
     k_reduce_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, C);
     return hipGetLastError();
 }
 
 hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st) {
     if (njobs <= 0) return hipSuccess;
-    if (maxq <= 8) k_lincomb_vec_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else if (maxq <= 16) k_lincomb_vec_batched<16><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else if (maxq <= 32) k_lincomb_vec_batched<32><<<total_blocks, 256, 0, st>>>(jobs, njobs);
-    else k_lincomb_batched<3><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    const int qg = (maxq + 3) >> 2;
+    if (maxq <= 32) {
+        if (qg <= 2) k_lincomb_rows_batched<2><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+        else if (qg <= 4) k_lincomb_rows_batched<4><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+        else k_lincomb_rows_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    } else {
+        k_lincomb_batched<3><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    }
     return hipGetLastError();
 }
 

@@ -957,8 +957,7 @@ static int batch_gram(BatchOps& bo, const std::vector<GramReq>& reqs, std::vecto
     std::vector<GramJob> jobs;
     std::vector<Sub> subs;
     long long part = 0;
-    int blocks = 0, outs = 0;
-    size_t lds = 0;
+    int blocks = 0, outs = 0, maxp = 1, maxq = 1;
     for (int r = 0; r < (int)reqs.size(); ++r) {
         const int p = (int)reqs[r].L.size(), q = (int)reqs[r].R.size();
         for (int i0 = 0; i0 < p; i0 += kMaxCols)
@@ -969,9 +968,9 @@ static int batch_gram(BatchOps& bo, const std::vector<GramReq>& reqs, std::vecto
                 for (int i = 0; i < jb.p; ++i) jb.L.p[i] = reqs[r].L[i0 + i];
                 for (int j = 0; j < jb.q; ++j) jb.R.p[j] = reqs[r].R[j0 + j];
                 jb.N = reqs[r].N;
-                size_t l = 0;
-                jb.nb = gram_job_blocks(jb.p, jb.q, jb.N, 256, &jb.rows_per_block, &jb.rows, &l);
-                lds = std::max(lds, l);
+                jb.nb = gram_job_blocks(jb.p, jb.N, 256, &jb.groups_per_block);
+                maxp = std::max(maxp, jb.p);
+                maxq = std::max(maxq, jb.q);
                 jb.start = blocks;
                 jb.out_start = outs;
                 jb.part_off = part;
@@ -994,7 +993,7 @@ static int batch_gram(BatchOps& bo, const std::vector<GramReq>& reqs, std::vecto
     if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
     std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GramJob));
     CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GramJob), hipMemcpyHostToDevice, bo.st));
-    CHECK_HIP(gram_batched((const GramJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs, lds,
+    CHECK_HIP(gram_batched((const GramJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs, maxp, maxq,
                            (double2*)bo.d_partial.ptr, (double2*)bo.d_out.ptr, bo.st));
     CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, (size_t)outs * sizeof(double2), hipMemcpyDeviceToHost, bo.st));
     CHECK_HIP(hipStreamSynchronize(bo.st));
@@ -1037,7 +1036,7 @@ static int batch_lincomb(BatchOps& bo, const std::vector<LinReq>& reqs) {
             for (int j = 0; j < jb.q; ++j) jb.Y.p[j] = r.Y[j0 + j];
             jb.beta = r.beta;
             jb.N = r.N;
-            jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (r.N + 255) / 256));
+            jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (r.N + 127) / 128));
             jb.start = blocks;
             blocks += jb.nb;
             maxq = std::max(maxq, jb.q);
