@@ -268,15 +268,22 @@ int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* 
  * Matrices are complex float64, column-major, interleaved (re, im), n x n.
  * iwfpm_dense_geneig - A c = w B c for Hermitian A and Hermitian positive
  *   definite B (B = NULL means the identity): Cholesky of B, reduction to a
- *   standard problem, cyclic Jacobi.  w: n ascending eigenvalues; C: the
+ *   standard problem, Householder tridiagonalisation and implicit QL (cyclic
+ *   Jacobi if QL does not converge).  w: n ascending eigenvalues; C: the
  *   B-orthonormal eigenvectors.  Errors: ERR_ARG (n < 1 or n > 512),
  *   ERR_NUMERIC (B not positive definite).
  * iwfpm_dense_svqb - for a Gram matrix G = V^H V (k x k) returns T (k x rank)
  *   with (V T)^H (V T) = I, dropping directions whose scaled eigenvalue is
  *   below 1e-12 of the largest.  T must hold k*k entries.
+ * iwfpm_dense_heev_lowest - the Rayleigh-Ritz step's eigensolver: all n
+ *   eigenvalues of the Hermitian A (w, ascending) and orthonormal
+ *   eigenvectors of the nv lowest (V, n x nv), rebuilt from the stored
+ *   reflectors and the recorded QL rotations for those columns only.
+ *   Errors: ERR_ARG (n < 1, n > 512, nv < 0 or nv > n).
  */
 int iwfpm_dense_geneig(int n, const double* A, const double* B, double* w, double* C);
 int iwfpm_dense_svqb(int k, const double* G, double* T, int* rank);
+int iwfpm_dense_heev_lowest(int n, int nv, const double* A, double* w, double* V);
 
 /*
  * Learned preconditioner.  The paper preconditions LOBPCG with the diagonal

@@ -25,7 +25,8 @@ _LIB = None
 EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_destroy", "iwfpm_dof",
             "iwfpm_grid_shape", "iwfpm_indices", "iwfpm_kinetic", "iwfpm_norm_bound", "iwfpm_apply",
             "iwfpm_apply_prec", "iwfpm_default_eigs_opts", "iwfpm_eigs", "iwfpm_profile",
-            "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb", "iwfpm_tune", "iwfpm_schedule",
+            "iwfpm_profile_read", "iwfpm_dense_geneig", "iwfpm_dense_svqb", "iwfpm_dense_heev_lowest",
+            "iwfpm_tune", "iwfpm_schedule",
             "iwfpm_batch_create", "iwfpm_batch_apply", "iwfpm_batch_destroy", "iwfpm_eigs_batched",
             "iwfpm_conv", "iwfpm_default_learned_opts", "iwfpm_default_train_opts", "iwfpm_learned_create",
             "iwfpm_learned_destroy", "iwfpm_learned_nparams", "iwfpm_learned_get", "iwfpm_learned_set",
@@ -119,6 +120,7 @@ def load_library():
     lib.iwfpm_schedule.argtypes = [vp, ctypes.c_int, ip]
     lib.iwfpm_dense_geneig.argtypes = [ctypes.c_int, dp, dp, dp, dp]
     lib.iwfpm_dense_svqb.argtypes = [ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    lib.iwfpm_dense_heev_lowest.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
     lib.iwfpm_default_eigs_opts.argtypes = [ctypes.POINTER(_EigsOpts)]
     lib.iwfpm_default_eigs_opts.restype = None
     lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
@@ -186,6 +188,18 @@ def dense_geneig(A, B=None):
                                    _ptr(w, ctypes.c_double), _ptr(C, ctypes.c_double))
     _check(st, "iwfpm_dense_geneig")
     return w, C.view(np.complex128).reshape(n, n, order="F")
+
+
+def dense_heev_lowest(A, nv):
+    """The Rayleigh-Ritz step's eigensolver: all eigenvalues, eigenvectors of the nv lowest."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    a = _f64(np.asfortranarray(A).reshape(-1, order="F").view(np.float64))
+    w = np.zeros(n)
+    V = np.zeros(2 * n * max(nv, 1))
+    _check(_lib().iwfpm_dense_heev_lowest(n, int(nv), _ptr(a, ctypes.c_double), _ptr(w, ctypes.c_double),
+                                          _ptr(V, ctypes.c_double)), "iwfpm_dense_heev_lowest")
+    return w, V.view(np.complex128)[:n * nv].reshape(n, nv, order="F")
 
 
 def dense_svqb(G):

@@ -273,6 +273,156 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
     return true;
 }
 
+// Hermitian eigenvalues (all, ascending) and the eigenvectors of the nv
+// lowest (V: n x nv), for the Rayleigh-Ritz step, which keeps only those.  Householder reduction of the lower triangle
+// to a real symmetric tridiagonal matrix (the reflectors kept, not
+// multiplied out), the implicit QL iteration with Wilkinson shifts on the
+// eigenvalues alone (its plane rotations recorded), then the selected
+// eigenvectors rebuilt from unit vectors by the rotations in reverse order,
+// the diagonal phases and the reflectors in reverse order.
+static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
+    std::vector<cd> U((size_t)n * n, 0.0);  // reflector k in column k (rows k+1..n-1)
+    std::vector<char> has(n, 0);
+    std::vector<cd> sub(n, 0.0), pv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const cd* ak = &A[(size_t)k * n];
+        double xn = 0.0;
+        for (int i = k + 1; i < n; ++i) xn += std::norm(ak[i]);
+        xn = std::sqrt(xn);
+        const cd x0 = ak[k + 1];
+        const double tail = xn * xn - std::norm(x0);
+        if (xn == 0.0 || tail <= 1e-300) {
+            sub[k] = x0;
+            continue;
+        }
+        const cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
+        const cd alpha = -ph * xn;
+        cd* u = &U[(size_t)k * n];
+        double un = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            u[i] = ak[i];
+            if (i == k + 1) u[i] -= alpha;
+            un += std::norm(u[i]);
+        }
+        const double inv = 1.0 / std::sqrt(un);
+        for (int i = k + 1; i < n; ++i) u[i] *= inv;
+        has[k] = 1;
+        sub[k] = alpha;
+        // p = A22 u (full trailing block, column loops)
+        for (int i = k + 1; i < n; ++i) pv[i] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const cd* aj = &A[(size_t)j * n];
+            const cd uj = u[j];
+            for (int i = k + 1; i < n; ++i) pv[i] += aj[i] * uj;
+        }
+        double K = 0.0;
+        for (int i = k + 1; i < n; ++i) K += (std::conj(u[i]) * pv[i]).real();
+        for (int i = k + 1; i < n; ++i) pv[i] -= K * u[i];
+        // A22 <- A22 - 2 (u w^H + w u^H)
+        for (int j = k + 1; j < n; ++j) {
+            cd* aj = &A[(size_t)j * n];
+            const cd a = 2.0 * std::conj(pv[j]), b = 2.0 * std::conj(u[j]);
+            for (int i = k + 1; i < n; ++i) aj[i] -= u[i] * a + pv[i] * b;
+        }
+    }
+    if (n >= 2) sub[n - 2] = A[(size_t)(n - 1) + (size_t)(n - 2) * n];
+    // real tridiagonal: d, and e made real by the diagonal phases ph
+    std::vector<double> d(n), e(n, 0.0);
+    std::vector<cd> phs(n, 1.0);
+    for (int k = 0; k < n; ++k) {
+        d[k] = A[k + (size_t)k * n].real();
+        if (k + 1 < n) {
+            const double a = std::abs(sub[k]);
+            phs[k + 1] = a > 0.0 ? phs[k] * (sub[k] / a) : phs[k];
+            e[k] = a;
+        }
+    }
+    // implicit QL with Wilkinson shifts (e[k] couples k and k+1), rotations recorded
+    struct Rot {
+        int i;
+        double c, s;
+    };
+    std::vector<Rot> rots;
+    rots.reserve((size_t)4 * n * n);
+    for (int l = 0; l < n; ++l) {
+        int iter = 0, m;
+        do {
+            for (m = l; m < n - 1; ++m) {
+                double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+            }
+            if (m != l) {
+                if (++iter > 80) return false;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = std::hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+                double sn = 1.0, cs = 1.0, pp = 0.0;
+                bool deflated = false;
+                for (int i = m - 1; i >= l; --i) {
+                    double f = sn * e[i], b = cs * e[i];
+                    r = std::hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= pp;
+                        e[m] = 0.0;
+                        deflated = true;
+                        break;
+                    }
+                    sn = f / r;
+                    cs = g / r;
+                    g = d[i + 1] - pp;
+                    r = (d[i] - g) * sn + 2.0 * cs * b;
+                    pp = sn * r;
+                    d[i + 1] = g + pp;
+                    g = cs * r - b;
+                    rots.push_back({i, cs, sn});
+                }
+                if (deflated) continue;
+                d[l] -= pp;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        } while (m != l);
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    w.resize(n);
+    for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
+    nv = std::max(0, std::min(nv, n));
+    // Y (row-major n x nv) = the rotations applied in reverse to the selected unit vectors
+    std::vector<double> Y((size_t)n * nv, 0.0);
+    for (int c = 0; c < nv; ++c) Y[(size_t)idx[c] * nv + c] = 1.0;
+    for (size_t t = rots.size(); t-- > 0;) {
+        const Rot& q = rots[t];
+        double* yi = &Y[(size_t)q.i * nv];
+        double* yi1 = yi + nv;
+        for (int c = 0; c < nv; ++c) {
+            const double a = yi[c], b = yi1[c];
+            yi[c] = q.c * a + q.s * b;
+            yi1[c] = q.c * b - q.s * a;
+        }
+    }
+    // V = H_0 ... H_{n-3} diag(ph) Y
+    V.assign((size_t)n * nv, 0.0);
+    for (int c = 0; c < nv; ++c) {
+        cd* vc = &V[(size_t)c * n];
+        for (int i = 0; i < n; ++i) vc[i] = phs[i] * Y[(size_t)i * nv + c];
+    }
+    for (int k = n - 3; k >= 0; --k) {
+        if (!has[k]) continue;
+        const cd* u = &U[(size_t)k * n];
+        for (int c = 0; c < nv; ++c) {
+            cd* vc = &V[(size_t)c * n];
+            cd s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += std::conj(u[i]) * vc[i];
+            s *= 2.0;
+            for (int i = k + 1; i < n; ++i) vc[i] -= u[i] * s;
+        }
+    }
+    return true;
+}
+
 // Hermitian eigensolver used throughout: Householder + QL, Jacobi as fallback
 void heev(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) {
     if (!householder_ql(A, n, w, V)) jacobi_eigh(A, n, w, V);
@@ -584,8 +734,8 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
         }
     for (int j = 0; j < m; ++j) A[j + (size_t)j * ns] = theta[j];
     hermitian_part(A, ns);
-    std::vector<cd> Cfull;
-    heev(A, ns, th, Cfull);
+    std::vector<cd> Cfull;  // ns x m: the Ritz vectors of the m lowest values
+    if (!heev_lowest(A, ns, m, th, Cfull)) heev(A, ns, th, Cfull);
     std::vector<cd> Z((size_t)ns * m, 0.0);
     for (int a = 0; a < ma; ++a)
         for (int i = m; i < ns; ++i) Z[i + (size_t)a * ns] = Cfull[i + (size_t)act[a] * ns];
@@ -1570,6 +1720,20 @@ int iwfpm_dense_geneig(int n, const double* A, const double* B, double* w, doubl
     for (size_t i = 0; i < c.size(); ++i) {
         C[2 * i] = c[i].real();
         C[2 * i + 1] = c[i].imag();
+    }
+    return IWFPM_OK;
+}
+
+int iwfpm_dense_heev_lowest(int n, int nv, const double* A, double* w, double* V) {
+    if (n < 1 || n > 512 || nv < 0 || nv > n || !A || !w || (nv > 0 && !V)) return IWFPM_ERR_ARG;
+    std::vector<cd> a((size_t)n * n), v;
+    for (size_t i = 0; i < a.size(); ++i) a[i] = cd(A[2 * i], A[2 * i + 1]);
+    std::vector<double> th;
+    if (!heev_lowest(a, n, nv, th, v)) heev(a, n, th, v);
+    for (int i = 0; i < n; ++i) w[i] = th[i];
+    for (size_t i = 0; i < (size_t)n * nv; ++i) {
+        V[2 * i] = v[i].real();
+        V[2 * i + 1] = v[i].imag();
     }
     return IWFPM_OK;
 }

@@ -129,7 +129,7 @@ def test_duplicate_modes_are_merged():
 
 @pytest.mark.parametrize("n", [1, 2, 7, 48, 96])
 def test_dense_geneig_matches_lapack(n):
-    """Cholesky + cyclic Jacobi against LAPACK's generalised Hermitian eigensolver."""
+    """Cholesky + Householder/QL against LAPACK's generalised Hermitian eigensolver."""
     import scipy.linalg as sla
     rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
@@ -160,3 +160,40 @@ def test_dense_svqb_drops_dependent_directions():
     assert T.shape == (7, 5)
     Q = V @ T
     assert np.allclose(Q.conj().T @ Q, np.eye(5), atol=1e-10)
+
+
+@pytest.mark.parametrize("n,nv", [(1, 1), (2, 0), (7, 3), (48, 16), (60, 20), (64, 64)])
+def test_dense_heev_lowest_matches_lapack(n, nv):
+    """Eigenvalues against LAPACK; the nv returned vectors are orthonormal
+    eigenvectors of the nv lowest values (checked through residuals and against
+    LAPACK's vectors up to phase, the spectrum being simple here)."""
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = A + A.conj().T
+    w, V = lib.dense_heev_lowest(A, nv)
+    wr, Vr = np.linalg.eigh(A)
+    scale = np.abs(wr).max()
+    assert np.allclose(w, wr, rtol=0, atol=1e-13 * scale)
+    assert V.shape == (n, nv)
+    if nv:
+        assert np.allclose(V.conj().T @ V, np.eye(nv), atol=1e-12)
+        assert np.abs(A @ V - V * w[None, :nv]).max() < 1e-12 * scale
+        overlap = np.abs(np.sum(Vr[:, :nv].conj() * V, axis=0))
+        assert np.allclose(overlap, 1.0, atol=1e-10)
+
+
+def test_dense_heev_lowest_degenerate_cluster():
+    """A multiple eigenvalue: the returned vectors span the LAPACK eigenspace."""
+    rng = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)))
+    vals = np.array([-1.0, -1.0, -1.0, 0.5, 0.5, 2.0, 3.0, 3.0, 4.0, 5.0, 6.0, 7.0])
+    A = (Q * vals) @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    w, V = lib.dense_heev_lowest(A, 5)
+    assert np.allclose(w, np.sort(vals), atol=1e-13)
+    assert np.allclose(V.conj().T @ V, np.eye(5), atol=1e-12)
+    # projector onto the span of the 5 lowest eigenvectors
+    P = Q[:, :5] @ Q[:, :5].conj().T
+    assert np.allclose(P @ V, V, atol=1e-12)
+    with pytest.raises(lib.IwfpmError):
+        lib.dense_heev_lowest(A, 13)
