@@ -781,6 +781,42 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
     return mpn;
 }
 
+// One-pass orthonormalisation of the new directions W (ma columns) against
+// the orthonormal [X P] (nx columns), in coefficient space.  Gall is the Gram
+// [X P W]^H W ((nx + ma) x ma).  With G = [X P]^H W, the complement W - [X P] G
+// has the Gram W^H W - G^H G; when no column loses more than a factor 10 of
+// its norm to [X P] (cancellation at most 100 ulp), SVQB of that Gram gives T
+// and the new block is [X P W] Cm with Cm = [-G T; T] ((nx + ma) x mw).
+// Returns false otherwise (the caller then projects explicitly, twice).
+static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std::vector<cd>& Cm, int& mw) {
+    const int ld = nx + ma;
+    std::vector<cd> Gc((size_t)ma * ma);
+    for (int j = 0; j < ma; ++j)
+        for (int i = 0; i < ma; ++i) {
+            cd acc = Gall[(size_t)(nx + i) + (size_t)j * ld];
+            for (int k = 0; k < nx; ++k) acc -= std::conj(Gall[k + (size_t)i * ld]) * Gall[k + (size_t)j * ld];
+            Gc[i + (size_t)j * ma] = acc;
+        }
+    for (int j = 0; j < ma; ++j) {
+        const double full = Gall[(size_t)(nx + j) + (size_t)j * ld].real(), rest = Gc[j + (size_t)j * ma].real();
+        if (!std::isfinite(full) || !std::isfinite(rest) || !(rest > 0.01 * full)) return false;
+    }
+    hermitian_part(Gc, ma);
+    std::vector<cd> T;
+    mw = svqb(Gc, ma, T, 1e-10);
+    if (mw < 1) return false;
+    Cm.assign((size_t)ld * mw, 0.0);
+    for (int c = 0; c < mw; ++c) {
+        for (int i = 0; i < ma; ++i) Cm[(size_t)(nx + i) + (size_t)c * ld] = T[i + (size_t)c * ma];
+        for (int k = 0; k < nx; ++k) {
+            cd acc = 0.0;
+            for (int i = 0; i < ma; ++i) acc += Gall[k + (size_t)i * ld] * T[i + (size_t)c * ma];
+            Cm[k + (size_t)c * ld] = -acc;
+        }
+    }
+    return true;
+}
+
 static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
                iwfpm_stats* stats, hipStream_t st, Capture* cap = nullptr) {
     const int nev = o.nev;
@@ -828,7 +864,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     // P holds mp orthonormal columns orthogonal to X (built in coefficient space)
     int mp = 0;
     std::vector<double> eta(m, 1.0);
-    int it = 0, polished = 0, fallback = 0;
+    int it = 0, polished = 0, fallback = 0, reortho = 0;
     double best_eta = 1e300;
     int best_it = 0;
     int status = IWFPM_OK;
@@ -870,8 +906,8 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             worst = std::max(worst, eta[j]);
         }
         if (verbose)
-            std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d\n", it,
-                         prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp);
+            std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n",
+                         it, prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
         if (conv == nev) {
             if (prec == 0 || !can64) break;
             // confirm with float64 applies (Rayleigh-Ritz of X with the float64 H)
@@ -912,6 +948,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         if (prec == 0 && p->opts.precision == 1) ++polished;
 
         // active set, W = M R_A
+        bool lp_used = false;
         std::vector<int> act;
         for (int j = 0; j < m; ++j)
             if (eta[j] > o.tol) act.push_back(j);
@@ -932,38 +969,56 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
                 }
             }
             if (!used_learned) CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
-            if (used_learned) {
-                // a non-finite learned direction falls back to M for the rest of the solve
-                std::vector<cd> G;
-                if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
-                bool finite = true;
-                for (int j = 0; j < ma; ++j) finite = finite && std::isfinite(G[j + (size_t)j * ma].real());
-                if (!finite) {
-                    fallback = 1;
-                    lp = nullptr;
-                    CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
-                }
-            }
+            lp_used = used_learned;
         }
         // P: built last iteration from the then-active Ritz vectors only,
         // orthonormal and orthogonal to X
         std::vector<double2*> Pa = cols(c, B_P, 0, mp), HPa = cols(c, B_HP, 0, mp);
         const int mq = mp;
-        // W <- W - [X P_A] ([X P_A]^H W), twice; then SVQB
+        // W <- orthonormal basis of the part of W orthogonal to [X P_A]: one
+        // Gram and one combination when little cancels, else the explicit
+        // projection twice and SVQB
         int mw = 0;
         {
             std::vector<double2*> XP = cols(c, B_X, 0, m);
             XP.insert(XP.end(), Pa.begin(), Pa.end());
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<cd> G;
-                if ((rc = host_gram(c, XP, cols(c, B_W, 0, ma), G))) return rc;
-                for (auto& g : G) g = -g;
-                if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G, (int)XP.size(), 0, 1.0))) return rc;
+            const int nx = (int)XP.size();
+            std::vector<double2*> XPW = XP;
+            for (int j = 0; j < ma; ++j) XPW.push_back(c.col(B_W, j));
+            std::vector<cd> Gall, Cm;
+            if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
+            if (lp_used) {
+                // a non-finite learned direction falls back to M for the rest of the solve
+                bool finite = true;
+                for (int j = 0; j < ma; ++j)
+                    finite = finite && std::isfinite(Gall[(size_t)(nx + j) + (size_t)j * (nx + ma)].real());
+                if (!finite) {
+                    fallback = 1;
+                    lp = nullptr;
+                    ColPtrs r{}, w{};
+                    for (int a = 0; a < ma; ++a) {
+                        r.p[a] = c.col(B_T1, act[a]);
+                        w.p[a] = c.col(B_W, a);
+                    }
+                    CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
+                    if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
+                }
             }
-            std::vector<cd> G, T;
-            if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
-            mw = svqb(G, ma, T, 1e-10);
-            if ((rc = dev_lincomb(c, cols(c, B_W, 0, ma), cols(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
+            if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
+                if ((rc = dev_lincomb(c, XPW, cols(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
+            } else {
+                ++reortho;
+                for (int pass = 0; pass < 2; ++pass) {
+                    std::vector<cd> G;
+                    if ((rc = host_gram(c, XP, cols(c, B_W, 0, ma), G))) return rc;
+                    for (auto& g : G) g = -g;
+                    if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G, nx, 0, 1.0))) return rc;
+                }
+                std::vector<cd> G, T;
+                if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
+                mw = svqb(G, ma, T, 1e-10);
+                if ((rc = dev_lincomb(c, cols(c, B_W, 0, ma), cols(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
+            }
             std::swap(s->buf[B_W], s->buf[B_T1]);
         }
         if ((rc = apply_block(c, B_W, B_HW, mw, prec, stats))) return rc;
@@ -1528,43 +1583,76 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
                 CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
             }
         }
-        // W <- W - [X P] ([X P]^H W), twice
-        for (int pass = 0; pass < 2; ++pass) {
-            std::vector<GramReq> g;
-            std::vector<std::vector<double2*>> XP(iter.size());
-            for (size_t k = 0; k < iter.size(); ++k) {
-                BInst& b = in[iter[k]];
-                XP[k] = cols(b.c, B_X, 0, m);
-                auto P = cols(b.c, B_P, 0, b.mq);
-                XP[k].insert(XP[k].end(), P.begin(), P.end());
-                g.push_back({XP[k], cols(b.c, B_W, 0, b.ma), b.c.N});
-            }
-            std::vector<std::vector<cd>> G;
-            if ((rc = batch_gram(bo, g, G))) return rc;
-            std::vector<LinReq> l;
-            for (size_t k = 0; k < iter.size(); ++k) {
-                for (auto& v : G[k]) v = -v;
-                BInst& b = in[iter[k]];
-                l.push_back({XP[k], cols(b.c, B_W, 0, b.ma), &G[k], (int)XP[k].size(), 0, 1.0, b.c.N});
-            }
-            if ((rc = batch_lincomb(bo, l))) return rc;
-        }
-        // SVQB of W into T1
+        // W <- orthonormal basis of the part of W orthogonal to [X P]: one
+        // Gram [X P W]^H W for all instances, one combination for those where
+        // little cancels; the others project explicitly, twice, then SVQB
         {
             std::vector<GramReq> g;
-            for (int i : iter) g.push_back({cols(in[i].c, B_W, 0, in[i].ma), cols(in[i].c, B_W, 0, in[i].ma), in[i].c.N});
-            std::vector<std::vector<cd>> G;
-            if ((rc = batch_gram(bo, g, G))) return rc;
+            std::vector<std::vector<double2*>> XPW(iter.size());
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                XPW[k] = cols(b.c, B_X, 0, m);
+                auto P = cols(b.c, B_P, 0, b.mq);
+                XPW[k].insert(XPW[k].end(), P.begin(), P.end());
+                auto Wc = cols(b.c, B_W, 0, b.ma);
+                XPW[k].insert(XPW[k].end(), Wc.begin(), Wc.end());
+                g.push_back({XPW[k], Wc, b.c.N});
+            }
+            std::vector<std::vector<cd>> Gall;
+            if ((rc = batch_gram(bo, g, Gall))) return rc;
+            std::vector<char> one(iter.size(), 0);
+            std::vector<std::vector<cd>> Cm(iter.size());
             parallel_for((int)iter.size(), [&](int k) {
                 BInst& b = in[iter[k]];
-                b.mw = svqb(G[k], b.ma, b.T, 1e-10);
+                one[k] = m + b.mq + b.ma <= kMaxCols && ortho_coefficients(Gall[k], m + b.mq, b.ma, Cm[k], b.mw);
             });
+            std::vector<size_t> two;
             std::vector<LinReq> l;
-            for (int i : iter) {
-                BInst& b = in[i];
-                l.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                if (one[k])
+                    l.push_back({XPW[k], cols(b.c, B_T1, 0, b.mw), &Cm[k], m + b.mq + b.ma, 0, 0.0, b.c.N});
+                else
+                    two.push_back(k);
             }
             if ((rc = batch_lincomb(bo, l))) return rc;
+            if (!two.empty()) {
+                for (int pass = 0; pass < 2; ++pass) {
+                    std::vector<GramReq> g2;
+                    std::vector<std::vector<double2*>> XP(two.size());
+                    for (size_t t = 0; t < two.size(); ++t) {
+                        BInst& b = in[iter[two[t]]];
+                        XP[t].assign(XPW[two[t]].begin(), XPW[two[t]].begin() + m + b.mq);
+                        g2.push_back({XP[t], cols(b.c, B_W, 0, b.ma), b.c.N});
+                    }
+                    std::vector<std::vector<cd>> G;
+                    if ((rc = batch_gram(bo, g2, G))) return rc;
+                    std::vector<LinReq> l2;
+                    for (size_t t = 0; t < two.size(); ++t) {
+                        for (auto& v : G[t]) v = -v;
+                        BInst& b = in[iter[two[t]]];
+                        l2.push_back({XP[t], cols(b.c, B_W, 0, b.ma), &G[t], (int)XP[t].size(), 0, 1.0, b.c.N});
+                    }
+                    if ((rc = batch_lincomb(bo, l2))) return rc;
+                }
+                std::vector<GramReq> g2;
+                for (size_t k : two) {
+                    BInst& b = in[iter[k]];
+                    g2.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_W, 0, b.ma), b.c.N});
+                }
+                std::vector<std::vector<cd>> G;
+                if ((rc = batch_gram(bo, g2, G))) return rc;
+                parallel_for((int)two.size(), [&](int t) {
+                    BInst& b = in[iter[two[t]]];
+                    b.mw = svqb(G[t], b.ma, b.T, 1e-10);
+                });
+                std::vector<LinReq> l2;
+                for (size_t k : two) {
+                    BInst& b = in[iter[k]];
+                    l2.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
+                }
+                if ((rc = batch_lincomb(bo, l2))) return rc;
+            }
             for (int i : iter) std::swap(in[i].s->buf[B_W], in[i].s->buf[B_T1]);
         }
         // HW = H W
