@@ -131,6 +131,13 @@ static void jacobi_eigh(std::vector<cd> A, int n, std::vector<double>& w, std::v
     V.swap(Vs);
 }
 
+// sqrt(f^2 + g^2) without the cost of std::hypot when the squares can neither
+// overflow nor underflow
+static inline double pyth(double f, double g) {
+    const double m = std::max(std::fabs(f), std::fabs(g));
+    return (m > 1e-150 && m < 1e150) ? std::sqrt(f * f + g * g) : std::hypot(f, g);
+}
+
 // Hermitian eigen-decomposition A = V diag(w) V^H (w ascending) by Householder
 // reduction to a real symmetric tridiagonal matrix followed by the implicit QL
 // iteration with Wilkinson shifts; false if QL does not converge.
@@ -216,14 +223,14 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
             if (m != l) {
                 if (++iter > 80) return false;
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
+                double r = pyth(g, 1.0);
                 g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
                 double sn = 1.0, cs = 1.0, pp = 0.0;
                 int i;
                 bool deflated = false;
                 for (i = m - 1; i >= l; --i) {
                     double f = sn * e[i], b = cs * e[i];
-                    r = std::hypot(f, g);
+                    r = pyth(f, g);
                     e[i + 1] = r;
                     if (r == 0.0) {
                         d[i + 1] -= pp;
@@ -273,23 +280,30 @@ static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std
     return true;
 }
 
-// Hermitian eigenvalues (all, ascending) and the eigenvectors of the nv
-// lowest (V: n x nv), for the Rayleigh-Ritz step, which keeps only those.  Householder reduction of the lower triangle
-// to a real symmetric tridiagonal matrix (the reflectors kept, not
-// multiplied out), the implicit QL iteration with Wilkinson shifts on the
-// eigenvalues alone (its plane rotations recorded), then the selected
-// eigenvectors rebuilt from unit vectors by the rotations in reverse order,
-// the diagonal phases and the reflectors in reverse order.
-static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
-    std::vector<cd> U((size_t)n * n, 0.0);  // reflector k in column k (rows k+1..n-1)
-    std::vector<char> has(n, 0);
-    std::vector<cd> sub(n, 0.0), pv(n);
+// Householder reduction of a Hermitian matrix (lower triangle, column-major,
+// split real/imaginary parts) to real symmetric tridiagonal form.  On exit:
+// d (diagonal), sub (complex subdiagonal entries A[k+1][k]), and the
+// reflectors u_k (unit, rows k+1..n-1) in columns of Ur/Ui with has[k].
+static void tridiag_soa(std::vector<cd>& A, int n, std::vector<double>& d, std::vector<cd>& sub,
+                        std::vector<double>& Ur, std::vector<double>& Ui, std::vector<char>& has) {
+    std::vector<double> ar((size_t)n * n), ai((size_t)n * n);
+    for (size_t e = 0; e < (size_t)n * n; ++e) {
+        ar[e] = A[e].real();
+        ai[e] = A[e].imag();
+    }
+    Ur.assign((size_t)n * n, 0.0);
+    Ui.assign((size_t)n * n, 0.0);
+    has.assign(n, 0);
+    sub.assign(n, 0.0);
+    d.assign(n, 0.0);
+    std::vector<double> pr(n), pi(n);
     for (int k = 0; k + 2 < n; ++k) {
-        const cd* ak = &A[(size_t)k * n];
+        const double* akr = &ar[(size_t)k * n];
+        const double* aki = &ai[(size_t)k * n];
         double xn = 0.0;
-        for (int i = k + 1; i < n; ++i) xn += std::norm(ak[i]);
+        for (int i = k + 1; i < n; ++i) xn += akr[i] * akr[i] + aki[i] * aki[i];
         xn = std::sqrt(xn);
-        const cd x0 = ak[k + 1];
+        const cd x0(akr[k + 1], aki[k + 1]);
         const double tail = xn * xn - std::norm(x0);
         if (xn == 0.0 || tail <= 1e-300) {
             sub[k] = x0;
@@ -297,40 +311,90 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
         }
         const cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0);
         const cd alpha = -ph * xn;
-        cd* u = &U[(size_t)k * n];
+        double* ur = &Ur[(size_t)k * n];
+        double* ui = &Ui[(size_t)k * n];
         double un = 0.0;
         for (int i = k + 1; i < n; ++i) {
-            u[i] = ak[i];
-            if (i == k + 1) u[i] -= alpha;
-            un += std::norm(u[i]);
+            ur[i] = akr[i];
+            ui[i] = aki[i];
         }
+        ur[k + 1] -= alpha.real();
+        ui[k + 1] -= alpha.imag();
+        for (int i = k + 1; i < n; ++i) un += ur[i] * ur[i] + ui[i] * ui[i];
         const double inv = 1.0 / std::sqrt(un);
-        for (int i = k + 1; i < n; ++i) u[i] *= inv;
+        for (int i = k + 1; i < n; ++i) {
+            ur[i] *= inv;
+            ui[i] *= inv;
+        }
         has[k] = 1;
         sub[k] = alpha;
-        // p = A22 u (full trailing block, column loops)
-        for (int i = k + 1; i < n; ++i) pv[i] = 0.0;
+        // p = A22 u from the lower triangle: column j contributes A[i][j] u_j to
+        // p_i (i > j) and conj(A[i][j]) u_i to p_j
+        for (int i = k + 1; i < n; ++i) pr[i] = pi[i] = 0.0;
         for (int j = k + 1; j < n; ++j) {
-            const cd* aj = &A[(size_t)j * n];
-            const cd uj = u[j];
-            for (int i = k + 1; i < n; ++i) pv[i] += aj[i] * uj;
+            const double* ajr = &ar[(size_t)j * n];
+            const double* aji = &ai[(size_t)j * n];
+            const double ujr = ur[j], uji = ui[j];
+            double s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+            int i = j + 1;
+            for (; i + 1 < n; i += 2) {
+                pr[i] += ajr[i] * ujr - aji[i] * uji;
+                pi[i] += ajr[i] * uji + aji[i] * ujr;
+                pr[i + 1] += ajr[i + 1] * ujr - aji[i + 1] * uji;
+                pi[i + 1] += ajr[i + 1] * uji + aji[i + 1] * ujr;
+                s0r += ajr[i] * ur[i] + aji[i] * ui[i];
+                s0i += ajr[i] * ui[i] - aji[i] * ur[i];
+                s1r += ajr[i + 1] * ur[i + 1] + aji[i + 1] * ui[i + 1];
+                s1i += ajr[i + 1] * ui[i + 1] - aji[i + 1] * ur[i + 1];
+            }
+            for (; i < n; ++i) {
+                pr[i] += ajr[i] * ujr - aji[i] * uji;
+                pi[i] += ajr[i] * uji + aji[i] * ujr;
+                s0r += ajr[i] * ur[i] + aji[i] * ui[i];
+                s0i += ajr[i] * ui[i] - aji[i] * ur[i];
+            }
+            pr[j] += ajr[j] * ujr + s0r + s1r;
+            pi[j] += ajr[j] * uji + s0i + s1i;
         }
         double K = 0.0;
-        for (int i = k + 1; i < n; ++i) K += (std::conj(u[i]) * pv[i]).real();
-        for (int i = k + 1; i < n; ++i) pv[i] -= K * u[i];
-        // A22 <- A22 - 2 (u w^H + w u^H)
+        for (int i = k + 1; i < n; ++i) K += ur[i] * pr[i] + ui[i] * pi[i];
+        for (int i = k + 1; i < n; ++i) {
+            pr[i] -= K * ur[i];
+            pi[i] -= K * ui[i];
+        }
+        // A22 <- A22 - 2 (u w^H + w u^H) on the lower triangle (w = p - K u)
         for (int j = k + 1; j < n; ++j) {
-            cd* aj = &A[(size_t)j * n];
-            const cd a = 2.0 * std::conj(pv[j]), b = 2.0 * std::conj(u[j]);
-            for (int i = k + 1; i < n; ++i) aj[i] -= u[i] * a + pv[i] * b;
+            double* ajr = &ar[(size_t)j * n];
+            double* aji = &ai[(size_t)j * n];
+            const double ar2 = 2.0 * pr[j], ai2 = -2.0 * pi[j];  // 2 conj(w_j)
+            const double br2 = 2.0 * ur[j], bi2 = -2.0 * ui[j];  // 2 conj(u_j)
+            for (int i = j; i < n; ++i) {
+                ajr[i] -= ur[i] * ar2 - ui[i] * ai2 + pr[i] * br2 - pi[i] * bi2;
+                aji[i] -= ur[i] * ai2 + ui[i] * ar2 + pr[i] * bi2 + pi[i] * br2;
+            }
         }
     }
-    if (n >= 2) sub[n - 2] = A[(size_t)(n - 1) + (size_t)(n - 2) * n];
+    if (n >= 2) sub[n - 2] = cd(ar[(size_t)(n - 1) + (size_t)(n - 2) * n], ai[(size_t)(n - 1) + (size_t)(n - 2) * n]);
+    for (int k = 0; k < n; ++k) d[k] = ar[k + (size_t)k * n];
+}
+
+// Hermitian eigenvalues (all, ascending) and the eigenvectors of the nv
+// lowest (V: n x nv), for the Rayleigh-Ritz step, which keeps only those.
+// Householder reduction (tridiag_soa, the reflectors kept, not multiplied
+// out), the implicit QL iteration with Wilkinson shifts on the eigenvalues
+// alone (its plane rotations recorded), then the selected
+// eigenvectors rebuilt from unit vectors by the rotations in reverse order,
+// the diagonal phases and the reflectors in reverse order.
+static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
+    std::vector<double> d0, Ur, Ui;
+    std::vector<cd> sub;
+    std::vector<char> has;
+    tridiag_soa(A, n, d0, sub, Ur, Ui, has);
     // real tridiagonal: d, and e made real by the diagonal phases ph
     std::vector<double> d(n), e(n, 0.0);
     std::vector<cd> phs(n, 1.0);
     for (int k = 0; k < n; ++k) {
-        d[k] = A[k + (size_t)k * n].real();
+        d[k] = d0[k];
         if (k + 1 < n) {
             const double a = std::abs(sub[k]);
             phs[k + 1] = a > 0.0 ? phs[k] * (sub[k] / a) : phs[k];
@@ -354,13 +418,13 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
             if (m != l) {
                 if (++iter > 80) return false;
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
+                double r = pyth(g, 1.0);
                 g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
                 double sn = 1.0, cs = 1.0, pp = 0.0;
                 bool deflated = false;
                 for (int i = m - 1; i >= l; --i) {
                     double f = sn * e[i], b = cs * e[i];
-                    r = std::hypot(f, g);
+                    r = pyth(f, g);
                     e[i + 1] = r;
                     if (r == 0.0) {
                         d[i + 1] -= pp;
@@ -411,13 +475,18 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
     }
     for (int k = n - 3; k >= 0; --k) {
         if (!has[k]) continue;
-        const cd* u = &U[(size_t)k * n];
+        const double* ur = &Ur[(size_t)k * n];
+        const double* ui = &Ui[(size_t)k * n];
         for (int c = 0; c < nv; ++c) {
             cd* vc = &V[(size_t)c * n];
-            cd s = 0.0;
-            for (int i = k + 1; i < n; ++i) s += std::conj(u[i]) * vc[i];
-            s *= 2.0;
-            for (int i = k + 1; i < n; ++i) vc[i] -= u[i] * s;
+            double sr = 0.0, si = 0.0;
+            for (int i = k + 1; i < n; ++i) {
+                sr += ur[i] * vc[i].real() + ui[i] * vc[i].imag();
+                si += ur[i] * vc[i].imag() - ui[i] * vc[i].real();
+            }
+            sr *= 2.0;
+            si *= 2.0;
+            for (int i = k + 1; i < n; ++i) vc[i] -= cd(ur[i] * sr - ui[i] * si, ur[i] * si + ui[i] * sr);
         }
     }
     return true;
