@@ -886,6 +886,13 @@ static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std:
     return true;
 }
 
+// IWFPM_ORTHO=explicit: always project explicitly (twice) and SVQB, the route
+// taken when the one-pass form would cancel too much
+static bool force_explicit_ortho() {
+    const char* e = std::getenv("IWFPM_ORTHO");
+    return e && std::strcmp(e, "explicit") == 0;
+}
+
 static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
                iwfpm_stats* stats, hipStream_t st, Capture* cap = nullptr) {
     const int nev = o.nev;
@@ -906,6 +913,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     const bool can64 = p->sched[0].ok;
     const char* venv = std::getenv("IWFPM_VERBOSE");
     const bool verbose = venv && venv[0] == '1';
+    const bool explicit_ortho = force_explicit_ortho();
     LearnedPrecond* lp = nullptr;
     if (o.precond == IWFPM_PRECOND_LEARNED) {
         lp = p->learned;
@@ -1073,7 +1081,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
                     if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
                 }
             }
-            if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
+            if (!explicit_ortho && ortho_coefficients(Gall, nx, ma, Cm, mw)) {
                 if ((rc = dev_lincomb(c, XPW, cols(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
             } else {
                 ++reortho;
@@ -1378,6 +1386,7 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
     const int nev = o.nev;
     const int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
     if (m < nev || 3 * m > kMaxCols) return IWFPM_ERR_ARG;
+    const bool explicit_ortho = force_explicit_ortho();
     std::vector<BInst> in(B);
     int rc;
     for (int i = 0; i < B; ++i) {
@@ -1673,7 +1682,8 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             std::vector<std::vector<cd>> Cm(iter.size());
             parallel_for((int)iter.size(), [&](int k) {
                 BInst& b = in[iter[k]];
-                one[k] = m + b.mq + b.ma <= kMaxCols && ortho_coefficients(Gall[k], m + b.mq, b.ma, Cm[k], b.mw);
+                one[k] = !explicit_ortho && m + b.mq + b.ma <= kMaxCols &&
+                         ortho_coefficients(Gall[k], m + b.mq, b.ma, Cm[k], b.mw);
             });
             std::vector<size_t> two;
             std::vector<LinReq> l;

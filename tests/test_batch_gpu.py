@@ -115,6 +115,23 @@ def test_eigs_batched_matches_oracle_and_single(prec):
         p.close()
 
 
+def test_eigs_batched_explicit_orthonormalisation(monkeypatch):
+    """The batched solver's explicit orthonormalisation route matches the oracle too."""
+    probs = [W.c2_2d(lam=lam, K=K, L=3) for lam, K in [(0.3, 3), (7.0, 4)]]
+    print(f"case: eigs_batched {len(probs)} fp64 explicit orthonormalisation", flush=True)
+    monkeypatch.setenv("IWFPM_ORTHO", "explicit")
+    plans = [lib.Plan.from_problem(p, precision="fp64") for p in probs]
+    try:
+        ev, eta, stats, st = lib.eigs_batched(plans, 8, tol=1e-10, maxit=400)
+        for i, p in enumerate(probs):
+            ref = dense_lowest(p, 8)
+            assert np.all(np.abs(ev[i] - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), (i, ev[i] - ref)
+            assert stats[i]["converged"] == 8
+    finally:
+        for p in plans:
+            p.close()
+
+
 def test_eigs_batched_sweep_workload_subset():
     """Eight instances of the coupling sweep (2D/4D geometry, L = 16, ragged K),
     float32 convolution, eta <= 1e-8; pairs verified with each instance's

@@ -82,6 +82,23 @@ def test_small_2d_lifted_4d(prec, lam):
     check_pairs_with_oracle(prob, r, 16, 1e-10)
 
 
+@pytest.mark.parametrize("lam", [0.5, 5.0])
+def test_explicit_orthonormalisation_route(lam, monkeypatch):
+    """The explicit route (projection twice + SVQB), taken when the one-pass
+    coefficient-space orthonormalisation would cancel too much, gives the same
+    pairs to the same bar."""
+    prob = W.c2_2d(lam=lam, K=3, L=4)
+    print(f"case: 2d_lifted_4d K=3 L=4 lam={lam} explicit orthonormalisation", flush=True)
+    with lib.Plan.from_problem(prob, precision="fp64") as p:
+        a = p.eigs(16, tol=1e-10, maxit=500)
+        monkeypatch.setenv("IWFPM_ORTHO", "explicit")
+        b = p.eigs(16, tol=1e-10, maxit=500)
+    ref = dense_ref(prob, 16)
+    for r in (a, b):
+        assert np.all(np.abs(r.evals - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), (r.evals - ref)
+    check_pairs_with_oracle(prob, b, 16, 1e-10)
+
+
 @pytest.mark.parametrize("window", ["rounded", "pm"])
 def test_window_variants_eigs(window):
     prob = W.paper_example_1d(2.5, 5, 12)
