@@ -82,6 +82,23 @@ def test_small_2d_lifted_4d(prec, lam):
     check_pairs_with_oracle(prob, r, 16, 1e-10)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_basis_wide_block(prec):
+    """N = 140 (a 12-row tail for the 4-row Gram groups' blocks, the 16-row
+    matrix-core tiles and the 64/128-row vector strips) with 16 pairs, so that
+    every block kernel, the wide matrix-core combination included, meets a
+    ragged end; eigenvalues against the dense oracle."""
+    prob = W.paper_example_1d(2.5, 7, 5)
+    print(f"case: paper_ex1 K=7 L=5 (N=140) 16 pairs {prec}", flush=True)
+    with lib.Plan.from_problem(prob, precision=prec) as p:
+        assert p.N == 140
+        r = p.eigs(16, tol=1e-10, maxit=500)
+    ref = dense_ref(prob, 16)
+    bar = 1e-10 if prec == "fp64" else 1e-5
+    assert np.all(np.abs(r.evals - ref) <= bar * np.maximum(1.0, np.abs(ref))), (r.evals - ref)
+    check_pairs_with_oracle(prob, r, 16, 1e-10)
+
+
 @pytest.mark.parametrize("lam", [0.5, 5.0])
 def test_explicit_orthonormalisation_route(lam, monkeypatch):
     """The explicit route (projection twice + SVQB), taken when the one-pass
