@@ -111,6 +111,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-pm", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
@@ -177,6 +178,8 @@ def main():
         out["eigs"] = run_eigs(lib, W, net)
         if not a.no_c3:
             out["eigs_3d_lifted_6d"] = run_eigs_c3(lib, W, net)
+    if not a.no_pm:
+        out["pm_vs_iwfpm"] = run_pm_compare(lib, W)
     if not a.no_sweep:
         out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
@@ -299,6 +302,36 @@ def run_eigs(lib, W, net):
                 res[f"lam{lam}_{precond}"] = {"seconds": t, "iterations": r.iterations, "matvecs": r.matvecs,
                                               "eta_max": float(max(r.eta)), "E0": float(r.evals[0]),
                                               "polished_iterations": r.polished, "fallback": r.fallback}
+    return res
+
+
+def run_pm_compare(lib, W):
+    """The paper's comparison of IWFPM with the projection method (the shear
+    switched off, rectangle [-K, K)^d x [-L, L)^(n-d)) at equal eigenvalue
+    accuracy: the PM truncation that the paper's error tables pair with
+    IWFPM's, at sizes whose axes fit this build (<= 64 points).  Ground state,
+    float64 plans, warm plan, eta <= 1e-13; the eigenvalue errors of these rows
+    against a converged reference are checked by the GPU tests."""
+    import math
+    cases = [("ex4.1 v0=2.5 L=20", lambda K: W.paper_example_1d(2.5, K, 20), 5, 14),
+             ("ex4.2 case I L=20", lambda K: W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, K, 20), 6, 16),
+             ("ex4.2 case I L=30", lambda K: W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, K, 30), 6, 24)]
+    res = []
+    for name, make, k_iw, k_pm in cases:
+        row = {"case": name, "K_iwfpm": k_iw, "K_pm": k_pm}
+        for tag, K, window in (("iwfpm", k_iw, "exact"), ("pm", k_pm, "pm")):
+            with lib.Plan.from_problem(make(K), window=window) as plan:
+                plan.eigs(1, block=4, tol=1e-13, maxit=1500)
+                ts = []
+                for _ in range(3):
+                    r, t = _timed(lambda: plan.eigs(1, block=4, tol=1e-13, maxit=1500))
+                    ts.append(t)
+                row[tag] = {"dof": plan.N, "iterations": r.iterations, "seconds": sorted(ts)[1],
+                            "E0": float(r.evals[0])}
+        row["dof_ratio"] = row["pm"]["dof"] / row["iwfpm"]["dof"]
+        row["time_ratio"] = row["pm"]["seconds"] / row["iwfpm"]["seconds"]
+        row["E0_rel_diff"] = abs(row["pm"]["E0"] - row["iwfpm"]["E0"]) / abs(row["iwfpm"]["E0"])
+        res.append(row)
     return res
 
 

@@ -84,6 +84,16 @@ def test_fused_small(prec, order):
     check_full(prob, prec, order=order, schedule="fused")
 
 
+@pytest.mark.parametrize("schedule", ["fused", "threepass"])
+@pytest.mark.parametrize("window", ["exact", "pm"])
+def test_sixty_point_axis(schedule, window):
+    """A 60-point axis (2L = 60, Table 5's L = 30) in both schedules."""
+    prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 3, 30) if schedule == "fused" else \
+        W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 6, 30)
+    print(f"case: 60-point axis {schedule} {window} N={prob.N}", flush=True)
+    check_full(prob, "fp64", window=window, schedule=schedule)
+
+
 @pytest.mark.parametrize("window", ["rounded", "pm"])
 def test_window_variants(window):
     prob = W.paper_example_1d(2.5, 5, 12)

@@ -146,15 +146,40 @@ def test_table2_on_gpu(L, printed):
     assert f"{ev:.2e}" == f"{printed:.2e}", ev
 
 
-def test_table5_on_gpu():
-    """Table 5 (Ex. 4.2 case I, K = 6, L = 20): E_v = 4.53e-8."""
+@pytest.mark.parametrize("L,printed", [(20, 4.53e-08), (30, 3.09e-11)])
+def test_table5_on_gpu(L, printed):
+    """Table 5 (Ex. 4.2 case I, IWFPM K = 6): E_v = 4.53e-8 (L = 20) and
+    3.09e-11 (L = 30, a 60-point axis)."""
     e0s = _golden("ex2_reference.json")["E0"]
-    prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 6, 20)
-    print("case: Table 5 K=6 L=20", flush=True)
+    prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 6, L)
+    print(f"case: Table 5 K=6 L={L}", flush=True)
     with lib.Plan.from_problem(prob) as p:
         r = p.eigs(1, block=4, tol=1e-13, maxit=800)
     ev = abs(r.evals[0] - e0s) / e0s
-    assert abs(ev - 4.53e-8) <= 0.006 * 4.53e-8, ev
+    assert abs(ev - printed) <= 0.006 * printed, ev
+
+
+@pytest.mark.parametrize("example,K,L,printed", [
+    ("1d", 14, 20, 5.64e-08),     # Table 2, PM K = 0.7 L
+    ("2d", 8, 20, 7.51e-05),      # Table 5, PM K = 0.4 L
+    ("2d", 16, 20, 7.35e-08),     # Table 5, PM K = 0.8 L
+    ("2d", 24, 30, 9.88e-11),     # Table 5, PM K = 0.8 L
+])
+def test_projection_method_rows_on_gpu(example, K, L, printed):
+    """The paper's projection-method rows (the shear switched off, rectangle
+    [-K, K)^d x [-L, L)^(n-d)) end to end on the GPU: E_v against the stored
+    reference E0*."""
+    if example == "1d":
+        e0s = _golden("ex1_reference.json")["E0"]
+        prob = W.paper_example_1d(2.5, K, L)
+    else:
+        e0s = _golden("ex2_reference.json")["E0"]
+        prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, K, L)
+    print(f"case: PM {example} K={K} L={L}", flush=True)
+    with lib.Plan.from_problem(prob, window="pm") as p:
+        r = p.eigs(1, block=4, tol=1e-13, maxit=1500)
+    ev = abs(r.evals[0] - e0s) / e0s
+    assert abs(ev - printed) <= 0.006 * printed, ev
 
 
 @pytest.mark.parametrize("lam", [0.5, 5.0])

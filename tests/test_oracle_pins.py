@@ -258,6 +258,18 @@ def test_table2_eigenvalue_errors(method, L, K, printed):
     assert f"{ev:.2e}" == f"{printed:.2e}", (ev, printed)
 
 
+def test_table5_pm_row():
+    """Table 5's projection-method row (Ex. 4.2 case I, rectangle K = 0.4 L,
+    L = 20): E_v = 7.51e-05 (the K = 0.6 L and 0.8 L rows, 2.55e-06 and
+    7.35e-08, also reproduce but take minutes on the oracle; the GPU tests
+    hold them)."""
+    e0s = _golden("ex2_reference.json")["E0"]
+    prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 8, 20)
+    e0 = _e0_dense(prob, "pm")
+    ev = abs(e0 - e0s) / e0s
+    assert abs(ev - 7.51e-05) <= 0.006 * 7.51e-05, ev
+
+
 @pytest.mark.parametrize("L,printed", [(20, 4.53e-08), (30, 3.09e-11)])
 def test_table5_eigenvalue_errors(L, printed):
     """Table 5 (Ex. 4.2 case I, beta = 0.8 pi, theta = 0.2 pi, IWFPM K = 6)."""
