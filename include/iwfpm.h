@@ -209,6 +209,8 @@ typedef struct {
     int precond;        /* IWFPM_PRECOND_* */
     uint64_t seed;      /* start block seed when x0 == NULL */
     int polish;         /* FP32 plans: 1 = finish with float64 applies once FP32 stalls */
+    int arith;          /* 0 = auto (real when H~ is real symmetric and x0 == NULL),
+                           1 = complex, 2 = real (requires every Vhat_m real and x0 == NULL) */
 } iwfpm_eigs_opts;
 
 typedef struct {
@@ -234,6 +236,12 @@ void iwfpm_default_eigs_opts(iwfpm_eigs_opts* opts);
  * Convergence: eta_i = ||H~ x_i - theta_i x_i|| / ((||H~||_est + |theta_i|) ||x_i||)
  * <= tol, with ||H~||_est from iwfpm_norm_bound; the final eta is always
  * evaluated with float64 applies.
+ * Real-symmetric problems (every Vhat_m real, so V is even and H~ is a real
+ * symmetric matrix) are solved by default in real arithmetic: real trial
+ * vectors stored two per complex column, the real and imaginary halves
+ * applied together; the returned eigenvectors are then real (zero imaginary
+ * parts).  opts->arith chooses explicitly; iwfpm_eigs_batched and the
+ * learned preconditioner's training solves always use complex arithmetic.
  * x0: device, N x m start block (m = block size) or NULL for a seeded random start.
  * evals, eta: host, nev float64 (eta may be NULL).  evecs: device, N x nev
  * complex float64, or NULL.  stats may be NULL.  Blocking (synchronises stream).

@@ -43,6 +43,7 @@ WINDOW = {"exact": 0, "rounded": 1, "pm": 2}
 ORDER = {"grid": 0, "window": 1}
 SCHED = {"auto": 0, "fused": 1, "threepass": 2}
 PRECOND = {"none": 0, "plain": 1, "learned": 2}
+ARITH = {"auto": 0, "complex": 1, "real": 2}
 
 
 class IwfpmError(RuntimeError):
@@ -61,7 +62,7 @@ class _Opts(ctypes.Structure):
 class _EigsOpts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("precond", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("polish", ctypes.c_int)]
+                ("polish", ctypes.c_int), ("arith", ctypes.c_int)]
 
 
 class _LearnedOpts(ctypes.Structure):
@@ -559,13 +560,14 @@ class Plan:
         return {n: {"ms": float(ms[i]), "launches": int(la[i]), "points": int(pt[i])} for i, n in enumerate(names)}
 
     def eigs(self, nev, tol=1e-8, maxit=500, block=0, precond="plain", x0=None, seed=2404045070,
-             polish=True, want_vectors=True, stream=None, allow_noconv=False) -> EigsResult:
+             polish=True, want_vectors=True, stream=None, allow_noconv=False, arith="auto") -> EigsResult:
         import torch
         lib = _lib()
         o = _EigsOpts()
         lib.iwfpm_default_eigs_opts(ctypes.byref(o))
         o.nev, o.block, o.tol, o.maxit = int(nev), int(block), float(tol), int(maxit)
         o.precond, o.seed, o.polish = PRECOND[precond], int(seed), int(bool(polish))
+        o.arith = ARITH[arith]
         evals = np.zeros(nev)
         eta = np.zeros(nev)
         vecs = None

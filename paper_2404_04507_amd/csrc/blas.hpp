@@ -23,6 +23,25 @@ hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, d
 // Y_j = beta Y_j + sum_i A_i C[j*p + i], q <= 48
 hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double2* C, double beta, long long N,
                    hipStream_t st);
+// Two real vectors per complex column (real part, imaginary part):
+//   gram_pairs     C (2p x 2q real, column-major) = real Gram of the 2p real vectors in L
+//                  with the 2q in R; `partial` holds max_blocks*4pq doubles
+//   lincomb_pairs  Y = beta Y + A C with C the real (2p x 2q, column-major) coefficients, q <= 32
+//   residual_norm_pairs  R = HX - X diag(theta) (one theta per real vector, 2m of them),
+//                  out[v] = ||R_v||^2 per real vector; `partial` holds max_blocks*2m doubles
+//   gather_pairs   packs n real vectors (part of src[v] given by bit v of parts), times M
+//                  when M is not null, into ceil(n/2) columns (a zero half when n is odd)
+//   unpack_real    complex column v = (real vector v, 0)
+hipError_t gram_pairs(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
+                      double* C, hipStream_t st);
+hipError_t lincomb_pairs(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double* C, double beta, long long N,
+                         hipStream_t st);
+hipError_t residual_norm_pairs(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, const Reals& theta, int m,
+                               long long N, double* partial, int max_blocks, double* out, hipStream_t st);
+hipError_t gather_pairs(const ColPtrs& src, unsigned long long parts, int n, const ColPtrs& dst, const double* M,
+                        long long N, hipStream_t st);
+hipError_t unpack_real(const ColPtrs& src, unsigned long long parts, int n, const ColPtrs& dst, long long N,
+                       hipStream_t st);
 hipError_t residual(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, const Reals& theta, int m, long long N,
                     hipStream_t st);
 // out[j] = ||V_j||^2; `partial` holds max_blocks*m doubles

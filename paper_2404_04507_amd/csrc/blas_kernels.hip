@@ -51,7 +51,10 @@ __device__ __forceinline__ void gram_load(const double2* lp, const double2* cons
     for (int t = 0; t < TQ; ++t) rv[t] = (ok && rp[t]) ? rp[t][row] : make_double2(0.0, 0.0);
 }
 
-template <int TQ>
+// PAIRS: every complex column holds two real vectors (real part, imaginary
+// part) and the result is their real Gram, four accumulators per tile
+// (rr, ri, ir, ii), written as real (2p x 2q, column-major) partials.
+template <int TQ, bool PAIRS = false>
 __device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N,
                                           long long groups_per_block, double2* __restrict__ partial, int bid) {
     constexpr int D = kGramDepth;
@@ -65,11 +68,15 @@ __device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs
         const int c = 16 * t + li;
         rp[t] = c < q ? R.p[c] : nullptr;
     }
-    dbl4 accr[TQ], acci[TQ];
+    dbl4 accr[TQ], acci[TQ], accx[PAIRS ? TQ : 1], accy[PAIRS ? TQ : 1];
 #pragma unroll
     for (int b = 0; b < TQ; ++b) {
         accr[b] = dbl4{0.0, 0.0, 0.0, 0.0};
         acci[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if constexpr (PAIRS) {
+            accx[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+            accy[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
     }
     const long long G = (N + 3) >> 2;
     const long long g0 = (long long)bid * groups_per_block, g1 = min(G, g0 + groups_per_block);
@@ -89,21 +96,48 @@ __device__ __forceinline__ void gram_body(const ColPtrs& L, int p, const ColPtrs
                 accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.x, rv[b].x, accr[b], 0, 0, 0);
                 acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.x, rv[b].y, acci[b], 0, 0, 0);
             }
+            if constexpr (PAIRS) {
 #pragma unroll
-            for (int b = 0; b < TQ; ++b) {
-                accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, rv[b].y, accr[b], 0, 0, 0);
-                acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, -rv[b].x, acci[b], 0, 0, 0);
+                for (int b = 0; b < TQ; ++b) {
+                    accx[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, rv[b].x, accx[b], 0, 0, 0);
+                    accy[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, rv[b].y, accy[b], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < TQ; ++b) {
+                    accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, rv[b].y, accr[b], 0, 0, 0);
+                    acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(lv.y, -rv[b].x, acci[b], 0, 0, 0);
+                }
             }
         }
     }
-    double2* out = partial + (size_t)bid * p * q;
+    if constexpr (PAIRS) {
+        double* out = reinterpret_cast<double*>(partial) + (size_t)bid * 4 * p * q;
+        const size_t ld = 2 * (size_t)p;
 #pragma unroll
-    for (int b = 0; b < TQ; ++b) {
-        const int j = 16 * b + li;
+        for (int b = 0; b < TQ; ++b) {
+            const int j = 16 * b + li;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = 16 * wave + lk + 4 * v;
-            if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[b][v], acci[b][v]);
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * wave + lk + 4 * v;
+                if (i < p && j < q) {
+                    out[(2 * (size_t)j) * ld + 2 * i] = accr[b][v];          // re . re
+                    out[(2 * (size_t)j + 1) * ld + 2 * i] = acci[b][v];      // re . im
+                    out[(2 * (size_t)j) * ld + 2 * i + 1] = accx[b][v];      // im . re
+                    out[(2 * (size_t)j + 1) * ld + 2 * i + 1] = accy[b][v];  // im . im
+                }
+            }
+        }
+    } else {
+        double2* out = partial + (size_t)bid * p * q;
+#pragma unroll
+        for (int b = 0; b < TQ; ++b) {
+            const int j = 16 * b + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * wave + lk + 4 * v;
+                if (i < p && j < q) out[(size_t)j * p + i] = make_double2(accr[b][v], acci[b][v]);
+            }
         }
     }
 }
@@ -113,6 +147,12 @@ template <int TQ>
 __global__ void __launch_bounds__(256) k_gram(ColPtrs L, int p, ColPtrs R, int q, long long N, long long groups_per_block,
                                               double2* __restrict__ partial) {
     gram_body<TQ>(L, p, R, q, N, groups_per_block, partial, blockIdx.x);
+}
+
+template <int TQ>
+__global__ void __launch_bounds__(256) k_gram_pairs(ColPtrs L, int p, ColPtrs R, int q, long long N,
+                                                    long long groups_per_block, double2* __restrict__ partial) {
+    gram_body<TQ, true>(L, p, R, q, N, groups_per_block, partial, blockIdx.x);
 }
 
 // C[e] = sum over the nb partials, one workgroup per entry, fixed summation order
@@ -146,7 +186,10 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double2* __restri
 // loads when it is a kernel argument, else from an LDS copy.  Two rows per
 // lane halve the C reads per multiply-add and double the loads in flight.
 // ---------------------------------------------------------------------------
-template <int QG>
+// PAIRS: A and Y hold two real vectors per complex column and C is the real
+// (2p x 2q, column-major) coefficient matrix: each (input, output) column pair
+// takes a 2 x 2 real block.
+template <int QG, bool PAIRS = false>
 __device__ __forceinline__ void lincomb_rows_body(const ColPtrs& A, int p, const ColPtrs& Y, int q,
                                                   const double2* __restrict__ C, double beta, long long N, int bid,
                                                   int nb) {
@@ -176,15 +219,31 @@ __device__ __forceinline__ void lincomb_rows_body(const ColPtrs& A, int p, const
         for (int i = 0; i < p; ++i) {
             const double2 a = A.p[i][r];
             const double2 a2 = ok2 ? A.p[i][r2] : make_double2(0.0, 0.0);
-            const double2* ci = C + (size_t)j0 * p + i;
+            if constexpr (PAIRS) {
+                // C real: rows 2i, 2i+1 of columns 2(j0+j), 2(j0+j)+1 (leading dimension 2p)
+                const double2* ci = C + (size_t)(2 * j0) * p + i;
 #pragma unroll
-            for (int j = 0; j < QG; ++j) {
-                if (j < nj) {
-                    const double2 c = ci[(size_t)j * p];
-                    acc[j].x += a.x * c.x - a.y * c.y;
-                    acc[j].y += a.x * c.y + a.y * c.x;
-                    acc2[j].x += a2.x * c.x - a2.y * c.y;
-                    acc2[j].y += a2.x * c.y + a2.y * c.x;
+                for (int j = 0; j < QG; ++j) {
+                    if (j < nj) {
+                        const double2 c0 = ci[(size_t)(2 * j) * p];      // (C[2i][2k], C[2i+1][2k])
+                        const double2 c1 = ci[(size_t)(2 * j + 1) * p];  // (C[2i][2k+1], C[2i+1][2k+1])
+                        acc[j].x += a.x * c0.x + a.y * c0.y;
+                        acc[j].y += a.x * c1.x + a.y * c1.y;
+                        acc2[j].x += a2.x * c0.x + a2.y * c0.y;
+                        acc2[j].y += a2.x * c1.x + a2.y * c1.y;
+                    }
+                }
+            } else {
+                const double2* ci = C + (size_t)j0 * p + i;
+#pragma unroll
+                for (int j = 0; j < QG; ++j) {
+                    if (j < nj) {
+                        const double2 c = ci[(size_t)j * p];
+                        acc[j].x += a.x * c.x - a.y * c.y;
+                        acc[j].y += a.x * c.y + a.y * c.x;
+                        acc2[j].x += a2.x * c.x - a2.y * c.y;
+                        acc2[j].y += a2.x * c.y + a2.y * c.x;
+                    }
                 }
             }
         }
@@ -201,6 +260,12 @@ template <int QG>
 __global__ void __launch_bounds__(256) k_lincomb_rows(ColPtrs A, int p, ColPtrs Y, int q,
                                                       const double2* __restrict__ C, double beta, long long N) {
     lincomb_rows_body<QG>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x);
+}
+
+template <int QG>
+__global__ void __launch_bounds__(256) k_lincomb_pairs(ColPtrs A, int p, ColPtrs Y, int q,
+                                                       const double2* __restrict__ C, double beta, long long N) {
+    lincomb_rows_body<QG, true>(A, p, Y, q, C, beta, N, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,6 +451,74 @@ __global__ void k_precond(ColPtrs R, ColPtrs W, int m, const double* __restrict_
         for (int j = 0; j < m; ++j) {
             double2 v = R.p[j][r];
             W.p[j][r] = make_double2(mm * v.x, mm * v.y);
+        }
+    }
+}
+
+// two real vectors per complex column: R = HX - X diag(theta) with one theta
+// per real vector (theta[2j] for the real parts of column j, theta[2j+1] for
+// the imaginary parts) and one squared norm per real vector
+__global__ void __launch_bounds__(256) k_residual_norm_pairs(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
+                                                             long long N, long long rows_per_block,
+                                                             double* __restrict__ partial) {
+    __shared__ double red[2][256];
+    const long long r0 = (long long)blockIdx.x * rows_per_block;
+    const long long r1 = min(N, r0 + rows_per_block);
+    for (int j = 0; j < m; ++j) {
+        double s0 = 0.0, s1 = 0.0;
+        const double t0 = theta.v[2 * j], t1 = theta.v[2 * j + 1];
+        for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+            const double2 h = HX.p[j][r], x = X.p[j][r];
+            const double2 v = make_double2(h.x - t0 * x.x, h.y - t1 * x.y);
+            Rout.p[j][r] = v;
+            s0 += v.x * v.x;
+            s1 += v.y * v.y;
+        }
+        red[0][threadIdx.x] = s0;
+        red[1][threadIdx.x] = s1;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            partial[(size_t)blockIdx.x * 2 * m + 2 * j] = red[0][0];
+            partial[(size_t)blockIdx.x * 2 * m + 2 * j + 1] = red[1][0];
+        }
+        __syncthreads();
+    }
+}
+
+// packs n real vectors (vector v: part (bit v of parts) of column src[v]),
+// scaled by M when given, two per destination column; the imaginary half of
+// the last column is zero when n is odd
+__global__ void k_gather_pairs(ColPtrs src, unsigned long long parts, int n, ColPtrs dst,
+                               const double* __restrict__ M, long long N) {
+    const int nd = (n + 1) >> 1;
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
+        const double mm = M ? M[r] : 1.0;
+        for (int d = 0; d < nd; ++d) {
+            const int v0 = 2 * d, v1 = 2 * d + 1;
+            const double2 a = src.p[v0][r];
+            double b = 0.0;
+            if (v1 < n) {
+                const double2 t = src.p[v1][r];
+                b = ((parts >> v1) & 1) ? t.y : t.x;
+            }
+            dst.p[d][r] = make_double2(mm * (((parts >> v0) & 1) ? a.y : a.x), mm * b);
+        }
+    }
+}
+
+// complex column v = (real vector v, 0), vector v being part (bit v) of src[v]
+__global__ void k_unpack_real(ColPtrs src, unsigned long long parts, int n, ColPtrs dst, long long N) {
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
+        for (int v = 0; v < n; ++v) {
+            const double2 a = src.p[v][r];
+            dst.p[v][r] = make_double2(((parts >> v) & 1) ? a.y : a.x, 0.0);
         }
     }
 }
@@ -577,6 +710,62 @@ hipError_t lincomb(const ColPtrs& A, int p, const ColPtrs& Y, int q, const doubl
         const int nt = (int)std::min<long long>(2048, std::max<long long>(1, (N + 63) / 64));
         k_lincomb<3><<<nt, 256, 0, st>>>(A, p, Y, q, C, beta, N);
     }
+    return hipGetLastError();
+}
+
+hipError_t gram_pairs(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
+                      double* C, hipStream_t st) {
+    if (p <= 0 || q <= 0) return hipSuccess;
+    const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4;
+    long long gpb;
+    const int nb = gram_job_blocks(p, N, max_blocks, &gpb);
+    switch (TQ) {
+        case 1: k_gram_pairs<1><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        case 2: k_gram_pairs<2><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        case 3: k_gram_pairs<3><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+        default: k_gram_pairs<4><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
+    }
+    // 4pq real entries per block, reduced as 2pq pairs
+    const int cnt = 2 * p * q;
+    k_reduce_partials<<<cnt, 256, 0, st>>>(partial, nb, cnt, reinterpret_cast<double2*>(C));
+    return hipGetLastError();
+}
+
+hipError_t lincomb_pairs(const ColPtrs& A, int p, const ColPtrs& Y, int q, const double* C, double beta, long long N,
+                         hipStream_t st) {
+    if (q <= 0) return hipSuccess;
+    if (q > 32) return hipErrorInvalidValue;
+    const int nb = (int)std::min<long long>(4096, std::max<long long>(1, (N + 127) / 128));
+    const int qg = (q + 3) >> 2;
+    const double2* C2 = reinterpret_cast<const double2*>(C);
+    if (qg <= 2) k_lincomb_pairs<2><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
+    else if (qg <= 4) k_lincomb_pairs<4><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
+    else k_lincomb_pairs<8><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
+    return hipGetLastError();
+}
+
+hipError_t residual_norm_pairs(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& R, const Reals& theta, int m,
+                               long long N, double* partial, int max_blocks, double* out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    if (2 * m > kMaxCols) return hipErrorInvalidValue;
+    long long rpb = (N + max_blocks - 1) / max_blocks;
+    int nb = (int)((N + rpb - 1) / rpb);
+    k_residual_norm_pairs<<<nb, 256, 0, st>>>(HX, X, R, theta, m, N, rpb, partial);
+    k_reduce_real<<<2 * m, 256, 0, st>>>(partial, nb, 2 * m, out);
+    return hipGetLastError();
+}
+
+hipError_t gather_pairs(const ColPtrs& src, unsigned long long parts, int n, const ColPtrs& dst, const double* M,
+                        long long N, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_gather_pairs<<<grid_for(N, 256), 256, 0, st>>>(src, parts, n, dst, M, N);
+    return hipGetLastError();
+}
+
+hipError_t unpack_real(const ColPtrs& src, unsigned long long parts, int n, const ColPtrs& dst, long long N,
+                       hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_unpack_real<<<grid_for(N, 256), 256, 0, st>>>(src, parts, n, dst, N);
     return hipGetLastError();
 }
 

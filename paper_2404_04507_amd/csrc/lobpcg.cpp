@@ -1155,6 +1155,409 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
 }
 
 
+// ---------------------------------------------------------------------------
+// Real-symmetric LOBPCG.  When every Vhat_m is real (Hermiticity then makes
+// V even), H~ is a real symmetric matrix and its eigenvectors can be taken
+// real: the solver then works on real trial vectors stored two per complex
+// column (real part, imaginary part).  The apply maps such a pair to its image
+// pair (H~ is real), the preconditioners act on both halves alike, and the
+// block algebra uses the pair kernels (four real Gram accumulators per tile,
+// 2 x 2 real coefficient blocks).  Small matrices are kept as complex arrays
+// with zero imaginary parts: the host solvers keep such inputs exactly real.
+// ---------------------------------------------------------------------------
+
+// real vector v of a block buffer: part v & 1 of column v >> 1
+struct RVec {
+    double2* col;
+    int part;
+};
+
+static std::vector<RVec> rvecs(Ctx& c, int b, int v0, int cnt) {
+    std::vector<RVec> r(cnt);
+    for (int k = 0; k < cnt; ++k) r[k] = {c.col(b, (v0 + k) >> 1), (v0 + k) & 1};
+    return r;
+}
+
+// distinct columns of a list of real vectors (first-seen order) and, per
+// vector, 2 * (its column's position) + part
+struct PairCols {
+    std::vector<double2*> cols;
+    std::vector<int> at;
+};
+
+static PairCols pair_cols(const std::vector<RVec>& v) {
+    PairCols pc;
+    for (const RVec& x : v) {
+        int ci = -1;
+        for (size_t j = 0; j < pc.cols.size(); ++j)
+            if (pc.cols[j] == x.col) {
+                ci = (int)j;
+                break;
+            }
+        if (ci < 0) {
+            ci = (int)pc.cols.size();
+            pc.cols.push_back(x.col);
+        }
+        pc.at.push_back(2 * ci + x.part);
+    }
+    return pc;
+}
+
+// G (|L| x |R|, real, zero imaginary parts) = L^T R over real vectors
+static int host_gram_real(Ctx& c, const std::vector<RVec>& L, const std::vector<RVec>& R, std::vector<cd>& G) {
+    const PairCols Lp = pair_cols(L), Rp = pair_cols(R);
+    const int P = (int)Lp.cols.size(), Q = (int)Rp.cols.size();
+    const size_t ldf = 2 * (size_t)P;
+    std::vector<double> Gf(ldf * 2 * (size_t)Q, 0.0);
+    double* dC = (double*)c.s->small.ptr;
+    double* h = (double*)c.s->hsmall;
+    constexpr int kc = kMaxCols / 2;
+    for (int i0 = 0; i0 < P; i0 += kc) {
+        const int pi = std::min(kc, P - i0);
+        for (int j0 = 0; j0 < Q; j0 += kc) {
+            const int qj = std::min(kc, Q - j0);
+            ColPtrs a{}, b{};
+            for (int i = 0; i < pi; ++i) a.p[i] = Lp.cols[i0 + i];
+            for (int j = 0; j < qj; ++j) b.p[j] = Rp.cols[j0 + j];
+            CHECK_HIP(gram_pairs(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, dC, c.st));
+            CHECK_HIP(hipMemcpyAsync(h, dC, (size_t)4 * pi * qj * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            if (int rc = sync(c)) return rc;
+            for (int s2 = 0; s2 < 2 * qj; ++s2)
+                for (int r2 = 0; r2 < 2 * pi; ++r2)
+                    Gf[(size_t)(2 * i0 + r2) + (size_t)(2 * j0 + s2) * ldf] = h[(size_t)r2 + (size_t)s2 * 2 * pi];
+        }
+    }
+    const int nl = (int)L.size(), nr = (int)R.size();
+    G.assign((size_t)nl * nr, 0.0);
+    for (int l = 0; l < nr; ++l)
+        for (int k = 0; k < nl; ++k) G[k + (size_t)l * nl] = Gf[(size_t)Lp.at[k] + (size_t)Rp.at[l] * ldf];
+    return IWFPM_OK;
+}
+
+// Y_l = beta Y_l + sum_k A_k Re C[(r0 + k) + l * ldc] over real vectors; the
+// outputs fill whole columns from their first half (a half with no output
+// vector receives beta times itself plus zero)
+static int dev_lincomb_real(Ctx& c, const std::vector<RVec>& A, const std::vector<RVec>& Y, const std::vector<cd>& Cm,
+                            int ldc, int r0, double beta) {
+    if (Y.empty()) return IWFPM_OK;
+    const PairCols Ap = pair_cols(A), Yp = pair_cols(Y);
+    const int P = (int)Ap.cols.size(), Q = (int)Yp.cols.size();
+    if (Q > 32) return IWFPM_ERR_ARG;
+    if (P == 0) {
+        if (beta == 0.0)
+            for (auto y : Yp.cols) CHECK_HIP(hipMemsetAsync(y, 0, c.N * sizeof(double2), c.st));
+        return IWFPM_OK;
+    }
+    constexpr int kc = kMaxCols / 2;  // input columns per call
+    for (int i0 = 0; i0 < P; i0 += kc) {
+        const int pi = std::min(kc, P - i0);
+        if (c.s->ring_since_sync >= kRingSlots - 1)
+            if (int rc = sync(c)) return rc;
+        const int slot = c.s->ring_next;
+        c.s->ring_next = (slot + 1) % kRingSlots;
+        c.s->ring_since_sync++;
+        double* h = (double*)(c.s->hring + (size_t)slot * kSlot);
+        double* dC = (double*)((double2*)c.s->dring.ptr + (size_t)slot * kSlot);
+        const size_t ld = 2 * (size_t)pi;
+        std::fill(h, h + ld * 2 * (size_t)Q, 0.0);
+        for (size_t k = 0; k < A.size(); ++k) {
+            const int row = Ap.at[k] - 2 * i0;
+            if (row < 0 || row >= (int)ld) continue;
+            for (size_t l = 0; l < Y.size(); ++l)
+                h[(size_t)row + (size_t)Yp.at[l] * ld] = Cm[(size_t)(r0 + k) + l * (size_t)ldc].real();
+        }
+        CHECK_HIP(hipMemcpyAsync(dC, h, ld * 2 * (size_t)Q * sizeof(double), hipMemcpyHostToDevice, c.st));
+        ColPtrs a{}, y{};
+        for (int i = 0; i < pi; ++i) a.p[i] = Ap.cols[i0 + i];
+        for (int j = 0; j < Q; ++j) y.p[j] = Yp.cols[j];
+        CHECK_HIP(lincomb_pairs(a, pi, y, Q, dC, i0 == 0 ? beta : 1.0, c.N, c.st));
+    }
+    return IWFPM_OK;
+}
+
+static ColPtrs colptrs(const std::vector<RVec>& v, unsigned long long* parts) {
+    ColPtrs cp{};
+    *parts = 0;
+    for (size_t k = 0; k < v.size(); ++k) {
+        cp.p[k] = v[k].col;
+        if (v[k].part) *parts |= 1ull << k;
+    }
+    return cp;
+}
+
+// Rayleigh-Ritz on X alone: X <- X C, HX <- HX C (real)
+static int rr_block_real(Ctx& c, int m, std::vector<double>& theta) {
+    std::vector<cd> G;
+    int rc = host_gram_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_HX, 0, m), G);
+    if (rc) return rc;
+    hermitian_part(G, m);
+    std::vector<cd> C;
+    heev(G, m, theta, C);
+    if ((rc = dev_lincomb_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
+    if ((rc = dev_lincomb_real(c, rvecs(c, B_HX, 0, m), rvecs(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
+    std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
+    std::swap(c.s->buf[B_HX], c.s->buf[B_HXN]);
+    return IWFPM_OK;
+}
+
+static int apply_real(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats* stats) {
+    if (cnt <= 0) return IWFPM_OK;
+    int rc = plan_apply(c.p, c.col(bin, 0), c.col(bout, 0), (cnt + 1) / 2, prec, c.st);
+    if (stats) stats->matvecs += cnt;
+    return rc;
+}
+
+static int run_real(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, double* evals, void* evecs, double* eta_out,
+                    iwfpm_stats* stats, hipStream_t st) {
+    const int nev = o.nev;
+    int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
+    if (m < nev || m > 32) return IWFPM_ERR_ARG;
+    if (m > p->geom.N) return IWFPM_ERR_ARG;
+    int rc = solver_ensure(p, m);
+    if (rc) return rc;
+    int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
+    if ((rc = solver_precond(p, pk))) return rc;
+    Solver* s = (Solver*)p->solver;
+    Ctx c{p, s, st, p->geom.N};
+    const long long N = c.N;
+    const double hnorm = p->lam_max + p->vsum_abs;
+    int prec = p->opts.precision;
+    if (!p->sched[prec].ok) prec = 1 - prec;
+    if (!p->sched[prec].ok) return IWFPM_ERR_UNSUPPORTED;
+    const bool can64 = p->sched[0].ok;
+    const char* venv = std::getenv("IWFPM_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
+    const bool explicit_ortho = force_explicit_ortho();
+    LearnedPrecond* lp = nullptr;
+    if (o.precond == IWFPM_PRECOND_LEARNED) {
+        lp = p->learned;
+        if (!lp || !learned_ready(lp, p)) return IWFPM_ERR_WEIGHTS;
+    }
+    const double* Mdiag = (const double*)s->M.ptr;
+
+    // start block: the real and imaginary parts of a seeded complex block
+    CHECK_HIP(randn(c.col(B_X, 0), N * ((m + 1) / 2), o.seed, st));
+    {
+        std::vector<cd> G, T;
+        if ((rc = host_gram_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_X, 0, m), G))) return rc;
+        hermitian_part(G, m);
+        int r = svqb(G, m, T);
+        if (r < m) return IWFPM_ERR_NUMERIC;
+        if ((rc = dev_lincomb_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_XN, 0, m), T, m, 0, 0.0))) return rc;
+        std::swap(s->buf[B_X], s->buf[B_XN]);
+    }
+    if ((rc = apply_real(c, B_X, B_HX, m, prec, stats))) return rc;
+    std::vector<double> theta;
+    if ((rc = rr_block_real(c, m, theta))) return rc;
+
+    int mp = 0;
+    std::vector<double> eta(m, 1.0);
+    int it = 0, polished = 0, fallback = 0, reortho = 0;
+    double best_eta = 1e300;
+    int best_it = 0;
+    int status = IWFPM_OK;
+    const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
+    double* dNorm = (double*)((double2*)s->small.ptr + 96 * 96);
+    const int mc = (m + 1) / 2;
+    for (;;) {
+        // residuals R = HX - X theta (two per column) and their norms
+        {
+            ColPtrs hx{}, x{}, r{};
+            Reals th{};
+            for (int j = 0; j < mc; ++j) {
+                hx.p[j] = c.col(B_HX, j);
+                x.p[j] = c.col(B_X, j);
+                r.p[j] = c.col(B_T1, j);
+            }
+            for (int v = 0; v < 2 * mc; ++v) th.v[v] = v < m ? theta[v] : 0.0;
+            CHECK_HIP(residual_norm_pairs(hx, x, r, th, mc, N, (double*)s->partial.ptr, s->max_blocks, dNorm, st));
+            double* h = (double*)(s->hsmall + 96 * 96);
+            CHECK_HIP(hipMemcpyAsync(h, dNorm, 2 * mc * sizeof(double), hipMemcpyDeviceToHost, st));
+            if ((rc = sync(c))) return rc;
+            for (int j = 0; j < m; ++j) {
+                eta[j] = std::sqrt(std::max(0.0, h[j])) / (hnorm + std::fabs(theta[j]));
+                if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
+            }
+        }
+        int conv = 0;
+        double worst = 0.0;
+        for (int j = 0; j < nev; ++j) {
+            conv += eta[j] <= o.tol;
+            worst = std::max(worst, eta[j]);
+        }
+        if (verbose)
+            std::fprintf(stderr,
+                         "[iwfpm_eigs real] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n", it,
+                         prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
+        if (conv == nev) {
+            if (prec == 0 || !can64) break;
+            prec = 0;
+            if ((rc = apply_real(c, B_X, B_HX, m, 0, stats))) return rc;
+            if (mp > 0 && (rc = apply_real(c, B_P, B_HP, mp, 0, stats))) return rc;
+            if ((rc = rr_block_real(c, m, theta))) return rc;
+            continue;
+        }
+        if (it >= o.maxit) {
+            status = IWFPM_ERR_NOCONV;
+            break;
+        }
+        bool stalled = false;
+        if (worst < 0.5 * best_eta) {
+            best_eta = worst;
+            best_it = it;
+        } else {
+            stalled = worst < 1e-5 && it - best_it >= 20;
+        }
+        if (lp && it - best_it >= 50) {
+            fallback = 1;
+            lp = nullptr;
+            best_it = it;
+        }
+        if (prec == 1 && o.polish && can64 && (worst < floor32 || stalled)) {
+            prec = 0;
+            if ((rc = apply_real(c, B_X, B_HX, m, 0, stats))) return rc;
+            if (mp > 0 && (rc = apply_real(c, B_P, B_HP, mp, 0, stats))) return rc;
+            if ((rc = rr_block_real(c, m, theta))) return rc;
+            best_eta = 1e300;
+            continue;
+        }
+        ++it;
+        if (prec == 0 && p->opts.precision == 1) ++polished;
+
+        // active set; W = M R_A (or the learned map of R_A), packed two per column
+        std::vector<int> act;
+        for (int j = 0; j < m; ++j)
+            if (eta[j] > o.tol) act.push_back(j);
+        const int ma = (int)act.size();
+        std::vector<RVec> Ract(ma);
+        for (int a = 0; a < ma; ++a) Ract[a] = {c.col(B_T1, act[a] >> 1), act[a] & 1};
+        unsigned long long rparts = 0;
+        const ColPtrs rsrc = colptrs(Ract, &rparts);
+        const int mac = (ma + 1) / 2;
+        ColPtrs wdst{};
+        for (int j = 0; j < mac; ++j) wdst.p[j] = c.col(B_W, j);
+        bool lp_used = false;
+        if (lp) {
+            // R_A packed into the (still free) HW buffer, then W = T(R_A)
+            ColPtrs rp{};
+            for (int j = 0; j < mac; ++j) rp.p[j] = c.col(B_HW, j);
+            CHECK_HIP(gather_pairs(rsrc, rparts, ma, rp, nullptr, N, st));
+            if (learned_apply(lp, p, rp, wdst, mac, st) == IWFPM_OK) lp_used = true;
+            else {
+                fallback = 1;
+                lp = nullptr;
+            }
+        }
+        if (!lp_used) CHECK_HIP(gather_pairs(rsrc, rparts, ma, wdst, Mdiag, N, st));
+        std::vector<RVec> Pa = rvecs(c, B_P, 0, mp), HPa = rvecs(c, B_HP, 0, mp);
+        const int mq = mp;
+        int mw = 0;
+        {
+            std::vector<RVec> XP = rvecs(c, B_X, 0, m);
+            XP.insert(XP.end(), Pa.begin(), Pa.end());
+            const int nx = (int)XP.size();
+            std::vector<RVec> XPW = XP, Wv = rvecs(c, B_W, 0, ma);
+            XPW.insert(XPW.end(), Wv.begin(), Wv.end());
+            std::vector<cd> Gall, Cm;
+            if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
+            if (lp_used) {
+                bool finite = true;
+                for (int j = 0; j < ma; ++j)
+                    finite = finite && std::isfinite(Gall[(size_t)(nx + j) + (size_t)j * (nx + ma)].real());
+                if (!finite) {
+                    fallback = 1;
+                    lp = nullptr;
+                    CHECK_HIP(gather_pairs(rsrc, rparts, ma, wdst, Mdiag, N, st));
+                    if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
+                }
+            }
+            if (!explicit_ortho && ortho_coefficients(Gall, nx, ma, Cm, mw)) {
+                if ((rc = dev_lincomb_real(c, XPW, rvecs(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
+            } else {
+                ++reortho;
+                for (int pass = 0; pass < 2; ++pass) {
+                    std::vector<cd> G;
+                    if ((rc = host_gram_real(c, XP, Wv, G))) return rc;
+                    for (auto& g : G) g = -g;
+                    if ((rc = dev_lincomb_real(c, XP, Wv, G, nx, 0, 1.0))) return rc;
+                }
+                std::vector<cd> G, T;
+                if ((rc = host_gram_real(c, Wv, Wv, G))) return rc;
+                hermitian_part(G, ma);
+                mw = svqb(G, ma, T, 1e-10);
+                if ((rc = dev_lincomb_real(c, Wv, rvecs(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
+            }
+            std::swap(s->buf[B_W], s->buf[B_T1]);
+        }
+        if ((rc = apply_real(c, B_W, B_HW, mw, prec, stats))) return rc;
+        // Rayleigh-Ritz on S = [X W P_A]
+        const int ns = m + mw + mq;
+        std::vector<RVec> S = rvecs(c, B_X, 0, m), HS = rvecs(c, B_HX, 0, m);
+        {
+            auto Wn = rvecs(c, B_W, 0, mw), HWn = rvecs(c, B_HW, 0, mw);
+            S.insert(S.end(), Wn.begin(), Wn.end());
+            HS.insert(HS.end(), HWn.begin(), HWn.end());
+        }
+        Pa = rvecs(c, B_P, 0, mq);
+        HPa = rvecs(c, B_HP, 0, mq);
+        S.insert(S.end(), Pa.begin(), Pa.end());
+        HS.insert(HS.end(), HPa.begin(), HPa.end());
+        std::vector<double> th;
+        std::vector<cd> U;
+        int mpn = 0;
+        {
+            std::vector<RVec> HR(HS.begin() + m, HS.end());
+            std::vector<cd> G;
+            if ((rc = host_gram_real(c, S, HR, G))) return rc;
+            mpn = rr_coefficients(G, theta, m, ns, act, th, U);
+        }
+        // [X_new | P_new] = S U, [HX_new | HP_new] = HS U
+        {
+            std::vector<RVec> out = rvecs(c, B_XN, 0, m), hout = rvecs(c, B_HXN, 0, m);
+            auto pn = rvecs(c, B_PN, 0, mpn), hpn = rvecs(c, B_HPN, 0, mpn);
+            out.insert(out.end(), pn.begin(), pn.end());
+            hout.insert(hout.end(), hpn.begin(), hpn.end());
+            if ((rc = dev_lincomb_real(c, S, out, U, ns, 0, 0.0))) return rc;
+            if ((rc = dev_lincomb_real(c, HS, hout, U, ns, 0, 0.0))) return rc;
+            std::swap(s->buf[B_X], s->buf[B_XN]);
+            std::swap(s->buf[B_HX], s->buf[B_HXN]);
+            std::swap(s->buf[B_P], s->buf[B_PN]);
+            std::swap(s->buf[B_HP], s->buf[B_HPN]);
+            mp = mpn;
+        }
+        theta.assign(th.begin(), th.begin() + m);
+    }
+    if (stats) {
+        stats->iterations = it;
+        stats->restarts = 0;
+        stats->fallback = fallback;
+        stats->polished = polished;
+        int conv = 0;
+        for (int j = 0; j < nev; ++j) conv += eta[j] <= o.tol;
+        stats->converged = conv;
+    }
+    for (int j = 0; j < nev; ++j) {
+        evals[j] = theta[j];
+        if (eta_out) eta_out[j] = eta[j];
+    }
+    if (evecs) {
+        unsigned long long parts = 0;
+        const ColPtrs src = colptrs(rvecs(c, B_X, 0, nev), &parts);
+        ColPtrs dst{};
+        for (int j = 0; j < nev; ++j) dst.p[j] = (double2*)evecs + (size_t)j * N;
+        CHECK_HIP(unpack_real(src, parts, nev, dst, N, st));
+    }
+    if ((rc = sync(c))) return rc;
+    return status;
+}
+
+// every potential coefficient real: H~ is real symmetric
+static bool real_symmetric(const iwfpm_plan_s* p) {
+    for (double v : p->vim)
+        if (v != 0.0) return false;
+    return true;
+}
+
 int eigs_capture(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, Capture* cap, double* evals, void* evecs,
                  hipStream_t st) {
     if (o.nev < 1 || o.nev > p->geom.N || !cap || cap->ncol > o.nev) return IWFPM_ERR_ARG;
@@ -1831,6 +2234,7 @@ void iwfpm_default_eigs_opts(iwfpm_eigs_opts* o) {
     o->precond = IWFPM_PRECOND_PLAIN;
     o->seed = 2404045070ull;
     o->polish = 1;
+    o->arith = 0;
 }
 
 int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, double* evals, void* evecs, double* eta,
@@ -1841,9 +2245,13 @@ int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, doub
     if (p->host_only) return IWFPM_ERR_NODEVICE;
     DeviceGuard guard(p->opts.device);
     if (!guard.ok) return IWFPM_ERR_DEVICE;
+    if (opts->arith < 0 || opts->arith > 2) return IWFPM_ERR_ARG;
+    const bool real = opts->arith == 2 || (opts->arith == 0 && !x0 && real_symmetric(p));
+    if (real && (x0 || !real_symmetric(p))) return IWFPM_ERR_ARG;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     auto t0 = std::chrono::steady_clock::now();
-    int rc = run(p, *opts, x0, evals, evecs, eta, stats, (hipStream_t)stream);
+    int rc = real ? run_real(p, *opts, evals, evecs, eta, stats, (hipStream_t)stream)
+                  : run(p, *opts, x0, evals, evecs, eta, stats, (hipStream_t)stream);
     if (stats) stats->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }

@@ -99,6 +99,49 @@ def test_ragged_basis_wide_block(prec):
     check_pairs_with_oracle(prob, r, 16, 1e-10)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nev,block", [(16, 0), (5, 7)])
+def test_real_symmetric_solver_matches_complex(prec, nev, block):
+    """Real V-hat makes H~ real symmetric: the real solver (two real trial
+    vectors per complex column; an odd block leaves a zero half) returns the
+    complex solver's eigenvalues and real eigenvectors that pass the oracle's
+    residual check."""
+    prob = W.c2_2d(lam=5.0, K=3, L=4)
+    print(f"case: real vs complex LOBPCG nev={nev} block={block} {prec}", flush=True)
+    with lib.Plan.from_problem(prob, precision=prec) as p:
+        a = p.eigs(nev, block=block, tol=1e-10, maxit=800, arith="real")
+        b = p.eigs(nev, block=block, tol=1e-10, maxit=800, arith="complex")
+    ref = dense_ref(prob, nev)
+    bar = 1e-10 if prec == "fp64" else 1e-5
+    for r in (a, b):
+        assert np.all(np.abs(r.evals - ref) <= bar * np.maximum(1.0, np.abs(ref))), (r.evals - ref)
+    assert torch.count_nonzero(a.evecs.imag).item() == 0
+    check_pairs_with_oracle(prob, a, nev, 1e-10)
+
+
+def test_real_solver_needs_real_potential():
+    """A potential with complex coefficients keeps the complex solver under
+    "auto" and refuses "real"."""
+    rng = np.random.default_rng(5)
+    modes, vhat = [[0, 0, 0, 0]], [1.5]
+    for _ in range(3):
+        m = rng.integers(-2, 3, size=4)
+        if not m.any():
+            continue
+        c = complex(rng.standard_normal(), rng.standard_normal())
+        modes += [list(m), list(-m)]
+        vhat += [c, c.conjugate()]
+    prob = W.Problem("general", 2, W.rot_pair_P(), [3, 2], [2, 3], np.array(modes), np.array(vhat))
+    print("case: complex potential, real solver refused", flush=True)
+    with lib.Plan.from_problem(prob) as p:
+        r = p.eigs(4, tol=1e-10, maxit=800)
+        H = O.hamiltonian_sparse(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, "exact").toarray()
+        ref = np.linalg.eigvalsh(H)[:4]
+        assert np.all(np.abs(r.evals - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref)))
+        with pytest.raises(lib.IwfpmError):
+            p.eigs(4, tol=1e-10, maxit=800, arith="real")
+
+
 @pytest.mark.parametrize("lam", [0.5, 5.0])
 def test_explicit_orthonormalisation_route(lam, monkeypatch):
     """The explicit route (projection twice + SVQB), taken when the one-pass
