@@ -240,8 +240,9 @@ void iwfpm_default_eigs_opts(iwfpm_eigs_opts* opts);
  * symmetric matrix) are solved by default in real arithmetic: real trial
  * vectors stored two per complex column, the real and imaginary halves
  * applied together; the returned eigenvectors are then real (zero imaginary
- * parts).  opts->arith chooses explicitly; iwfpm_eigs_batched and the
- * learned preconditioner's training solves always use complex arithmetic.
+ * parts).  opts->arith chooses explicitly (iwfpm_eigs_batched likewise, real
+ * when every plan is real symmetric); the learned preconditioner's training
+ * solves always use complex arithmetic.
  * x0: device, N x m start block (m = block size) or NULL for a seeded random start.
  * evals, eta: host, nev float64 (eta may be NULL).  evecs: device, N x nev
  * complex float64, or NULL.  stats may be NULL.  Blocking (synchronises stream).

@@ -255,7 +255,7 @@ class Batch:
 
 
 def eigs_batched(plans, nev, tol=1e-8, maxit=500, block=0, precond="plain", seed=2404045070, polish=True,
-                 stream=None, allow_noconv=False):
+                 stream=None, allow_noconv=False, arith="auto"):
     """Lowest nev eigenpairs of every plan, solved in lock step (iwfpm_eigs_batched)."""
     lib = _lib()
     B = len(plans)
@@ -263,6 +263,7 @@ def eigs_batched(plans, nev, tol=1e-8, maxit=500, block=0, precond="plain", seed
     lib.iwfpm_default_eigs_opts(ctypes.byref(o))
     o.nev, o.block, o.tol, o.maxit = int(nev), int(block), float(tol), int(maxit)
     o.precond, o.seed, o.polish = PRECOND[precond], int(seed), int(bool(polish))
+    o.arith = ARITH[arith]
     evals = np.zeros((B, nev))
     eta = np.zeros((B, nev))
     stats = (_Stats * B)()

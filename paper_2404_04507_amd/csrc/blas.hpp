@@ -60,6 +60,7 @@ struct GramJob {
     long long N, groups_per_block;  // 4-row groups per block
     int nb, start, out_start;
     long long part_off;  // offset of this job's partials (entries)
+    int width = 1;       // entries per (column, column) pair: 1 complex, 2 for a real 2 x 2 block
 };
 struct LinJob {
     ColPtrs A, Y;
@@ -74,6 +75,14 @@ struct ResJob {
     long long N, rows_per_block;
     int m, nb, start, out_start;
     long long part_off;
+    int width = 1;  // norms per column: 1, or 2 with two real vectors per column
+};
+struct GatherJob {
+    ColPtrs src, dst;
+    unsigned long long parts;
+    const double* M;
+    long long N;
+    int n, nb, start;
 };
 struct PreJob {
     ColPtrs R, W;
@@ -91,5 +100,12 @@ hipError_t lincomb_batched(const LinJob* jobs, int njobs, int total_blocks, int 
 hipError_t residual_norm_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,
                                  double* out, hipStream_t st);
 hipError_t precond_batched(const PreJob* jobs, int njobs, int total_blocks, hipStream_t st);
+// batched forms of the pair kernels (jobs: width 2; LinJob.C real 2p x 2q as pairs of doubles)
+hipError_t gram_batched_pairs(const GramJob* jobs, int njobs, int total_blocks, int total_out, int maxp, int maxq,
+                              double2* partial, double2* C, hipStream_t st);
+hipError_t lincomb_pairs_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st);
+hipError_t residual_norm_pairs_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,
+                                       double* out, hipStream_t st);
+hipError_t gather_pairs_batched(const GatherJob* jobs, int njobs, int total_blocks, hipStream_t st);
 
 }  // namespace iwfpm

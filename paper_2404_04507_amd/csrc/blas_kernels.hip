@@ -458,11 +458,11 @@ __global__ void k_precond(ColPtrs R, ColPtrs W, int m, const double* __restrict_
 // two real vectors per complex column: R = HX - X diag(theta) with one theta
 // per real vector (theta[2j] for the real parts of column j, theta[2j+1] for
 // the imaginary parts) and one squared norm per real vector
-__global__ void __launch_bounds__(256) k_residual_norm_pairs(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
-                                                             long long N, long long rows_per_block,
-                                                             double* __restrict__ partial) {
-    __shared__ double red[2][256];
-    const long long r0 = (long long)blockIdx.x * rows_per_block;
+__device__ __forceinline__ void residual_norm_pairs_body(const ColPtrs& HX, const ColPtrs& X, const ColPtrs& Rout,
+                                                         const Reals& theta, int m, long long N,
+                                                         long long rows_per_block, double* __restrict__ partial,
+                                                         int bid, double (*red)[256]) {
+    const long long r0 = (long long)bid * rows_per_block;
     const long long r1 = min(N, r0 + rows_per_block);
     for (int j = 0; j < m; ++j) {
         double s0 = 0.0, s1 = 0.0;
@@ -485,20 +485,27 @@ __global__ void __launch_bounds__(256) k_residual_norm_pairs(ColPtrs HX, ColPtrs
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            partial[(size_t)blockIdx.x * 2 * m + 2 * j] = red[0][0];
-            partial[(size_t)blockIdx.x * 2 * m + 2 * j + 1] = red[1][0];
+            partial[(size_t)bid * 2 * m + 2 * j] = red[0][0];
+            partial[(size_t)bid * 2 * m + 2 * j + 1] = red[1][0];
         }
         __syncthreads();
     }
 }
 
+__global__ void __launch_bounds__(256) k_residual_norm_pairs(ColPtrs HX, ColPtrs X, ColPtrs Rout, Reals theta, int m,
+                                                             long long N, long long rows_per_block,
+                                                             double* __restrict__ partial) {
+    __shared__ double red[2][256];
+    residual_norm_pairs_body(HX, X, Rout, theta, m, N, rows_per_block, partial, blockIdx.x, red);
+}
+
 // packs n real vectors (vector v: part (bit v of parts) of column src[v]),
 // scaled by M when given, two per destination column; the imaginary half of
 // the last column is zero when n is odd
-__global__ void k_gather_pairs(ColPtrs src, unsigned long long parts, int n, ColPtrs dst,
-                               const double* __restrict__ M, long long N) {
+__device__ __forceinline__ void gather_pairs_body(const ColPtrs& src, unsigned long long parts, int n, const ColPtrs& dst,
+                                                  const double* __restrict__ M, long long N, int bid, int nb) {
     const int nd = (n + 1) >> 1;
-    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (long long)gridDim.x * blockDim.x) {
+    for (long long r = (long long)bid * blockDim.x + threadIdx.x; r < N; r += (long long)nb * blockDim.x) {
         const double mm = M ? M[r] : 1.0;
         for (int d = 0; d < nd; ++d) {
             const int v0 = 2 * d, v1 = 2 * d + 1;
@@ -511,6 +518,11 @@ __global__ void k_gather_pairs(ColPtrs src, unsigned long long parts, int n, Col
             dst.p[d][r] = make_double2(mm * (((parts >> v0) & 1) ? a.y : a.x), mm * b);
         }
     }
+}
+
+__global__ void k_gather_pairs(ColPtrs src, unsigned long long parts, int n, ColPtrs dst,
+                               const double* __restrict__ M, long long N) {
+    gather_pairs_body(src, parts, n, dst, M, N, blockIdx.x, gridDim.x);
 }
 
 // complex column v = (real vector v, 0), vector v being part (bit v) of src[v]
@@ -585,7 +597,7 @@ __global__ void __launch_bounds__(256) k_reduce_batched(const GramJob* __restric
         else hi = mid - 1;
     }
     const GramJob& jb = jobs[lo];
-    const int le = e - jb.out_start, cnt = jb.p * jb.q;
+    const int le = e - jb.out_start, cnt = jb.p * jb.q * jb.width;
     double2 s = make_double2(0.0, 0.0);
     for (int b = threadIdx.x; b < jb.nb; b += 256) {
         double2 v = partial[jb.part_off + (size_t)b * cnt + le];
@@ -646,7 +658,7 @@ __global__ void __launch_bounds__(256) k_reduce_res_batched(const ResJob* __rest
     const ResJob& jb = jobs[lo];
     const int le = e - jb.out_start;
     double s = 0.0;
-    for (int b = threadIdx.x; b < jb.nb; b += 256) s += partial[jb.part_off + (size_t)b * jb.m + le];
+    for (int b = threadIdx.x; b < jb.nb; b += 256) s += partial[jb.part_off + (size_t)b * (jb.m * jb.width) + le];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -654,6 +666,41 @@ __global__ void __launch_bounds__(256) k_reduce_res_batched(const ResJob* __rest
         __syncthreads();
     }
     if (threadIdx.x == 0) out[e] = red[0];
+}
+
+template <int TQ>
+__global__ void __launch_bounds__(256) k_gram_batched_pairs(const GramJob* __restrict__ jobs, int njobs,
+                                                            double2* __restrict__ partial) {
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const GramJob& jb = jobs[j];
+    if ((int)(threadIdx.x >> 6) * 16 >= jb.p) return;
+    gram_body<TQ, true>(jb.L, jb.p, jb.R, jb.q, jb.N, jb.groups_per_block, partial + jb.part_off,
+                        blockIdx.x - jb.start);
+}
+
+template <int QG>
+__global__ void __launch_bounds__(256) k_lincomb_pairs_batched(const LinJob* __restrict__ jobs, int njobs) {
+    __shared__ double2 sC[kMaxCols * 32];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const LinJob& jb = jobs[j];
+    for (int e = threadIdx.x; e < 2 * jb.p * jb.q; e += blockDim.x) sC[e] = jb.C[e];
+    __syncthreads();
+    lincomb_rows_body<QG, true>(jb.A, jb.p, jb.Y, jb.q, sC, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb);
+}
+
+__global__ void __launch_bounds__(256) k_residual_norm_pairs_batched(const ResJob* __restrict__ jobs, int njobs,
+                                                                     double* __restrict__ partial) {
+    __shared__ double red[2][256];
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const ResJob& jb = jobs[j];
+    residual_norm_pairs_body(jb.HX, jb.X, jb.R, jb.theta, jb.m, jb.N, jb.rows_per_block, partial + jb.part_off,
+                             blockIdx.x - jb.start, red);
+}
+
+__global__ void __launch_bounds__(256) k_gather_pairs_batched(const GatherJob* __restrict__ jobs, int njobs) {
+    const int j = find_job(jobs, njobs, blockIdx.x);
+    const GatherJob& jb = jobs[j];
+    gather_pairs_body(jb.src, jb.parts, jb.n, jb.dst, jb.M, jb.N, blockIdx.x - jb.start, jb.nb);
 }
 
 __global__ void __launch_bounds__(256) k_precond_batched(const PreJob* __restrict__ jobs, int njobs) {
@@ -842,6 +889,44 @@ hipError_t residual_norm_batched(const ResJob* jobs, int njobs, int total_blocks
     if (njobs <= 0) return hipSuccess;
     k_residual_norm_batched<<<total_blocks, 256, 0, st>>>(jobs, njobs, partial);
     k_reduce_res_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t gram_batched_pairs(const GramJob* jobs, int njobs, int total_blocks, int total_out, int maxp, int maxq,
+                              double2* partial, double2* C, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    const int threads = 64 * ((maxp + 15) >> 4), TQ = (maxq + 15) >> 4;
+    switch (TQ) {
+        case 1: k_gram_batched_pairs<1><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        case 2: k_gram_batched_pairs<2><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        case 3: k_gram_batched_pairs<3><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+        default: k_gram_batched_pairs<4><<<total_blocks, threads, 0, st>>>(jobs, njobs, partial); break;
+    }
+    k_reduce_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, C);
+    return hipGetLastError();
+}
+
+hipError_t lincomb_pairs_batched(const LinJob* jobs, int njobs, int total_blocks, int maxq, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    if (maxq > 32) return hipErrorInvalidValue;
+    const int qg = (maxq + 3) >> 2;
+    if (qg <= 2) k_lincomb_pairs_batched<2><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (qg <= 4) k_lincomb_pairs_batched<4><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else k_lincomb_pairs_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    return hipGetLastError();
+}
+
+hipError_t residual_norm_pairs_batched(const ResJob* jobs, int njobs, int total_blocks, int total_out, double* partial,
+                                       double* out, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    k_residual_norm_pairs_batched<<<total_blocks, 256, 0, st>>>(jobs, njobs, partial);
+    k_reduce_res_batched<<<total_out, 256, 0, st>>>(jobs, njobs, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t gather_pairs_batched(const GatherJob* jobs, int njobs, int total_blocks, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    k_gather_pairs_batched<<<total_blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
 

@@ -764,13 +764,48 @@ static void hermitian_part(std::vector<cd>& A, int n) {
 }
 
 // Rayleigh-Ritz on the block X alone (orthonormal X, HX = H X): X <- X C, HX <- HX C
+// Rayleigh-Ritz of X alone with X first made orthonormal again (the block
+// updates keep it so only up to accumulated rounding): from the Gram
+// G = X^H [X HX] (m x 2m), T = SVQB(X^H X) and the eigenvectors C of
+// T^H (X^H H X) T; the update is X <- X (T C), HX <- HX (T C).  false if X
+// has lost rank.
+static bool rr_transform(const std::vector<cd>& G, int m, std::vector<double>& theta, std::vector<cd>& TC) {
+    std::vector<cd> Gxx(G.begin(), G.begin() + (size_t)m * m), T;
+    if (svqb(Gxx, m, T) < m) return false;
+    std::vector<cd> A((size_t)m * m, 0.0), GT((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j)  // (X^H H X) T
+        for (int i = 0; i < m; ++i) {
+            cd acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += G[(size_t)i + (size_t)(m + k) * m] * T[k + (size_t)j * m];
+            GT[i + (size_t)j * m] = acc;
+        }
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            cd acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += std::conj(T[k + (size_t)i * m]) * GT[k + (size_t)j * m];
+            A[i + (size_t)j * m] = acc;
+        }
+    hermitian_part(A, m);
+    std::vector<cd> C;
+    heev(A, m, theta, C);
+    TC.assign((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < m; ++i) {
+            cd acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += T[i + (size_t)k * m] * C[k + (size_t)j * m];
+            TC[i + (size_t)j * m] = acc;
+        }
+    return true;
+}
+
 static int rr_block(Ctx& c, int m, std::vector<double>& theta) {
     std::vector<cd> G;
-    int rc = host_gram(c, cols(c, B_X, 0, m), cols(c, B_HX, 0, m), G);
+    std::vector<double2*> XHX = cols(c, B_X, 0, m), HX = cols(c, B_HX, 0, m);
+    XHX.insert(XHX.end(), HX.begin(), HX.end());
+    int rc = host_gram(c, cols(c, B_X, 0, m), XHX, G);
     if (rc) return rc;
-    hermitian_part(G, m);
     std::vector<cd> C;
-    heev(G, m, theta, C);
+    if (!rr_transform(G, m, theta, C)) return IWFPM_ERR_NUMERIC;
     if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
     if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), cols(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
     std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
@@ -850,13 +885,21 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
     return mpn;
 }
 
-// One-pass orthonormalisation of the new directions W (ma columns) against
-// the orthonormal [X P] (nx columns), in coefficient space.  Gall is the Gram
-// [X P W]^H W ((nx + ma) x ma).  With G = [X P]^H W, the complement W - [X P] G
-// has the Gram W^H W - G^H G; when no column loses more than a factor 10 of
-// its norm to [X P] (cancellation at most 100 ulp), SVQB of that Gram gives T
-// and the new block is [X P W] Cm with Cm = [-G T; T] ((nx + ma) x mw).
-// Returns false otherwise (the caller then projects explicitly, twice).
+// Second projection and orthonormalisation of the new directions W (ma
+// columns) against the orthonormal [X P] (nx columns), in coefficient space,
+// after one explicit projection W <- W - [X P] ([X P]^H W).  Gall is the Gram
+// [X P W]^H W ((nx + ma) x ma) of the projected W.  With G = [X P]^H W (now
+// small: what the first projection left, including the effect of any loss of
+// orthonormality in [X P] itself), the complement W - [X P] G has the Gram
+// Gc = W^H W - G^H G, in which nothing cancels any more; SVQB of Gc gives T
+// (dropping dependent directions) and the new block is [X P W] Cm,
+// Cm = [-G T; T] ((nx + ma) x mw).  Together with the explicit first pass this
+// is the classical project-twice scheme, with the second pass, the Gram of the
+// result and its combination folded into one Gram and one combination.  (A
+// single projection in coefficient space is not enough: it takes [X P] as
+// exactly orthonormal, so any drift there passes into W and then into the
+// next X and P, and accumulates.)  Returns false when the Gram is not finite
+// or nothing is left (the caller then projects explicitly).
 static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std::vector<cd>& Cm, int& mw) {
     const int ld = nx + ma;
     std::vector<cd> Gc((size_t)ma * ma);
@@ -866,10 +909,8 @@ static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std:
             for (int k = 0; k < nx; ++k) acc -= std::conj(Gall[k + (size_t)i * ld]) * Gall[k + (size_t)j * ld];
             Gc[i + (size_t)j * ma] = acc;
         }
-    for (int j = 0; j < ma; ++j) {
-        const double full = Gall[(size_t)(nx + j) + (size_t)j * ld].real(), rest = Gc[j + (size_t)j * ma].real();
-        if (!std::isfinite(full) || !std::isfinite(rest) || !(rest > 0.01 * full)) return false;
-    }
+    for (int j = 0; j < ma; ++j)
+        if (!std::isfinite(Gc[j + (size_t)j * ma].real()) || !(Gc[j + (size_t)j * ma].real() > 0.0)) return false;
     hermitian_part(Gc, ma);
     std::vector<cd> T;
     mw = svqb(Gc, ma, T, 1e-10);
@@ -886,8 +927,17 @@ static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std:
     return true;
 }
 
-// IWFPM_ORTHO=explicit: always project explicitly (twice) and SVQB, the route
-// taken when the one-pass form would cancel too much
+// -G (the [X P] rows of a Gram [X P W]^H W, negated): the coefficients of one
+// explicit projection W <- W - [X P] G
+static std::vector<cd> neg_projection(const std::vector<cd>& Gall, int nx, int ma) {
+    std::vector<cd> G((size_t)nx * ma);
+    for (int j = 0; j < ma; ++j)
+        for (int k = 0; k < nx; ++k) G[k + (size_t)j * nx] = -Gall[k + (size_t)j * (nx + ma)];
+    return G;
+}
+
+// IWFPM_ORTHO=explicit: always project explicitly twice and apply SVQB to the
+// result (the route taken when the coefficient-space second pass fails)
 static bool force_explicit_ortho() {
     const char* e = std::getenv("IWFPM_ORTHO");
     return e && std::strcmp(e, "explicit") == 0;
@@ -942,6 +992,7 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
     int mp = 0;
     std::vector<double> eta(m, 1.0);
     int it = 0, polished = 0, fallback = 0, reortho = 0;
+    bool cleaned = false;
     double best_eta = 1e300;
     int best_it = 0;
     int status = IWFPM_OK;
@@ -986,7 +1037,13 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
             std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n",
                          it, prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
         if (conv == nev) {
-            if (prec == 0 || !can64) break;
+            if ((prec == 0 || !can64) && cleaned) break;
+            cleaned = true;
+            if (prec == 0 || !can64) {
+                // re-orthonormalise X and take the Ritz pairs once more, then confirm
+                if ((rc = rr_block(c, m, theta))) return rc;
+                continue;
+            }
             // confirm with float64 applies (Rayleigh-Ritz of X with the float64 H)
             prec = 0;
             if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
@@ -1053,8 +1110,8 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
         std::vector<double2*> Pa = cols(c, B_P, 0, mp), HPa = cols(c, B_HP, 0, mp);
         const int mq = mp;
         // W <- orthonormal basis of the part of W orthogonal to [X P_A]: one
-        // Gram and one combination when little cancels, else the explicit
-        // projection twice and SVQB
+        // explicit projection with the Gram [X P W]^H W, then the second
+        // projection and SVQB in coefficient space (explicit twice as fallback)
         int mw = 0;
         {
             std::vector<double2*> XP = cols(c, B_X, 0, m);
@@ -1081,9 +1138,18 @@ static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double
                     if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
                 }
             }
-            if (!explicit_ortho && ortho_coefficients(Gall, nx, ma, Cm, mw)) {
-                if ((rc = dev_lincomb(c, XPW, cols(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
-            } else {
+            bool done = false;
+            if (!explicit_ortho) {
+                // one explicit projection, then the second one and SVQB in coefficient space
+                const std::vector<cd> G1 = neg_projection(Gall, nx, ma);
+                if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G1, nx, 0, 1.0))) return rc;
+                if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
+                if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
+                    if ((rc = dev_lincomb(c, XPW, cols(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
+                    done = true;
+                }
+            }
+            if (!done) {
                 ++reortho;
                 for (int pass = 0; pass < 2; ++pass) {
                     std::vector<cd> G;
@@ -1288,11 +1354,12 @@ static ColPtrs colptrs(const std::vector<RVec>& v, unsigned long long* parts) {
 // Rayleigh-Ritz on X alone: X <- X C, HX <- HX C (real)
 static int rr_block_real(Ctx& c, int m, std::vector<double>& theta) {
     std::vector<cd> G;
-    int rc = host_gram_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_HX, 0, m), G);
+    std::vector<RVec> XHX = rvecs(c, B_X, 0, m), HX = rvecs(c, B_HX, 0, m);
+    XHX.insert(XHX.end(), HX.begin(), HX.end());
+    int rc = host_gram_real(c, rvecs(c, B_X, 0, m), XHX, G);
     if (rc) return rc;
-    hermitian_part(G, m);
     std::vector<cd> C;
-    heev(G, m, theta, C);
+    if (!rr_transform(G, m, theta, C)) return IWFPM_ERR_NUMERIC;
     if ((rc = dev_lincomb_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
     if ((rc = dev_lincomb_real(c, rvecs(c, B_HX, 0, m), rvecs(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
     std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
@@ -1353,6 +1420,7 @@ static int run_real(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, double* evals, vo
     int mp = 0;
     std::vector<double> eta(m, 1.0);
     int it = 0, polished = 0, fallback = 0, reortho = 0;
+    bool cleaned = false;
     double best_eta = 1e300;
     int best_it = 0;
     int status = IWFPM_OK;
@@ -1390,7 +1458,12 @@ static int run_real(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, double* evals, vo
                          "[iwfpm_eigs real] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n", it,
                          prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
         if (conv == nev) {
-            if (prec == 0 || !can64) break;
+            if ((prec == 0 || !can64) && cleaned) break;
+            cleaned = true;
+            if (prec == 0 || !can64) {
+                if ((rc = rr_block_real(c, m, theta))) return rc;
+                continue;
+            }
             prec = 0;
             if ((rc = apply_real(c, B_X, B_HX, m, 0, stats))) return rc;
             if (mp > 0 && (rc = apply_real(c, B_P, B_HP, mp, 0, stats))) return rc;
@@ -1471,9 +1544,18 @@ static int run_real(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, double* evals, vo
                     if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
                 }
             }
-            if (!explicit_ortho && ortho_coefficients(Gall, nx, ma, Cm, mw)) {
-                if ((rc = dev_lincomb_real(c, XPW, rvecs(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
-            } else {
+            bool done = false;
+            if (!explicit_ortho) {
+                // one explicit projection, then the second one and SVQB in coefficient space
+                const std::vector<cd> G1 = neg_projection(Gall, nx, ma);
+                if ((rc = dev_lincomb_real(c, XP, Wv, G1, nx, 0, 1.0))) return rc;
+                if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
+                if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
+                    if ((rc = dev_lincomb_real(c, XPW, rvecs(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
+                    done = true;
+                }
+            }
+            if (!done) {
                 ++reortho;
                 for (int pass = 0; pass < 2; ++pass) {
                     std::vector<cd> G;
@@ -1767,6 +1849,7 @@ struct BInst {
     int prec = 0;
     bool can64 = false;
     bool done = false;
+    bool cleaned = false;  // X re-orthonormalised since its pairs converged
     int status = IWFPM_OK;
     std::vector<double> theta, eta;
     int mp = 0, it = 0, polished = 0;
@@ -1880,14 +1963,18 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
     auto rr_blocks = [&](const std::vector<int>& which) -> int {
         if (which.empty()) return IWFPM_OK;
         std::vector<GramReq> g;
-        for (int i : which) g.push_back({cols(in[i].c, B_X, 0, m), cols(in[i].c, B_HX, 0, m), in[i].c.N});
+        for (int i : which) {
+            std::vector<double2*> XHX = cols(in[i].c, B_X, 0, m), HX = cols(in[i].c, B_HX, 0, m);
+            XHX.insert(XHX.end(), HX.begin(), HX.end());
+            g.push_back({cols(in[i].c, B_X, 0, m), XHX, in[i].c.N});
+        }
         std::vector<std::vector<cd>> G;
         if ((rc = batch_gram(bo, g, G))) return rc;
         std::vector<std::vector<cd>> C(which.size());
-        parallel_for((int)which.size(), [&](int k) {
-            hermitian_part(G[k], m);
-            heev(G[k], m, in[which[k]].theta, C[k]);
-        });
+        std::vector<char> okt(which.size(), 1);
+        parallel_for((int)which.size(), [&](int k) { okt[k] = rr_transform(G[k], m, in[which[k]].theta, C[k]); });
+        for (char ok : okt)
+            if (!ok) return IWFPM_ERR_NUMERIC;
         std::vector<LinReq> l;
         for (size_t k = 0; k < which.size(); ++k) {
             BInst& b = in[which[k]];
@@ -1962,7 +2049,7 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             }
         }
         // per-instance decisions
-        std::vector<int> to64, iter;
+        std::vector<int> to64, iter, to_clean;
         for (int i : live) {
             BInst& b = in[i];
             if (b.done) continue;
@@ -1973,8 +2060,10 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
                 worst = std::max(worst, b.eta[j]);
             }
             if (conv == nev) {
-                if (b.prec == 0 || !b.can64) b.done = true;
+                if ((b.prec == 0 || !b.can64) && b.cleaned) b.done = true;
+                else if (b.prec == 0 || !b.can64) to_clean.push_back(i);  // re-orthonormalise X once more
                 else to64.push_back(i);  // confirm with float64 applies
+                if (!b.done) b.cleaned = true;
                 continue;
             }
             if (b.it >= o.maxit) {
@@ -2001,6 +2090,7 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             }
             iter.push_back(i);
         }
+        if ((rc = rr_blocks(to_clean))) return rc;
         if (!to64.empty()) {
             std::vector<int> cx(B, 0), cp(B, 0), p0(B, 0);
             for (int i : to64) {
@@ -2065,8 +2155,8 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             }
         }
         // W <- orthonormal basis of the part of W orthogonal to [X P]: one
-        // Gram [X P W]^H W for all instances, one combination for those where
-        // little cancels; the others project explicitly, twice, then SVQB
+        // explicit projection with the Gram [X P W]^H W, then the second
+        // projection and SVQB in coefficient space (explicit twice as fallback)
         {
             std::vector<GramReq> g;
             std::vector<std::vector<double2*>> XPW(iter.size());
@@ -2081,23 +2171,42 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
             }
             std::vector<std::vector<cd>> Gall;
             if ((rc = batch_gram(bo, g, Gall))) return rc;
-            std::vector<char> one(iter.size(), 0);
-            std::vector<std::vector<cd>> Cm(iter.size());
-            parallel_for((int)iter.size(), [&](int k) {
-                BInst& b = in[iter[k]];
-                one[k] = !explicit_ortho && m + b.mq + b.ma <= kMaxCols &&
-                         ortho_coefficients(Gall[k], m + b.mq, b.ma, Cm[k], b.mw);
-            });
-            std::vector<size_t> two;
-            std::vector<LinReq> l;
-            for (size_t k = 0; k < iter.size(); ++k) {
-                BInst& b = in[iter[k]];
-                if (one[k])
-                    l.push_back({XPW[k], cols(b.c, B_T1, 0, b.mw), &Cm[k], m + b.mq + b.ma, 0, 0.0, b.c.N});
-                else
-                    two.push_back(k);
+            std::vector<size_t> two(iter.size());
+            for (size_t k = 0; k < iter.size(); ++k) two[k] = k;
+            if (!two.empty() && !explicit_ortho) {
+                // one explicit projection, then the second one and SVQB in coefficient space
+                std::vector<std::vector<cd>> G1(two.size());
+                std::vector<LinReq> lp1;
+                std::vector<GramReq> g2;
+                for (size_t t = 0; t < two.size(); ++t) {
+                    BInst& b = in[iter[two[t]]];
+                    const int nx = m + b.mq;
+                    G1[t] = neg_projection(Gall[two[t]], nx, b.ma);
+                    std::vector<double2*> XP(XPW[two[t]].begin(), XPW[two[t]].begin() + nx);
+                    lp1.push_back({XP, cols(b.c, B_W, 0, b.ma), &G1[t], nx, 0, 1.0, b.c.N});
+                    g2.push_back({XPW[two[t]], cols(b.c, B_W, 0, b.ma), b.c.N});
+                }
+                if ((rc = batch_lincomb(bo, lp1))) return rc;
+                std::vector<std::vector<cd>> Gall2;
+                if ((rc = batch_gram(bo, g2, Gall2))) return rc;
+                std::vector<char> ok2(two.size(), 0);
+                std::vector<std::vector<cd>> Cm2(two.size());
+                parallel_for((int)two.size(), [&](int t) {
+                    BInst& b = in[iter[two[t]]];
+                    ok2[t] = ortho_coefficients(Gall2[t], m + b.mq, b.ma, Cm2[t], b.mw);
+                });
+                std::vector<LinReq> l2;
+                std::vector<size_t> rest;
+                for (size_t t = 0; t < two.size(); ++t) {
+                    BInst& b = in[iter[two[t]]];
+                    if (ok2[t])
+                        l2.push_back({XPW[two[t]], cols(b.c, B_T1, 0, b.mw), &Cm2[t], m + b.mq + b.ma, 0, 0.0, b.c.N});
+                    else
+                        rest.push_back(two[t]);
+                }
+                if ((rc = batch_lincomb(bo, l2))) return rc;
+                two.swap(rest);
             }
-            if ((rc = batch_lincomb(bo, l))) return rc;
             if (!two.empty()) {
                 for (int pass = 0; pass < 2; ++pass) {
                     std::vector<GramReq> g2;
@@ -2237,6 +2346,590 @@ void iwfpm_default_eigs_opts(iwfpm_eigs_opts* o) {
     o->arith = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Real-symmetric lock-step batched LOBPCG (two real trial vectors per complex
+// column, as run_real), every tall operation one launch over a job table.
+// ---------------------------------------------------------------------------
+
+struct GramReqR {
+    std::vector<RVec> L, R;
+    long long N;
+};
+
+// G_k (|L| x |R| real, zero imaginary parts) for every request, one launch (two with the reduction)
+static int batch_gram_real(BatchOps& bo, const std::vector<GramReqR>& reqs, std::vector<std::vector<cd>>& out) {
+    std::vector<GramJob> jobs;
+    std::vector<PairCols> Lp, Rp;
+    long long part = 0;
+    int blocks = 0, outs = 0, maxp = 1, maxq = 1;
+    for (const GramReqR& r : reqs) {
+        Lp.push_back(pair_cols(r.L));
+        Rp.push_back(pair_cols(r.R));
+        GramJob jb{};
+        jb.p = (int)Lp.back().cols.size();
+        jb.q = (int)Rp.back().cols.size();
+        if (jb.p > kMaxCols / 2 || jb.q > kMaxCols / 2) return IWFPM_ERR_ARG;
+        for (int i = 0; i < jb.p; ++i) jb.L.p[i] = Lp.back().cols[i];
+        for (int j = 0; j < jb.q; ++j) jb.R.p[j] = Rp.back().cols[j];
+        jb.N = r.N;
+        jb.width = 2;
+        jb.nb = gram_job_blocks(jb.p, jb.N, 256, &jb.groups_per_block);
+        maxp = std::max(maxp, jb.p);
+        maxq = std::max(maxq, jb.q);
+        jb.start = blocks;
+        jb.out_start = outs;
+        jb.part_off = part;
+        blocks += jb.nb;
+        outs += 2 * jb.p * jb.q;
+        part += (long long)jb.nb * 2 * jb.p * jb.q;
+        jobs.push_back(jb);
+    }
+    out.assign(reqs.size(), {});
+    if (jobs.empty()) return IWFPM_OK;
+    int rc;
+    if ((rc = bo.wait_staged())) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(GramJob)))) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(GramJob)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
+    std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GramJob));
+    CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GramJob), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(gram_batched_pairs((const GramJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs, maxp, maxq,
+                                 (double2*)bo.d_partial.ptr, (double2*)bo.d_out.ptr, bo.st));
+    CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, (size_t)outs * sizeof(double2), hipMemcpyDeviceToHost, bo.st));
+    CHECK_HIP(hipStreamSynchronize(bo.st));
+    for (size_t k = 0; k < jobs.size(); ++k) {
+        const double* g = (const double*)(bo.h_out + jobs[k].out_start);  // 2p x 2q real, column-major
+        const size_t ld = 2 * (size_t)jobs[k].p;
+        const int nl = (int)reqs[k].L.size(), nr = (int)reqs[k].R.size();
+        out[k].assign((size_t)nl * nr, 0.0);
+        for (int l = 0; l < nr; ++l)
+            for (int i = 0; i < nl; ++i)
+                out[k][i + (size_t)l * nl] = g[(size_t)Lp[k].at[i] + (size_t)Rp[k].at[l] * ld];
+    }
+    return IWFPM_OK;
+}
+
+struct LinReqR {
+    std::vector<RVec> A, Y;  // Y: the first vectors of one or more buffers, filling columns from the first half
+    const std::vector<cd>* C;
+    int ldc, r0;
+    double beta;
+    long long N;
+};
+
+// Y_k = beta Y_k + A_k Re C_k for every request, one launch
+static int batch_lincomb_real(BatchOps& bo, const std::vector<LinReqR>& reqs) {
+    std::vector<LinJob> jobs;
+    std::vector<PairCols> Ap, Yp;
+    std::vector<size_t> coef_off;
+    size_t coefs = 0;  // in double2 units
+    int blocks = 0, maxq = 1;
+    for (const LinReqR& r : reqs) {
+        if (r.Y.empty()) continue;
+        Ap.push_back(pair_cols(r.A));
+        Yp.push_back(pair_cols(r.Y));
+        LinJob jb{};
+        jb.p = (int)Ap.back().cols.size();
+        jb.q = (int)Yp.back().cols.size();
+        if (jb.p > kMaxCols || jb.q > 32) return IWFPM_ERR_ARG;
+        for (int i = 0; i < jb.p; ++i) jb.A.p[i] = Ap.back().cols[i];
+        for (int j = 0; j < jb.q; ++j) jb.Y.p[j] = Yp.back().cols[j];
+        jb.beta = r.beta;
+        jb.N = r.N;
+        jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (r.N + 127) / 128));
+        jb.start = blocks;
+        blocks += jb.nb;
+        maxq = std::max(maxq, jb.q);
+        coef_off.push_back(coefs);
+        coefs += (size_t)2 * jb.p * jb.q;
+        jobs.push_back(jb);
+    }
+    if (jobs.empty()) return IWFPM_OK;
+    int rc;
+    if ((rc = bo.wait_staged())) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(LinJob)))) return rc;
+    if ((rc = bo.reserve_host((void**)&bo.h_coef, bo.coef_cap, std::max<size_t>(1, coefs) * sizeof(double2)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(LinJob)))) return rc;
+    if ((rc = bo.reserve_dev(bo.d_coef, std::max<size_t>(1, coefs) * sizeof(double2)))) return rc;
+    size_t k = 0;
+    for (const LinReqR& r : reqs) {
+        if (r.Y.empty()) continue;
+        LinJob& jb = jobs[k];
+        double* h = (double*)(bo.h_coef + coef_off[k]);
+        const size_t ld = 2 * (size_t)jb.p;
+        std::fill(h, h + ld * 2 * (size_t)jb.q, 0.0);
+        for (size_t a = 0; a < r.A.size(); ++a)
+            for (size_t l = 0; l < r.Y.size(); ++l)
+                h[(size_t)Ap[k].at[a] + (size_t)Yp[k].at[l] * ld] =
+                    (*r.C)[(size_t)(r.r0 + a) + l * (size_t)r.ldc].real();
+        jb.C = (const double2*)bo.d_coef.ptr + coef_off[k];
+        ++k;
+    }
+    std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(LinJob));
+    CHECK_HIP(hipMemcpyAsync(bo.d_coef.ptr, bo.h_coef, coefs * sizeof(double2), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(LinJob), hipMemcpyHostToDevice, bo.st));
+    CHECK_HIP(hipEventRecord(bo.staged, bo.st));
+    CHECK_HIP(lincomb_pairs_batched((const LinJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, maxq, bo.st));
+    return IWFPM_OK;
+}
+
+static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, double* evals,
+                            double* eta_out, iwfpm_stats* stats, hipStream_t st) {
+    const int nev = o.nev;
+    const int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
+    if (m < nev || 3 * m > kMaxCols) return IWFPM_ERR_ARG;
+    const int mc = (m + 1) / 2;
+    const bool explicit_ortho = force_explicit_ortho();
+    std::vector<BInst> in(B);
+    int rc;
+    for (int i = 0; i < B; ++i) {
+        BInst& b = in[i];
+        b.p = plans[i];
+        if (m > b.p->geom.N) return IWFPM_ERR_ARG;
+        if ((rc = solver_ensure(b.p, m))) return rc;
+        int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
+        if ((rc = solver_precond(b.p, pk))) return rc;
+        b.s = (Solver*)b.p->solver;
+        b.c = Ctx{b.p, b.s, st, b.p->geom.N};
+        b.prec = b.p->opts.precision;
+        if (!b.p->sched[b.prec].ok) b.prec = 1 - b.prec;
+        if (!b.p->sched[b.prec].ok) return IWFPM_ERR_UNSUPPORTED;
+        b.can64 = b.p->sched[0].ok;
+        b.hnorm = b.p->lam_max + b.p->vsum_abs;
+        b.floor32 = 30.0 * 6e-8 * b.p->vsum_abs / b.hnorm;
+        b.eta.assign(m, 1.0);
+        if (o.precond == IWFPM_PRECOND_LEARNED) {
+            b.lp = b.p->learned;
+            if (!b.lp || !learned_ready(b.lp, b.p)) return IWFPM_ERR_WEIGHTS;
+        }
+    }
+    BatchOps bo;
+    bo.st = st;
+    CHECK_HIP(hipEventCreateWithFlags(&bo.staged, hipEventDisableTiming));
+    std::vector<iwfpm_plan_t> pl(plans, plans + B);
+    iwfpm_batch_t bat[2] = {nullptr, nullptr};
+    struct BatchGuard {
+        iwfpm_batch_t* b;
+        ~BatchGuard() {
+            for (int k = 0; k < 2; ++k)
+                if (b[k]) iwfpm_batch_destroy(b[k]);
+        }
+    } bguard{bat};
+    for (int k = 0; k < 2; ++k) {
+        bool ok = true;
+        for (auto* p : pl) ok = ok && p->sched[k].ok;
+        if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
+            return rc;
+    }
+    // apply H to the first cnt[i] real vectors (ceil(cnt/2) columns) of bin into bout
+    auto apply_all = [&](int bin, int bout, const std::vector<int>& cnt, const std::vector<int>& precs) -> int {
+        for (int k = 0; k < 2; ++k) {
+            std::vector<const void*> x(B, nullptr);
+            std::vector<void*> y(B, nullptr);
+            std::vector<int> nv(B, 0);
+            bool any = false;
+            for (int i = 0; i < B; ++i)
+                if (cnt[i] > 0 && precs[i] == k) {
+                    x[i] = in[i].c.col(bin, 0);
+                    y[i] = in[i].c.col(bout, 0);
+                    nv[i] = (cnt[i] + 1) / 2;
+                    in[i].matvecs += cnt[i];
+                    any = true;
+                }
+            if (!any) continue;
+            if (!bat[k]) {
+                for (int i = 0; i < B; ++i)
+                    if (nv[i] && (rc = plan_apply(in[i].p, x[i], y[i], nv[i], k, st))) return rc;
+                continue;
+            }
+            if ((rc = iwfpm_batch_apply(bat[k], x.data(), y.data(), nv.data(), st))) return rc;
+        }
+        return IWFPM_OK;
+    };
+    // start blocks: real and imaginary parts of seeded complex blocks, orthonormalised
+    for (int i = 0; i < B; ++i)
+        CHECK_HIP(randn(in[i].c.col(B_X, 0), in[i].c.N * mc, o.seed + (unsigned long long)i, st));
+    {
+        std::vector<GramReqR> g(B);
+        for (int i = 0; i < B; ++i) g[i] = {rvecs(in[i].c, B_X, 0, m), rvecs(in[i].c, B_X, 0, m), in[i].c.N};
+        std::vector<std::vector<cd>> G;
+        if ((rc = batch_gram_real(bo, g, G))) return rc;
+        std::vector<int> bad(B, 0);
+        parallel_for(B, [&](int i) { bad[i] = svqb(G[i], m, in[i].T) < m; });
+        for (int i = 0; i < B; ++i)
+            if (bad[i]) return IWFPM_ERR_NUMERIC;
+        std::vector<LinReqR> l(B);
+        for (int i = 0; i < B; ++i)
+            l[i] = {rvecs(in[i].c, B_X, 0, m), rvecs(in[i].c, B_XN, 0, m), &in[i].T, m, 0, 0.0, in[i].c.N};
+        if ((rc = batch_lincomb_real(bo, l))) return rc;
+        for (auto& b : in) std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
+    }
+    std::vector<int> all_m(B, m), precs(B);
+    for (int i = 0; i < B; ++i) precs[i] = in[i].prec;
+    if ((rc = apply_all(B_X, B_HX, all_m, precs))) return rc;
+    auto rr_blocks = [&](const std::vector<int>& which) -> int {
+        if (which.empty()) return IWFPM_OK;
+        std::vector<GramReqR> g;
+        for (int i : which) {
+            std::vector<RVec> XHX = rvecs(in[i].c, B_X, 0, m), HX = rvecs(in[i].c, B_HX, 0, m);
+            XHX.insert(XHX.end(), HX.begin(), HX.end());
+            g.push_back({rvecs(in[i].c, B_X, 0, m), XHX, in[i].c.N});
+        }
+        std::vector<std::vector<cd>> G;
+        if ((rc = batch_gram_real(bo, g, G))) return rc;
+        std::vector<std::vector<cd>> C(which.size());
+        std::vector<char> okt(which.size(), 1);
+        parallel_for((int)which.size(), [&](int k) { okt[k] = rr_transform(G[k], m, in[which[k]].theta, C[k]); });
+        for (char ok : okt)
+            if (!ok) return IWFPM_ERR_NUMERIC;
+        std::vector<LinReqR> l;
+        for (size_t k = 0; k < which.size(); ++k) {
+            BInst& b = in[which[k]];
+            l.push_back({rvecs(b.c, B_X, 0, m), rvecs(b.c, B_XN, 0, m), &C[k], m, 0, 0.0, b.c.N});
+            l.push_back({rvecs(b.c, B_HX, 0, m), rvecs(b.c, B_HXN, 0, m), &C[k], m, 0, 0.0, b.c.N});
+        }
+        if ((rc = batch_lincomb_real(bo, l))) return rc;
+        for (int i : which) {
+            std::swap(in[i].s->buf[B_X], in[i].s->buf[B_XN]);
+            std::swap(in[i].s->buf[B_HX], in[i].s->buf[B_HXN]);
+        }
+        return IWFPM_OK;
+    };
+    {
+        std::vector<int> allidx(B);
+        for (int i = 0; i < B; ++i) allidx[i] = i;
+        if ((rc = rr_blocks(allidx))) return rc;
+    }
+    for (;;) {
+        std::vector<int> live;
+        for (int i = 0; i < B; ++i)
+            if (!in[i].done) live.push_back(i);
+        if (live.empty()) break;
+        // residuals and their norms (one per real vector), one launch for all live instances
+        {
+            std::vector<ResJob> jobs;
+            int blocks = 0, outs = 0;
+            long long part = 0;
+            for (int i : live) {
+                BInst& b = in[i];
+                ResJob jb{};
+                for (int j = 0; j < mc; ++j) {
+                    jb.HX.p[j] = b.c.col(B_HX, j);
+                    jb.X.p[j] = b.c.col(B_X, j);
+                    jb.R.p[j] = b.c.col(B_T1, j);
+                }
+                for (int v = 0; v < 2 * mc; ++v) jb.theta.v[v] = v < m ? b.theta[v] : 0.0;
+                jb.m = mc;
+                jb.width = 2;
+                jb.N = b.c.N;
+                jb.nb = (int)std::min<long long>(256, std::max<long long>(1, (jb.N + 1023) / 1024));
+                jb.rows_per_block = (jb.N + jb.nb - 1) / jb.nb;
+                jb.start = blocks;
+                jb.out_start = outs;
+                jb.part_off = part;
+                blocks += jb.nb;
+                outs += 2 * mc;
+                part += (long long)jb.nb * 2 * mc;
+                jobs.push_back(jb);
+            }
+            if ((rc = bo.wait_staged())) return rc;
+            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(ResJob)))) return rc;
+            if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(ResJob)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
+            if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
+            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(ResJob));
+            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
+            CHECK_HIP(residual_norm_pairs_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
+                                                  (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, st));
+            CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, outs * sizeof(double), hipMemcpyDeviceToHost, st));
+            CHECK_HIP(hipStreamSynchronize(st));
+            const double* h = (const double*)bo.h_out;
+            for (size_t k = 0; k < live.size(); ++k) {
+                BInst& b = in[live[k]];
+                for (int j = 0; j < m; ++j) {
+                    b.eta[j] = std::sqrt(std::max(0.0, h[k * 2 * mc + j])) / (b.hnorm + std::fabs(b.theta[j]));
+                    if (!std::isfinite(b.eta[j])) {
+                        b.done = true;
+                        b.status = IWFPM_ERR_NUMERIC;
+                    }
+                }
+            }
+        }
+        std::vector<int> to64, iter, to_clean;
+        for (int i : live) {
+            BInst& b = in[i];
+            if (b.done) continue;
+            int conv = 0;
+            double worst = 0.0;
+            for (int j = 0; j < nev; ++j) {
+                conv += b.eta[j] <= o.tol;
+                worst = std::max(worst, b.eta[j]);
+            }
+            if (conv == nev) {
+                if ((b.prec == 0 || !b.can64) && b.cleaned) b.done = true;
+                else if (b.prec == 0 || !b.can64) to_clean.push_back(i);
+                else to64.push_back(i);
+                if (!b.done) b.cleaned = true;
+                continue;
+            }
+            if (b.it >= o.maxit) {
+                b.done = true;
+                b.status = IWFPM_ERR_NOCONV;
+                continue;
+            }
+            bool stalled = false;
+            if (worst < 0.5 * b.best_eta) {
+                b.best_eta = worst;
+                b.best_it = b.it;
+            } else {
+                stalled = worst < 1e-5 && b.it - b.best_it >= 20;
+            }
+            if (b.lp && b.it - b.best_it >= 50) {
+                b.fallback = 1;
+                b.lp = nullptr;
+                b.best_it = b.it;
+            }
+            if (b.prec == 1 && o.polish && b.can64 && (worst < b.floor32 || stalled)) {
+                to64.push_back(i);
+                continue;
+            }
+            iter.push_back(i);
+        }
+        if ((rc = rr_blocks(to_clean))) return rc;
+        if (!to64.empty()) {
+            std::vector<int> cx(B, 0), cp(B, 0), p0(B, 0);
+            for (int i : to64) {
+                in[i].prec = 0;
+                in[i].best_eta = 1e300;
+                cx[i] = m;
+                cp[i] = in[i].mp;
+            }
+            if ((rc = apply_all(B_X, B_HX, cx, p0))) return rc;
+            if ((rc = apply_all(B_P, B_HP, cp, p0))) return rc;
+            if ((rc = rr_blocks(to64))) return rc;
+        }
+        if (iter.empty()) continue;
+        for (int i : iter) {
+            BInst& b = in[i];
+            ++b.it;
+            if (b.prec == 0 && b.p->opts.precision == 1) ++b.polished;
+            b.act.clear();
+            for (int j = 0; j < m; ++j)
+                if (b.eta[j] > o.tol) b.act.push_back(j);
+            b.ma = (int)b.act.size();
+            b.mq = b.mp;
+        }
+        // W = T(R_A) (learned, per instance) or M R_A (all plain instances in one launch), packed
+        {
+            std::vector<GatherJob> jobs;
+            int blocks = 0;
+            for (int i : iter) {
+                BInst& b = in[i];
+                std::vector<RVec> Ract(b.ma);
+                for (int a = 0; a < b.ma; ++a) Ract[a] = {b.c.col(B_T1, b.act[a] >> 1), b.act[a] & 1};
+                GatherJob jb{};
+                jb.src = colptrs(Ract, &jb.parts);
+                jb.n = b.ma;
+                jb.N = b.c.N;
+                const int mac = (b.ma + 1) / 2;
+                if (b.lp) {
+                    ColPtrs rp{}, w{};
+                    for (int j = 0; j < mac; ++j) {
+                        rp.p[j] = b.c.col(B_HW, j);
+                        w.p[j] = b.c.col(B_W, j);
+                    }
+                    CHECK_HIP(gather_pairs(jb.src, jb.parts, b.ma, rp, nullptr, b.c.N, st));
+                    if (learned_apply(b.lp, b.p, rp, w, mac, st) == IWFPM_OK) continue;
+                    b.fallback = 1;
+                    b.lp = nullptr;
+                }
+                for (int j = 0; j < mac; ++j) jb.dst.p[j] = b.c.col(B_W, j);
+                jb.M = (const double*)b.s->M.ptr;
+                jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
+                jb.start = blocks;
+                blocks += jb.nb;
+                jobs.push_back(jb);
+            }
+            if (!jobs.empty()) {
+                if ((rc = bo.wait_staged())) return rc;
+                if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(GatherJob)))) return rc;
+                if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(GatherJob)))) return rc;
+                std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GatherJob));
+                CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GatherJob),
+                                         hipMemcpyHostToDevice, st));
+                CHECK_HIP(hipEventRecord(bo.staged, st));
+                CHECK_HIP(gather_pairs_batched((const GatherJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
+            }
+        }
+        // W <- orthonormal basis of the part of W orthogonal to [X P] (as in the complex solver)
+        {
+            std::vector<GramReqR> g;
+            std::vector<std::vector<RVec>> XPW(iter.size()), Wv(iter.size());
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                XPW[k] = rvecs(b.c, B_X, 0, m);
+                auto P = rvecs(b.c, B_P, 0, b.mq);
+                XPW[k].insert(XPW[k].end(), P.begin(), P.end());
+                Wv[k] = rvecs(b.c, B_W, 0, b.ma);
+                XPW[k].insert(XPW[k].end(), Wv[k].begin(), Wv[k].end());
+                g.push_back({XPW[k], Wv[k], b.c.N});
+            }
+            std::vector<std::vector<cd>> Gall;
+            if ((rc = batch_gram_real(bo, g, Gall))) return rc;
+            std::vector<size_t> two(iter.size());
+            for (size_t k = 0; k < iter.size(); ++k) two[k] = k;
+            if (!two.empty() && !explicit_ortho) {
+                // one explicit projection, then the second one and SVQB in coefficient space
+                std::vector<std::vector<cd>> G1(two.size());
+                std::vector<LinReqR> lp1;
+                std::vector<GramReqR> g2;
+                for (size_t t = 0; t < two.size(); ++t) {
+                    BInst& b = in[iter[two[t]]];
+                    const int nx = m + b.mq;
+                    G1[t] = neg_projection(Gall[two[t]], nx, b.ma);
+                    std::vector<RVec> XP(XPW[two[t]].begin(), XPW[two[t]].begin() + nx);
+                    lp1.push_back({XP, Wv[two[t]], &G1[t], nx, 0, 1.0, b.c.N});
+                    g2.push_back({XPW[two[t]], Wv[two[t]], b.c.N});
+                }
+                if ((rc = batch_lincomb_real(bo, lp1))) return rc;
+                std::vector<std::vector<cd>> Gall2;
+                if ((rc = batch_gram_real(bo, g2, Gall2))) return rc;
+                std::vector<char> ok2(two.size(), 0);
+                std::vector<std::vector<cd>> Cm2(two.size());
+                parallel_for((int)two.size(), [&](int t) {
+                    BInst& b = in[iter[two[t]]];
+                    ok2[t] = ortho_coefficients(Gall2[t], m + b.mq, b.ma, Cm2[t], b.mw);
+                });
+                std::vector<LinReqR> l2;
+                std::vector<size_t> rest;
+                for (size_t t = 0; t < two.size(); ++t) {
+                    BInst& b = in[iter[two[t]]];
+                    if (ok2[t])
+                        l2.push_back({XPW[two[t]], rvecs(b.c, B_T1, 0, b.mw), &Cm2[t], m + b.mq + b.ma, 0, 0.0, b.c.N});
+                    else
+                        rest.push_back(two[t]);
+                }
+                if ((rc = batch_lincomb_real(bo, l2))) return rc;
+                two.swap(rest);
+            }
+            if (!two.empty()) {
+                for (int pass = 0; pass < 2; ++pass) {
+                    std::vector<GramReqR> g2;
+                    std::vector<std::vector<RVec>> XP(two.size());
+                    for (size_t t = 0; t < two.size(); ++t) {
+                        BInst& b = in[iter[two[t]]];
+                        XP[t].assign(XPW[two[t]].begin(), XPW[two[t]].begin() + m + b.mq);
+                        g2.push_back({XP[t], Wv[two[t]], b.c.N});
+                    }
+                    std::vector<std::vector<cd>> G;
+                    if ((rc = batch_gram_real(bo, g2, G))) return rc;
+                    std::vector<LinReqR> l2;
+                    for (size_t t = 0; t < two.size(); ++t) {
+                        for (auto& v : G[t]) v = -v;
+                        BInst& b = in[iter[two[t]]];
+                        l2.push_back({XP[t], Wv[two[t]], &G[t], (int)XP[t].size(), 0, 1.0, b.c.N});
+                    }
+                    if ((rc = batch_lincomb_real(bo, l2))) return rc;
+                }
+                std::vector<GramReqR> g2;
+                for (size_t k : two) g2.push_back({Wv[k], Wv[k], in[iter[k]].c.N});
+                std::vector<std::vector<cd>> G;
+                if ((rc = batch_gram_real(bo, g2, G))) return rc;
+                parallel_for((int)two.size(), [&](int t) {
+                    BInst& b = in[iter[two[t]]];
+                    hermitian_part(G[t], b.ma);
+                    b.mw = svqb(G[t], b.ma, b.T, 1e-10);
+                });
+                std::vector<LinReqR> l2;
+                for (size_t k : two) {
+                    BInst& b = in[iter[k]];
+                    l2.push_back({Wv[k], rvecs(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
+                }
+                if ((rc = batch_lincomb_real(bo, l2))) return rc;
+            }
+            for (int i : iter) std::swap(in[i].s->buf[B_W], in[i].s->buf[B_T1]);
+        }
+        {
+            std::vector<int> cnt(B, 0), pr(B, 0);
+            for (int i : iter) {
+                cnt[i] = in[i].mw;
+                pr[i] = in[i].prec;
+            }
+            if ((rc = apply_all(B_W, B_HW, cnt, pr))) return rc;
+        }
+        // Rayleigh-Ritz: G = [X W P]^T [HW HP] for all, small problems on host threads
+        std::vector<std::vector<RVec>> S(iter.size()), HS(iter.size());
+        {
+            std::vector<GramReqR> g;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                S[k] = rvecs(b.c, B_X, 0, m);
+                HS[k] = rvecs(b.c, B_HX, 0, m);
+                auto Wn = rvecs(b.c, B_W, 0, b.mw), HWn = rvecs(b.c, B_HW, 0, b.mw);
+                auto Pn = rvecs(b.c, B_P, 0, b.mq), HPn = rvecs(b.c, B_HP, 0, b.mq);
+                S[k].insert(S[k].end(), Wn.begin(), Wn.end());
+                S[k].insert(S[k].end(), Pn.begin(), Pn.end());
+                HS[k].insert(HS[k].end(), HWn.begin(), HWn.end());
+                HS[k].insert(HS[k].end(), HPn.begin(), HPn.end());
+                b.ns = (int)S[k].size();
+                g.push_back({S[k], std::vector<RVec>(HS[k].begin() + m, HS[k].end()), b.c.N});
+            }
+            std::vector<std::vector<cd>> G;
+            if ((rc = batch_gram_real(bo, g, G))) return rc;
+            parallel_for((int)iter.size(), [&](int k) {
+                BInst& b = in[iter[k]];
+                b.mpn = rr_coefficients(G[k], b.theta, m, b.ns, b.act, b.th, b.U);
+            });
+        }
+        {
+            std::vector<LinReqR> l;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                std::vector<RVec> out = rvecs(b.c, B_XN, 0, m), hout = rvecs(b.c, B_HXN, 0, m);
+                auto pn = rvecs(b.c, B_PN, 0, b.mpn), hpn = rvecs(b.c, B_HPN, 0, b.mpn);
+                out.insert(out.end(), pn.begin(), pn.end());
+                hout.insert(hout.end(), hpn.begin(), hpn.end());
+                l.push_back({S[k], out, &b.U, b.ns, 0, 0.0, b.c.N});
+                l.push_back({HS[k], hout, &b.U, b.ns, 0, 0.0, b.c.N});
+            }
+            if ((rc = batch_lincomb_real(bo, l))) return rc;
+            for (int i : iter) {
+                BInst& b = in[i];
+                std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
+                std::swap(b.s->buf[B_HX], b.s->buf[B_HXN]);
+                std::swap(b.s->buf[B_P], b.s->buf[B_PN]);
+                std::swap(b.s->buf[B_HP], b.s->buf[B_HPN]);
+                b.mp = b.mpn;
+                b.theta.assign(b.th.begin(), b.th.begin() + m);
+            }
+        }
+    }
+    CHECK_HIP(hipStreamSynchronize(st));
+    int worst_status = IWFPM_OK;
+    for (int i = 0; i < B; ++i) {
+        BInst& b = in[i];
+        for (int j = 0; j < nev; ++j) {
+            evals[(size_t)i * nev + j] = b.theta[j];
+            if (eta_out) eta_out[(size_t)i * nev + j] = b.eta[j];
+        }
+        if (stats) {
+            iwfpm_stats& s = stats[i];
+            s.iterations = b.it;
+            s.matvecs = b.matvecs;
+            s.polished = b.polished;
+            s.fallback = b.fallback;
+            int conv = 0;
+            for (int j = 0; j < nev; ++j) conv += b.eta[j] <= o.tol;
+            s.converged = conv;
+        }
+        if (b.status != IWFPM_OK && worst_status == IWFPM_OK) worst_status = b.status;
+    }
+    return worst_status;
+}
+
 int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, double* evals, void* evecs, double* eta,
                iwfpm_stats* stats, void* stream) {
     if (!p || !opts || !evals) return IWFPM_ERR_ARG;
@@ -2270,11 +2963,17 @@ int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* 
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return IWFPM_ERR_ARG;
     }
+    if (opts->arith < 0 || opts->arith > 2) return IWFPM_ERR_ARG;
+    bool all_real = true;
+    for (int i = 0; i < B; ++i) all_real = all_real && real_symmetric(plans[i]);
+    const bool real = opts->arith == 2 || (opts->arith == 0 && all_real);
+    if (real && !all_real) return IWFPM_ERR_ARG;
     DeviceGuard guard(dev);
     if (!guard.ok) return IWFPM_ERR_DEVICE;
     if (stats) std::memset(stats, 0, sizeof(iwfpm_stats) * B);
     auto t0 = std::chrono::steady_clock::now();
-    int rc = run_batched(B, plans, *opts, evals, eta, stats, (hipStream_t)stream);
+    int rc = real ? run_batched_real(B, plans, *opts, evals, eta, stats, (hipStream_t)stream)
+                  : run_batched(B, plans, *opts, evals, eta, stats, (hipStream_t)stream);
     double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats)
         for (int i = 0; i < B; ++i) stats[i].t_total = t;

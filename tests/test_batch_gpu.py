@@ -132,6 +132,30 @@ def test_eigs_batched_explicit_orthonormalisation(monkeypatch):
             p.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_eigs_batched_real_matches_complex(prec):
+    """The real-symmetric lock-step solver (two real trial vectors per complex
+    column) gives the complex lock-step solver's eigenvalues, and the oracle's."""
+    probs = [W.c2_2d(lam=lam, K=K, L=3) for lam, K in [(0.3, 3), (2.5, 2), (7.0, 4)]]
+    print(f"case: eigs_batched real vs complex {prec}", flush=True)
+    plans = [lib.Plan.from_problem(p, precision=prec) for p in probs]
+    try:
+        # 6 pairs in an odd block of 9 (a zero half in the real solver's last
+        # column); the 6th eigenvalue closes a near-degenerate pair, so the
+        # eigenvalue bar is not limited by a cluster at the block edge
+        er, _, sr, _ = lib.eigs_batched(plans, 6, block=9, tol=1e-10, maxit=600, arith="real")
+        ec, _, sc, _ = lib.eigs_batched(plans, 6, block=9, tol=1e-10, maxit=600, arith="complex")
+        bar = 1e-10 if prec == "fp64" else 1e-5
+        for i, p in enumerate(probs):
+            ref = dense_lowest(p, 6)
+            for ev in (er[i], ec[i]):
+                assert np.all(np.abs(ev - ref) <= bar * np.maximum(1.0, np.abs(ref))), (i, ev - ref)
+            assert sr[i]["converged"] == 6 and sc[i]["converged"] == 6
+    finally:
+        for p in plans:
+            p.close()
+
+
 def test_eigs_batched_sweep_workload_subset():
     """Eight instances of the coupling sweep (2D/4D geometry, L = 16, ragged K),
     float32 convolution, eta <= 1e-8; pairs verified with each instance's
