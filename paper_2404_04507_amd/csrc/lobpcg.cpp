@@ -378,30 +378,70 @@ static void tridiag_soa(std::vector<cd>& A, int n, std::vector<double>& d, std::
     for (int k = 0; k < n; ++k) d[k] = ar[k + (size_t)k * n];
 }
 
-// Hermitian eigenvalues (all, ascending) and the eigenvectors of the nv
-// lowest (V: n x nv), for the Rayleigh-Ritz step, which keeps only those.
-// Householder reduction (tridiag_soa, the reflectors kept, not multiplied
-// out), the implicit QL iteration with Wilkinson shifts on the eigenvalues
-// alone (its plane rotations recorded), then the selected
-// eigenvectors rebuilt from unit vectors by the rotations in reverse order,
-// the diagonal phases and the reflectors in reverse order.
-static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
-    std::vector<double> d0, Ur, Ui;
-    std::vector<cd> sub;
-    std::vector<char> has;
-    tridiag_soa(A, n, d0, sub, Ur, Ui, has);
-    // real tridiagonal: d, and e made real by the diagonal phases ph
-    std::vector<double> d(n), e(n, 0.0);
-    std::vector<cd> phs(n, 1.0);
-    for (int k = 0; k < n; ++k) {
-        d[k] = d0[k];
-        if (k + 1 < n) {
-            const double a = std::abs(sub[k]);
-            phs[k + 1] = a > 0.0 ? phs[k] * (sub[k] / a) : phs[k];
-            e[k] = a;
+// Householder reduction of a real symmetric matrix (lower triangle,
+// column-major) to tridiagonal form: d (diagonal), e (e[k] = T[k+1][k]) and
+// the reflectors u_k (unit, rows k+1..n-1) in the columns of U with has[k].
+static void tridiag_real(std::vector<double>& a, int n, std::vector<double>& d, std::vector<double>& e,
+                         std::vector<double>& U, std::vector<char>& has) {
+    U.assign((size_t)n * n, 0.0);
+    has.assign(n, 0);
+    e.assign(n, 0.0);
+    d.assign(n, 0.0);
+    std::vector<double> p(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const double* ak = &a[(size_t)k * n];
+        double xn = 0.0;
+        for (int i = k + 1; i < n; ++i) xn += ak[i] * ak[i];
+        xn = std::sqrt(xn);
+        const double x0 = ak[k + 1];
+        if (xn == 0.0 || xn * xn - x0 * x0 <= 1e-300) {
+            e[k] = x0;
+            continue;
+        }
+        const double alpha = x0 >= 0.0 ? -xn : xn;
+        double* u = &U[(size_t)k * n];
+        for (int i = k + 1; i < n; ++i) u[i] = ak[i];
+        u[k + 1] -= alpha;
+        double un = 0.0;
+        for (int i = k + 1; i < n; ++i) un += u[i] * u[i];
+        const double inv = 1.0 / std::sqrt(un);
+        for (int i = k + 1; i < n; ++i) u[i] *= inv;
+        has[k] = 1;
+        e[k] = alpha;
+        // p = A22 u from the lower triangle
+        for (int i = k + 1; i < n; ++i) p[i] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const double* aj = &a[(size_t)j * n];
+            const double uj = u[j];
+            double s = 0.0;
+            for (int i = j + 1; i < n; ++i) {
+                p[i] += aj[i] * uj;
+                s += aj[i] * u[i];
+            }
+            p[j] += aj[j] * uj + s;
+        }
+        double K = 0.0;
+        for (int i = k + 1; i < n; ++i) K += u[i] * p[i];
+        for (int i = k + 1; i < n; ++i) p[i] -= K * u[i];
+        // A22 <- A22 - 2 (u w^T + w u^T) on the lower triangle (w = p - K u)
+        for (int j = k + 1; j < n; ++j) {
+            double* aj = &a[(size_t)j * n];
+            const double pj = 2.0 * p[j], uj = 2.0 * u[j];
+            for (int i = j; i < n; ++i) aj[i] -= u[i] * pj + p[i] * uj;
         }
     }
-    // implicit QL with Wilkinson shifts (e[k] couples k and k+1), rotations recorded
+    if (n >= 2) e[n - 2] = a[(size_t)(n - 1) + (size_t)(n - 2) * n];
+    for (int k = 0; k < n; ++k) d[k] = a[k + (size_t)k * n];
+}
+
+// Eigenvalues (all, ascending, in w) of the real symmetric tridiagonal matrix
+// with diagonal d and off-diagonal e (e[k] couples k and k+1), and the
+// eigenvectors of the nv lowest (Y: row-major n x nv).  Implicit QL with
+// Wilkinson shifts on the eigenvalues alone, its plane rotations recorded;
+// the selected eigenvectors are then rebuilt from unit vectors by the
+// rotations in reverse order.  false if QL does not converge.
+static bool tridiag_lowest(std::vector<double> d, std::vector<double> e, int n, int nv, std::vector<double>& w,
+                           std::vector<double>& Y) {
     struct Rot {
         int i;
         double c, s;
@@ -453,9 +493,7 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
     w.resize(n);
     for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
-    nv = std::max(0, std::min(nv, n));
-    // Y (row-major n x nv) = the rotations applied in reverse to the selected unit vectors
-    std::vector<double> Y((size_t)n * nv, 0.0);
+    Y.assign((size_t)n * nv, 0.0);
     for (int c = 0; c < nv; ++c) Y[(size_t)idx[c] * nv + c] = 1.0;
     for (size_t t = rots.size(); t-- > 0;) {
         const Rot& q = rots[t];
@@ -467,6 +505,82 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
             yi1[c] = q.c * b - q.s * a;
         }
     }
+    return true;
+}
+
+// Real symmetric eigenvalues (all, ascending) and the eigenvectors of the nv
+// lowest (V: n x nv): tridiag_real, tridiag_lowest, then the reflectors in
+// reverse order.
+static bool syev_lowest(std::vector<double> A, int n, int nv, std::vector<double>& w, std::vector<double>& V) {
+    nv = std::max(0, std::min(nv, n));
+    std::vector<double> d, e, U, Y;
+    std::vector<char> has;
+    tridiag_real(A, n, d, e, U, has);
+    if (!tridiag_lowest(d, e, n, nv, w, Y)) return false;
+    V.assign((size_t)n * nv, 0.0);
+    for (int c = 0; c < nv; ++c)
+        for (int i = 0; i < n; ++i) V[i + (size_t)c * n] = Y[(size_t)i * nv + c];
+    for (int k = n - 3; k >= 0; --k) {
+        if (!has[k]) continue;
+        const double* u = &U[(size_t)k * n];
+        for (int c = 0; c < nv; ++c) {
+            double* vc = &V[(size_t)c * n];
+            double s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += u[i] * vc[i];
+            s *= 2.0;
+            for (int i = k + 1; i < n; ++i) vc[i] -= u[i] * s;
+        }
+    }
+    return true;
+}
+
+// true when every entry has an exactly zero imaginary part: the real-symmetric
+// solver route produces such Hermitian matrices, and they are handed to the
+// real arithmetic (the same results up to the order of rounding, at a
+// quarter of the multiplications)
+static bool exactly_real(const std::vector<cd>& A) {
+    for (const cd& a : A)
+        if (a.imag() != 0.0) return false;
+    return true;
+}
+
+static std::vector<double> real_parts(const std::vector<cd>& A) {
+    std::vector<double> r(A.size());
+    for (size_t i = 0; i < A.size(); ++i) r[i] = A[i].real();
+    return r;
+}
+
+static std::vector<cd> as_complex(const std::vector<double>& A) {
+    return std::vector<cd>(A.begin(), A.end());
+}
+
+// Hermitian eigenvalues (all, ascending) and the eigenvectors of the nv
+// lowest (V: n x nv), for the Rayleigh-Ritz step, which keeps only those.
+// Householder reduction (tridiag_soa, the reflectors kept, not multiplied
+// out), tridiag_lowest on the real tridiagonal matrix, then the diagonal
+// phases and the reflectors in reverse order.  A matrix with exactly zero
+// imaginary parts goes through syev_lowest.
+static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
+    nv = std::max(0, std::min(nv, n));
+    if (exactly_real(A)) {
+        std::vector<double> Vr;
+        if (!syev_lowest(real_parts(A), n, nv, w, Vr)) return false;
+        V = as_complex(Vr);
+        return true;
+    }
+    std::vector<double> d0, Ur, Ui;
+    std::vector<cd> sub;
+    std::vector<char> has;
+    tridiag_soa(A, n, d0, sub, Ur, Ui, has);
+    // real tridiagonal: d, and e made real by the diagonal phases ph
+    std::vector<double> e(n, 0.0), Y;
+    std::vector<cd> phs(n, 1.0);
+    for (int k = 0; k + 1 < n; ++k) {
+        const double a = std::abs(sub[k]);
+        phs[k + 1] = a > 0.0 ? phs[k] * (sub[k] / a) : phs[k];
+        e[k] = a;
+    }
+    if (!tridiag_lowest(d0, e, n, nv, w, Y)) return false;
     // V = H_0 ... H_{n-3} diag(ph) Y
     V.assign((size_t)n * nv, 0.0);
     for (int c = 0; c < nv; ++c) {
@@ -494,29 +608,60 @@ static bool heev_lowest(std::vector<cd> A, int n, int nv, std::vector<double>& w
 
 // Hermitian eigensolver used throughout: Householder + QL, Jacobi as fallback
 void heev(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) {
+    if (exactly_real(A)) {
+        std::vector<double> Vr;
+        if (syev_lowest(real_parts(A), n, n, w, Vr)) {
+            V = as_complex(Vr);
+            return;
+        }
+    }
     if (!householder_ql(A, n, w, V)) jacobi_eigh(A, n, w, V);
+}
+
+// The Rayleigh-Ritz and orthonormalisation algebra below is written once for
+// complex (cd) and real (double) entries; the real-symmetric solver route
+// hands exactly real matrices to the real instantiation.
+static inline double conj_(double x) { return x; }
+static inline cd conj_(const cd& x) { return std::conj(x); }
+static inline double real_(double x) { return x; }
+static inline double real_(const cd& x) { return x.real(); }
+
+static void heev_t(const std::vector<cd>& A, int n, std::vector<double>& w, std::vector<cd>& V) { heev(A, n, w, V); }
+static void heev_t(const std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V) {
+    if (syev_lowest(A, n, n, w, V)) return;
+    std::vector<cd> Vc;  // QL failed: the complex route (Jacobi as its fallback) keeps real data real
+    heev(as_complex(A), n, w, Vc);
+    V = real_parts(Vc);
+}
+static bool heev_lowest_t(const std::vector<cd>& A, int n, int nv, std::vector<double>& w, std::vector<cd>& V) {
+    return heev_lowest(A, n, nv, w, V);
+}
+static bool heev_lowest_t(const std::vector<double>& A, int n, int nv, std::vector<double>& w,
+                          std::vector<double>& V) {
+    return syev_lowest(A, n, nv, w, V);
 }
 
 // SVQB: T (k x r) with (B T)^H (B T) = I for the Gram matrix G = B^H B (k x k);
 // directions whose scaled eigenvalue is below eps are dropped.  Returns r.
-int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps) {
+template <class S>
+static int svqb_t(const std::vector<S>& G, int k, std::vector<S>& T, double eps) {
     std::vector<double> dsc(k);
     for (int i = 0; i < k; ++i) {
-        double g = G[i + i * k].real();
+        double g = real_(G[i + i * k]);
         dsc[i] = g > 0.0 ? 1.0 / std::sqrt(g) : 0.0;
     }
-    std::vector<cd> S((size_t)k * k);
+    std::vector<S> Sm((size_t)k * k);
     for (int j = 0; j < k; ++j)
-        for (int i = 0; i < k; ++i) S[i + j * k] = dsc[i] * G[i + j * k] * dsc[j];
+        for (int i = 0; i < k; ++i) Sm[i + j * k] = dsc[i] * G[i + j * k] * dsc[j];
     for (int j = 0; j < k; ++j)  // exact Hermitian symmetry
         for (int i = 0; i < j; ++i) {
-            cd a = 0.5 * (S[i + j * k] + std::conj(S[j + i * k]));
-            S[i + j * k] = a;
-            S[j + i * k] = std::conj(a);
+            S a = 0.5 * (Sm[i + j * k] + conj_(Sm[j + i * k]));
+            Sm[i + j * k] = a;
+            Sm[j + i * k] = conj_(a);
         }
     std::vector<double> w;
-    std::vector<cd> U;
-    heev(S, k, w, U);
+    std::vector<S> U;
+    heev_t(Sm, k, w, U);
     double wmax = k ? w[k - 1] : 0.0;
     std::vector<int> keep;
     for (int j = 0; j < k; ++j)
@@ -529,6 +674,16 @@ int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps) {
         for (int i = 0; i < k; ++i) T[i + c * k] = dsc[i] * U[i + j * k] * f;
     }
     return r;
+}
+
+int svqb(const std::vector<cd>& G, int k, std::vector<cd>& T, double eps) {
+    if (exactly_real(G)) {
+        std::vector<double> Tr;
+        const int r = svqb_t(real_parts(G), k, Tr, eps);
+        T = as_complex(Tr);
+        return r;
+    }
+    return svqb_t(G, k, T, eps);
 }
 
 // A c = theta B c (Hermitian A, Hermitian PD B): theta ascending, C (n x n)
@@ -752,49 +907,58 @@ static std::vector<double2*> cols(Ctx& c, int b, int j0, int cnt) {
     return v;
 }
 
-static void hermitian_part(std::vector<cd>& A, int n) {
+template <class S>
+static void hermitian_part(std::vector<S>& A, int n) {
     for (int j = 0; j < n; ++j) {
-        A[j + (size_t)j * n] = A[j + (size_t)j * n].real();
+        A[j + (size_t)j * n] = real_(A[j + (size_t)j * n]);
         for (int i = 0; i < j; ++i) {
-            cd a = 0.5 * (A[i + (size_t)j * n] + std::conj(A[j + (size_t)i * n]));
+            S a = 0.5 * (A[i + (size_t)j * n] + conj_(A[j + (size_t)i * n]));
             A[i + (size_t)j * n] = a;
-            A[j + (size_t)i * n] = std::conj(a);
+            A[j + (size_t)i * n] = conj_(a);
         }
     }
 }
 
-// Rayleigh-Ritz on the block X alone (orthonormal X, HX = H X): X <- X C, HX <- HX C
 // Rayleigh-Ritz of X alone with X first made orthonormal again (the block
 // updates keep it so only up to accumulated rounding): from the Gram
 // G = X^H [X HX] (m x 2m), T = SVQB(X^H X) and the eigenvectors C of
 // T^H (X^H H X) T; the update is X <- X (T C), HX <- HX (T C).  false if X
 // has lost rank.
-static bool rr_transform(const std::vector<cd>& G, int m, std::vector<double>& theta, std::vector<cd>& TC) {
-    std::vector<cd> Gxx(G.begin(), G.begin() + (size_t)m * m), T;
-    if (svqb(Gxx, m, T) < m) return false;
-    std::vector<cd> A((size_t)m * m, 0.0), GT((size_t)m * m, 0.0);
+template <class S>
+static bool rr_transform_t(const std::vector<S>& G, int m, std::vector<double>& theta, std::vector<S>& TC) {
+    std::vector<S> Gxx(G.begin(), G.begin() + (size_t)m * m), T;
+    if (svqb_t(Gxx, m, T, 1e-12) < m) return false;
+    std::vector<S> A((size_t)m * m, 0.0), GT((size_t)m * m, 0.0);
     for (int j = 0; j < m; ++j)  // (X^H H X) T
         for (int i = 0; i < m; ++i) {
-            cd acc = 0.0;
+            S acc = 0.0;
             for (int k = 0; k < m; ++k) acc += G[(size_t)i + (size_t)(m + k) * m] * T[k + (size_t)j * m];
             GT[i + (size_t)j * m] = acc;
         }
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
-            cd acc = 0.0;
-            for (int k = 0; k < m; ++k) acc += std::conj(T[k + (size_t)i * m]) * GT[k + (size_t)j * m];
+            S acc = 0.0;
+            for (int k = 0; k < m; ++k) acc += conj_(T[k + (size_t)i * m]) * GT[k + (size_t)j * m];
             A[i + (size_t)j * m] = acc;
         }
     hermitian_part(A, m);
-    std::vector<cd> C;
-    heev(A, m, theta, C);
+    std::vector<S> C;
+    heev_t(A, m, theta, C);
     TC.assign((size_t)m * m, 0.0);
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < m; ++i) {
-            cd acc = 0.0;
+            S acc = 0.0;
             for (int k = 0; k < m; ++k) acc += T[i + (size_t)k * m] * C[k + (size_t)j * m];
             TC[i + (size_t)j * m] = acc;
         }
+    return true;
+}
+
+static bool rr_transform(const std::vector<cd>& G, int m, std::vector<double>& theta, std::vector<cd>& TC) {
+    if (!exactly_real(G)) return rr_transform_t(G, m, theta, TC);
+    std::vector<double> t;
+    if (!rr_transform_t(real_parts(G), m, theta, t)) return false;
+    TC = as_complex(t);
     return true;
 }
 
@@ -826,34 +990,35 @@ static int apply_block(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats
 // [C_x | Z T] (ns x 2m): the m lowest Ritz vectors, then the next P as the
 // non-X part of the active Ritz vectors, orthogonalised against C_x and
 // orthonormalised; the return value is the number of P columns.
-static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& theta, int m, int ns,
-                           const std::vector<int>& act, std::vector<double>& th, std::vector<cd>& U) {
+template <class S>
+static int rr_coefficients_t(const std::vector<S>& G, const std::vector<double>& theta, int m, int ns,
+                             const std::vector<int>& act, std::vector<double>& th, std::vector<S>& U) {
     const int ma = (int)act.size();
-    std::vector<cd> A((size_t)ns * ns, 0.0);
+    std::vector<S> A((size_t)ns * ns, 0.0);
     const int nr = ns - m;
     for (int j = 0; j < nr; ++j)
         for (int i = 0; i < ns; ++i) {
             A[i + (size_t)(m + j) * ns] = G[i + (size_t)j * ns];
-            if (i < m) A[(m + j) + (size_t)i * ns] = std::conj(G[i + (size_t)j * ns]);
+            if (i < m) A[(m + j) + (size_t)i * ns] = conj_(G[i + (size_t)j * ns]);
         }
     for (int j = 0; j < m; ++j) A[j + (size_t)j * ns] = theta[j];
     hermitian_part(A, ns);
-    std::vector<cd> Cfull;  // ns x m: the Ritz vectors of the m lowest values
-    if (!heev_lowest(A, ns, m, th, Cfull)) heev(A, ns, th, Cfull);
-    std::vector<cd> Z((size_t)ns * m, 0.0);
+    std::vector<S> Cfull;  // ns x m: the Ritz vectors of the m lowest values
+    if (!heev_lowest_t(A, ns, m, th, Cfull)) heev_t(A, ns, th, Cfull);
+    std::vector<S> Z((size_t)ns * m, 0.0);
     for (int a = 0; a < ma; ++a)
         for (int i = m; i < ns; ++i) Z[i + (size_t)a * ns] = Cfull[i + (size_t)act[a] * ns];
     for (int pass = 0; pass < 2; ++pass) {
-        std::vector<cd> Gx((size_t)m * m, 0.0);  // C_x^H Z
+        std::vector<S> Gx((size_t)m * m, 0.0);  // C_x^H Z
         for (int j = 0; j < ma; ++j)
             for (int i = 0; i < m; ++i) {
-                cd acc = 0.0;
-                for (int k = 0; k < ns; ++k) acc += std::conj(Cfull[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                S acc = 0.0;
+                for (int k = 0; k < ns; ++k) acc += conj_(Cfull[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
                 Gx[i + (size_t)j * m] = acc;
             }
         for (int j = 0; j < ma; ++j)
             for (int k = 0; k < ns; ++k) {
-                cd acc = 0.0;
+                S acc = 0.0;
                 for (int i = 0; i < m; ++i) acc += Cfull[k + (size_t)i * ns] * Gx[i + (size_t)j * m];
                 Z[k + (size_t)j * ns] -= acc;
             }
@@ -863,25 +1028,34 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
     for (int j = 0; j < m; ++j)
         for (int i = 0; i < ns; ++i) U[i + (size_t)j * ns] = Cfull[i + (size_t)j * ns];
     if (ns > m && ma > 0) {
-        std::vector<cd> Gz((size_t)ma * ma, 0.0), T;
+        std::vector<S> Gz((size_t)ma * ma, 0.0), T;
         for (int j = 0; j < ma; ++j)
             for (int i = 0; i < ma; ++i) {
-                cd acc = 0.0;
-                for (int k = 0; k < ns; ++k) acc += std::conj(Z[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
+                S acc = 0.0;
+                for (int k = 0; k < ns; ++k) acc += conj_(Z[k + (size_t)i * ns]) * Z[k + (size_t)j * ns];
                 Gz[i + (size_t)j * ma] = acc;
             }
         double gmax = 0.0;
-        for (int j = 0; j < ma; ++j) gmax = std::max(gmax, Gz[j + (size_t)j * ma].real());
+        for (int j = 0; j < ma; ++j) gmax = std::max(gmax, real_(Gz[j + (size_t)j * ma]));
         if (gmax > 1e-28) {
-            mpn = svqb(Gz, ma, T, 1e-12);
+            mpn = svqb_t(Gz, ma, T, 1e-12);
             for (int j = 0; j < mpn; ++j)
                 for (int i = 0; i < ns; ++i) {
-                    cd acc = 0.0;
+                    S acc = 0.0;
                     for (int k = 0; k < ma; ++k) acc += Z[i + (size_t)k * ns] * T[k + (size_t)j * ma];
                     U[i + (size_t)(m + j) * ns] = acc;
                 }
         }
     }
+    return mpn;
+}
+
+static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& theta, int m, int ns,
+                           const std::vector<int>& act, std::vector<double>& th, std::vector<cd>& U) {
+    if (!exactly_real(G)) return rr_coefficients_t(G, theta, m, ns, act, th, U);
+    std::vector<double> u;
+    const int mpn = rr_coefficients_t(real_parts(G), theta, m, ns, act, th, u);
+    U = as_complex(u);
     return mpn;
 }
 
@@ -900,30 +1074,39 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
 // exactly orthonormal, so any drift there passes into W and then into the
 // next X and P, and accumulates.)  Returns false when the Gram is not finite
 // or nothing is left (the caller then projects explicitly).
-static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std::vector<cd>& Cm, int& mw) {
+template <class S>
+static bool ortho_coefficients_t(const std::vector<S>& Gall, int nx, int ma, std::vector<S>& Cm, int& mw) {
     const int ld = nx + ma;
-    std::vector<cd> Gc((size_t)ma * ma);
+    std::vector<S> Gc((size_t)ma * ma);
     for (int j = 0; j < ma; ++j)
         for (int i = 0; i < ma; ++i) {
-            cd acc = Gall[(size_t)(nx + i) + (size_t)j * ld];
-            for (int k = 0; k < nx; ++k) acc -= std::conj(Gall[k + (size_t)i * ld]) * Gall[k + (size_t)j * ld];
+            S acc = Gall[(size_t)(nx + i) + (size_t)j * ld];
+            for (int k = 0; k < nx; ++k) acc -= conj_(Gall[k + (size_t)i * ld]) * Gall[k + (size_t)j * ld];
             Gc[i + (size_t)j * ma] = acc;
         }
     for (int j = 0; j < ma; ++j)
-        if (!std::isfinite(Gc[j + (size_t)j * ma].real()) || !(Gc[j + (size_t)j * ma].real() > 0.0)) return false;
+        if (!std::isfinite(real_(Gc[j + (size_t)j * ma])) || !(real_(Gc[j + (size_t)j * ma]) > 0.0)) return false;
     hermitian_part(Gc, ma);
-    std::vector<cd> T;
-    mw = svqb(Gc, ma, T, 1e-10);
+    std::vector<S> T;
+    mw = svqb_t(Gc, ma, T, 1e-10);
     if (mw < 1) return false;
     Cm.assign((size_t)ld * mw, 0.0);
     for (int c = 0; c < mw; ++c) {
         for (int i = 0; i < ma; ++i) Cm[(size_t)(nx + i) + (size_t)c * ld] = T[i + (size_t)c * ma];
         for (int k = 0; k < nx; ++k) {
-            cd acc = 0.0;
+            S acc = 0.0;
             for (int i = 0; i < ma; ++i) acc += Gall[k + (size_t)i * ld] * T[i + (size_t)c * ma];
             Cm[k + (size_t)c * ld] = -acc;
         }
     }
+    return true;
+}
+
+static bool ortho_coefficients(const std::vector<cd>& Gall, int nx, int ma, std::vector<cd>& Cm, int& mw) {
+    if (!exactly_real(Gall)) return ortho_coefficients_t(Gall, nx, ma, Cm, mw);
+    std::vector<double> c;
+    if (!ortho_coefficients_t(real_parts(Gall), nx, ma, c, mw)) return false;
+    Cm = as_complex(c);
     return true;
 }
 

@@ -152,25 +152,33 @@ def test_dense_geneig_degenerate_and_identity():
         lib.dense_geneig(A, -np.eye(4))
 
 
-def test_dense_svqb_drops_dependent_directions():
+@pytest.mark.parametrize("real", [False, True], ids=["complex", "real"])
+def test_dense_svqb_drops_dependent_directions(real):
     rng = np.random.default_rng(3)
-    V = rng.standard_normal((200, 5)) + 1j * rng.standard_normal((200, 5))
+    V = (rng.standard_normal((200, 5)) + (0 if real else 1j) * rng.standard_normal((200, 5))).astype(complex)
     V = np.concatenate([V, V[:, :2] * 2.0 + V[:, 2:4]], axis=1)  # rank 5 of 7
     T = lib.dense_svqb(V.conj().T @ V)
     assert T.shape == (7, 5)
     Q = V @ T
     assert np.allclose(Q.conj().T @ Q, np.eye(5), atol=1e-10)
+    if real:
+        assert np.all(T.imag == 0.0)
 
 
+@pytest.mark.parametrize("real", [False, True], ids=["complex", "real"])
 @pytest.mark.parametrize("n,nv", [(1, 1), (2, 0), (7, 3), (48, 16), (60, 20), (64, 64)])
-def test_dense_heev_lowest_matches_lapack(n, nv):
+def test_dense_heev_lowest_matches_lapack(n, nv, real):
     """Eigenvalues against LAPACK; the nv returned vectors are orthonormal
     eigenvectors of the nv lowest values (checked through residuals and against
-    LAPACK's vectors up to phase, the spectrum being simple here)."""
+    LAPACK's vectors up to phase, the spectrum being simple here).  A real
+    symmetric input takes the real Householder reduction and must come back
+    with exactly real vectors."""
     rng = np.random.default_rng(100 + n)
-    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
-    A = A + A.conj().T
+    A = rng.standard_normal((n, n)) + (0 if real else 1j) * rng.standard_normal((n, n))
+    A = (A + A.conj().T).astype(complex)
     w, V = lib.dense_heev_lowest(A, nv)
+    if real:
+        assert np.all(V.imag == 0.0)
     wr, Vr = np.linalg.eigh(A)
     scale = np.abs(wr).max()
     assert np.allclose(w, wr, rtol=0, atol=1e-13 * scale)
@@ -182,10 +190,12 @@ def test_dense_heev_lowest_matches_lapack(n, nv):
         assert np.allclose(overlap, 1.0, atol=1e-10)
 
 
-def test_dense_heev_lowest_degenerate_cluster():
+@pytest.mark.parametrize("real", [False, True], ids=["complex", "real"])
+def test_dense_heev_lowest_degenerate_cluster(real):
     """A multiple eigenvalue: the returned vectors span the LAPACK eigenspace."""
     rng = np.random.default_rng(7)
-    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)))
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)) + (0 if real else 1j) * rng.standard_normal((12, 12)))
+    Q = Q.astype(complex)
     vals = np.array([-1.0, -1.0, -1.0, 0.5, 0.5, 2.0, 3.0, 3.0, 4.0, 5.0, 6.0, 7.0])
     A = (Q * vals) @ Q.conj().T
     A = 0.5 * (A + A.conj().T)
