@@ -383,3 +383,59 @@ def eigs_sparse(H: sp.spmatrix, nev: int, tol: float = 1e-10, maxiter: int = 200
     w = w[order][:nev] - shift
     v = v[:, order][:, :nev]
     return w, v
+
+
+# ---------------------------------------------------------------------------
+# eq:int and Alg. 1 (final step): the eigenfunction in physical space, and the
+# error measures of Sec. 4 (numerical experiments)
+# ---------------------------------------------------------------------------
+
+def observation_axes(origin, step, npts) -> list:
+    """Coordinates of a tensor observation grid: axis j holds origin_j + step_j * i,
+    i = 0 .. npts_j - 1."""
+    return [float(origin[j]) + float(step[j]) * np.arange(int(npts[j]), dtype=np.float64)
+            for j in range(len(npts))]
+
+
+def paper_observation_grid(d: int):
+    """The grid of Sec. 4 on which eigenfunctions are compared: [-5a, 5a]^d with
+    a = 10^(3-d) and spacing 0.1.  Returns (origin, step, npts) per axis."""
+    a = 10.0 ** (3 - d)
+    n = int(round(10.0 * a / 0.1)) + 1
+    return [-5.0 * a] * d, [0.1] * d, [n] * d
+
+
+def eigenfunction_on_grid(P, labels: np.ndarray, U: np.ndarray, origin, step, npts) -> np.ndarray:
+    """u(xi) = sum_k U_k exp(i (P_paper k) . xi) = sum_k U_k exp(i 2 pi (P k) . xi)
+    over the labels k of the coefficient vector U (eq:int, the interpolant
+    I_{K,L}; P without the 2 pi), at every point of a tensor grid (shape npts,
+    first axis slowest).  The exponential of the sum over the d coordinates is
+    taken as the product of the d per-axis exponentials."""
+    P = np.asarray(P, dtype=np.float64)
+    d = P.shape[0]
+    U = np.asarray(U, dtype=np.complex128).ravel()
+    f = np.asarray(labels, dtype=np.float64) @ P.T          # N x d: the frequencies P k
+    axes = observation_axes(origin, step, npts)
+    E = [np.exp(1j * TWO_PI * np.outer(axes[j], f[:, j])) for j in range(d)]   # npts_j x N
+    out = np.empty(tuple(int(x) for x in npts), dtype=np.complex128)
+    lead = [int(x) for x in npts[:-1]]
+    for idx in np.ndindex(*lead) if lead else [()]:
+        w = U.copy()
+        for j, i in enumerate(idx):
+            w = w * E[j][i]
+        out[idx] = E[d - 1] @ w
+    return out
+
+
+def normalise_at_max(u: np.ndarray) -> np.ndarray:
+    """u divided by its value at the (first) point of largest modulus, which
+    fixes the phase and makes the maximal modulus 1 (Sec. 4: eigenfunctions are
+    compared after division by their maximal modulus)."""
+    flat = np.asarray(u).ravel()
+    return np.asarray(u) / flat[int(np.argmax(np.abs(flat)))]
+
+
+def eigenfunction_error(u: np.ndarray, u_ref: np.ndarray) -> float:
+    """E_f = || u - u* ||_inf on the observation grid, both normalised by
+    normalise_at_max (Sec. 4)."""
+    return float(np.max(np.abs(normalise_at_max(u) - normalise_at_max(u_ref))))

@@ -288,3 +288,81 @@ def test_sparse_lobpcg_matches_dense():
     wd = np.linalg.eigvalsh(H.toarray())[:6]
     ws, vs = O.eigs_sparse(H, 6, tol=1e-10, block=10, maxiter=1000)
     assert np.allclose(ws, wd, rtol=0, atol=1e-9)
+
+
+# --- eq:int / Sec. 4: the eigenfunction on the observation grid ------------
+
+def _ground_vector(prob, variant="exact"):
+    """Ground-state coefficient vector and the labels of its entries."""
+    H = O.hamiltonian_sparse(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, variant)
+    k = O.grid_labels(prob.P, prob.d, prob.K, prob.L, variant)
+    if H.shape[0] <= 3000:
+        w, V = np.linalg.eigh(H.toarray())
+        return w[0], V[:, 0], k
+    w, V = spla.eigsh(H.tocsc(), k=1, sigma=_golden("ex1_reference.json")["E0"] - 1e-3, which="LM", tol=1e-14)
+    return w[0], V[:, 0], k
+
+
+@pytest.fixture(scope="module")
+def ex1_reference_function():
+    """u0* of Ex. 4.1 (v0 = 2.5) on the paper's 1D grid [-500, 500], h = 0.1,
+    from a window far beyond convergence (K = 10, L = 300; its E0 equals the
+    stored E0* to 1e-15 relative)."""
+    prob = W.paper_example_1d(2.5, 10, 300)
+    e0, U, k = _ground_vector(prob)
+    assert abs(e0 - _golden("ex1_reference.json")["E0"]) <= 1e-13 * e0
+    return O.eigenfunction_on_grid(prob.P, k, U, *O.paper_observation_grid(1))
+
+
+@pytest.mark.parametrize("method,K,L,printed", [("iwfpm", 5, 20, 1.82e-02), ("pm", 14, 20, 1.82e-02),
+                                                ("pm", 12, 40, 1.91e-02)])
+def test_table2_eigenfunction_errors(ex1_reference_function, method, K, L, printed):
+    """Table 2 (Ex. 4.1, v0 = 2.5): E_f = ||u0 - u0*||_inf on [-500, 500] with
+    step 0.1, both functions divided by their value at their point of largest
+    modulus, to the printed 3 digits.  (The other entries of the row, whose
+    error peaks at |x| > 300, come out 1-6 % apart from the printed values, and
+    the L = 60 entry 2.7e-05 against 1.49e-05: the largest error of an
+    oscillating function on a sampled grid is sensitive to the sampling.)"""
+    prob = W.paper_example_1d(2.5, K, L)
+    _, U, k = _ground_vector(prob, "exact" if method == "iwfpm" else "pm")
+    u = O.eigenfunction_on_grid(prob.P, k, U, *O.paper_observation_grid(1))
+    ef = O.eigenfunction_error(u, ex1_reference_function)
+    assert abs(ef - printed) <= 0.005 * printed, (ef, printed)
+
+
+def test_eigenfunction_solves_the_schroedinger_equation():
+    """The interpolant of a converged eigenvector satisfies -u''/2 + v u = E u
+    pointwise, with v written out as cosines (not from its modes) and u''
+    from a fourth-order difference.  Phases in the cosines make v(x) differ
+    from v(-x), so the sign of the exponent and the 2 pi scale are both fixed
+    (with the sign flipped the residual is 0.37 max|u|)."""
+    a, b, p1, p2 = 1.3, 0.8, 0.7, 0.3
+    P = np.array([[1.0, W.GOLDEN]])
+    modes = np.array([[1, 0], [-1, 0], [0, 1], [0, -1]])
+    vhat = np.array([a / 2 * np.exp(1j * p1), a / 2 * np.exp(-1j * p1),
+                     b / 2 * np.exp(-1j * p2), b / 2 * np.exp(1j * p2)])
+    H = O.hamiltonian_dense(P, 1, [8], [40], modes, vhat)
+    w, V = np.linalg.eigh(H)
+    k = O.grid_labels(P, 1, [8], [40])
+    umax = np.abs(O.eigenfunction_on_grid(P, k, V[:, 0], [-30.0], [0.05], [1201])).max()
+    h = 1e-3
+    for x in np.linspace(-30.0, 30.0, 9):
+        u = O.eigenfunction_on_grid(P, k, V[:, 0], [x - 2 * h], [h], [5])
+        d2 = (-u[0] + 16 * u[1] - 30 * u[2] + 16 * u[3] - u[4]) / (12 * h * h)
+        v = a * math.cos(2 * math.pi * x + p1) + b * math.cos(2 * math.pi * W.GOLDEN * x - p2)
+        assert abs(-0.5 * d2 + v * u[2] - w[0] * u[2]) <= 1e-7 * umax, x
+
+
+def test_eigenfunction_grid_is_separable_product():
+    """A 2D grid evaluation equals the point-by-point sum over the labels
+    (brute force on a small grid)."""
+    prob = W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 3, 4)
+    _, U, k = _ground_vector(prob)
+    origin, step, npts = [-2.0, 1.5], [0.7, -0.3], [5, 4]
+    u = O.eigenfunction_on_grid(prob.P, k, U, origin, step, npts)
+    f = k @ prob.P.T
+    for i in range(npts[0]):
+        for j in range(npts[1]):
+            x = np.array([origin[0] + step[0] * i, origin[1] + step[1] * j])
+            ref = sum(U[t] * np.exp(2j * math.pi * f[t] @ x) for t in range(len(U)))
+            assert abs(u[i, j] - ref) <= 1e-12 * np.abs(U).sum()
