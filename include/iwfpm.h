@@ -148,6 +148,30 @@ int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
 int iwfpm_conv(iwfpm_plan_t plan, const void* psi, void* out, int nvec, int precision, void* stream);
 
 /*
+ * iwfpm_eigenfunction - the eigenfunction in physical space (eq:int, the
+ * interpolant I_{K,L} of Alg. 1's last step): for a coefficient vector U in
+ * the plan's vector order,
+ *     out(xi) = sum over the window of U_k exp(i 2 pi (P k) . xi)
+ * (P in this library's convention, without the paper's 2 pi), at every point
+ * of the tensor grid xi_j = origin[j] + step[j] * i_j, i_j = 0 .. npts[j] - 1,
+ * j = 0 .. d-1 (the physical dimensions).  Sec. 4 compares eigenfunctions on
+ * [-5a, 5a]^d, a = 10^(3-d), with spacing 0.1.
+ * u: device, N complex float64.  origin, step: host, d float64; npts: host, d
+ * int, each >= 1, product <= 2^36.  out: device, prod(npts) complex float64,
+ * row-major (axis 0 slowest); it must not overlap u.  Float64 throughout:
+ * phases are reduced to one turn before the sine and cosine.  Asynchronous on
+ * `stream` after a one-time set-up per plan (the frequencies P k of the
+ * window points, computed on the host and copied synchronously) and growth of
+ * the plan's scratch (per-axis tables of up to 256 MB plus slice partials of
+ * up to 512 MB), which synchronises `stream` when it reallocates.  Not
+ * re-entrant per plan (shared scratch).
+ * Errors: ERR_ARG (NULL pointers, npts < 1, non-finite origin or step, too
+ * many points), ERR_NODEVICE / ERR_DEVICE, ERR_ALLOC.
+ */
+int iwfpm_eigenfunction(iwfpm_plan_t plan, const void* u, const double* origin, const double* step,
+                        const int* npts, void* out, void* stream);
+
+/*
  * Ragged batches: many plans (for example a sweep of couplings whose windows,
  * and so grid sizes, differ) applied together, Sec. 4.1's H~ psi per plan.
  * iwfpm_batch_create - B plans on one device, convolution precision

@@ -31,7 +31,7 @@ EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_de
             "iwfpm_conv", "iwfpm_default_learned_opts", "iwfpm_default_train_opts", "iwfpm_learned_create",
             "iwfpm_learned_destroy", "iwfpm_learned_nparams", "iwfpm_learned_get", "iwfpm_learned_set",
             "iwfpm_learned_attach", "iwfpm_learned_shells", "iwfpm_learned_forward", "iwfpm_learned_grad",
-            "iwfpm_learned_step", "iwfpm_learned_train"]
+            "iwfpm_learned_step", "iwfpm_learned_train", "iwfpm_eigenfunction"]
 
 _VOID_FUNCS = ("iwfpm_default_opts", "iwfpm_status_string", "iwfpm_default_eigs_opts",
                "iwfpm_default_learned_opts", "iwfpm_default_train_opts")
@@ -126,6 +126,7 @@ def load_library():
     lib.iwfpm_default_eigs_opts.restype = None
     lib.iwfpm_eigs.argtypes = [vp, ctypes.POINTER(_EigsOpts), vp, dp, vp, dp, ctypes.POINTER(_Stats), vp]
     lib.iwfpm_conv.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.iwfpm_eigenfunction.argtypes = [vp, vp, dp, dp, ip, vp, vp]
     fp = ctypes.POINTER(ctypes.c_float)
     lib.iwfpm_default_learned_opts.argtypes = [ctypes.POINTER(_LearnedOpts)]
     lib.iwfpm_default_learned_opts.restype = None
@@ -475,6 +476,29 @@ class Plan:
         st = _lib().iwfpm_apply_prec(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                      nvec, prec, _stream_handle(stream))
         _check(st, "iwfpm_apply")
+        return out
+
+    def eigenfunction(self, u, origin, step, npts, out=None, stream=None):
+        """u(xi) = sum_k U_k exp(i 2 pi (P k) . xi) on the tensor grid
+        xi_j = origin[j] + step[j] * i_j (iwfpm_eigenfunction); u: (N,)
+        complex128 on the plan's GPU; returns a complex128 tensor of shape npts."""
+        import torch
+        if u.dim() != 1 or u.dtype != torch.complex128 or u.numel() != self.N or not u.is_cuda:
+            raise ValueError(f"u must be a CUDA complex128 vector of length {self.N}")
+        u = u.contiguous()
+        npts = [int(x) for x in npts]
+        if not (len(origin) == len(step) == len(npts) == self.d):
+            raise ValueError(f"origin, step and npts need {self.d} entries")
+        if out is None:
+            out = torch.empty(npts, dtype=torch.complex128, device=u.device)
+        elif tuple(out.shape) != tuple(npts) or out.dtype != torch.complex128 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex128 tensor of shape npts")
+        o = (ctypes.c_double * self.d)(*[float(x) for x in origin])
+        h = (ctypes.c_double * self.d)(*[float(x) for x in step])
+        n = (ctypes.c_int32 * self.d)(*npts)
+        _check(_lib().iwfpm_eigenfunction(self._h, ctypes.c_void_p(u.data_ptr()), o, h, n,
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+               "iwfpm_eigenfunction")
         return out
 
     def conv(self, psi, out=None, precision=None, stream=None):

@@ -3219,6 +3219,8 @@ int iwfpm_destroy(iwfpm_plan_t p) {
         dev_free(p->d_vgrid32);
         dev_free(p->d_vgrid64);
         dev_free(p->d_ws);
+        dev_free(p->d_ef_freq);
+        dev_free(p->d_ef_ws);
         for (auto& sl : p->prof.ring)
             for (auto& e : sl.ev)
                 if (e) (void)hipEventDestroy(e);

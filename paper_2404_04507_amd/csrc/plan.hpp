@@ -72,6 +72,8 @@ struct iwfpm_plan_s {
     bool host_only = true;
     iwfpm::DeviceBuf d_slice_a, d_slice_g, d_vtab32, d_vtab64, d_vgrid32, d_vgrid64;
     iwfpm::DeviceBuf d_ws;        // apply workspace
+    iwfpm::DeviceBuf d_ef_freq;   // eigenfunction output: (P k)_j per window point (d x N)
+    iwfpm::DeviceBuf d_ef_ws;     // eigenfunction output: per-axis tables and slice partials
     iwfpm::DevTabs tabs{};
     iwfpm::ApplyProfiler prof;
     // eigensolver state (lobpcg.cpp)
