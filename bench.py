@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-pm", action="store_true")
+    ap.add_argument("--no-ef", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
@@ -180,6 +181,8 @@ def main():
             out["eigs_3d_lifted_6d"] = run_eigs_c3(lib, W, net)
     if not a.no_pm:
         out["pm_vs_iwfpm"] = run_pm_compare(lib, W)
+    if not a.no_ef:
+        out["eigenfunction"] = run_eigenfunction(lib, W)
     if not a.no_sweep:
         out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
@@ -332,6 +335,43 @@ def run_pm_compare(lib, W):
         row["time_ratio"] = row["pm"]["seconds"] / row["iwfpm"]["seconds"]
         row["E0_rel_diff"] = abs(row["pm"]["E0"] - row["iwfpm"]["E0"]) / abs(row["iwfpm"]["E0"])
         res.append(row)
+    return res
+
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def run_eigenfunction(lib, W, reps=5):
+    """The ground state in physical space (eq:int) on the paper's 2D
+    observation grid [-50, 50]^2, step 0.1 (1001 x 1001 points): the paper's
+    Ex. 4.2 case I window (K = 6, L = 20) and the 2D/4D benchmark window.
+    Algorithmic flops = 8 N x points (one complex multiply-add per window
+    point and grid point); median of `reps` timed calls with the frequencies
+    and scratch already set up."""
+    import math
+    import torch
+    cases = [("ex4.2 case I K=6 L=20", W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 6, 20), "fp64"),
+             ("2d_lifted_4d lam=0.5 K=12 L=16", W.c2_2d(lam=0.5), "fp32")]
+    origin, step, npts = [-50.0, -50.0], [0.1, 0.1], [1001, 1001]
+    res = []
+    for name, prob, prec in cases:
+        with lib.Plan.from_problem(prob, precision=prec) as plan:
+            r = plan.eigs(1, block=4, tol=1e-10 if prec == "fp64" else 1e-8, maxit=2000)
+            u = r.evecs[0].contiguous()
+            out = plan.eigenfunction(u, origin, step, npts)
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                plan.eigenfunction(u, origin, step, npts, out=out)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = sorted(ts)[len(ts) // 2]
+            flops = 8.0 * plan.N * npts[0] * npts[1]
+            tf = flops / (ms / 1e3) / 1e12
+            res.append({"case": name, "N": plan.N, "grid": npts, "ms": ms, "tflops": tf,
+                        "frac_fp64_mfma_peak": tf / FP64_MFMA_PEAK_TFLOPS, "E0": float(r.evals[0])})
     return res
 
 
