@@ -278,6 +278,12 @@ __device__ __forceinline__ int remap_block(int bid, int nblocks, int on) {
 // independent global loads each thread keeps in flight in the tile copies
 constexpr int kBatch = 8;
 
+// two adjacent complex entries, moved as one access
+template <typename R>
+struct alignas(16) CPair {
+    cplx<R> a, b;
+};
+
 // element iterator over a tile of `rows` rows of length sl: thread-strided,
 // with row / column updated incrementally (no division per element)
 struct RowIter {
@@ -357,6 +363,7 @@ __device__ __forceinline__ void load_gather(const DevGeom& g, const DevTabs& t, 
 // the room to psi and to the grid still in use by the other passes (pass 3
 // 77 -> 71 us and pass 1 60 -> 51 us on the 589,824-point, 16-vector block).
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ cplx<float> nt_load(const cplx<float>* p) {
     nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
@@ -372,6 +379,33 @@ __device__ __forceinline__ cplx<double> nt_load(const cplx<double>* p) {
 template <typename R>
 __device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ w, int count, cplx<R>* tile, RowGeom rg) {
     const int nt = blockDim.x;
+    if constexpr (sizeof(cplx<R>) == 8) {
+        // float entries: adjacent pairs (rows of even length, 16-byte aligned
+        // start) as one 16-byte load, stored to LDS as two entries
+        if ((rg.sl & 1) == 0 && (count & 1) == 0 && (reinterpret_cast<uintptr_t>(w) & 15) == 0) {
+            const int count2 = count >> 1;
+            const nt_f4* w4 = reinterpret_cast<const nt_f4*>(w);
+            for (RowIter it(threadIdx.x, nt, rg.sl >> 1); it.e < count2;) {
+                nt_f4 v[kBatch];
+                RowIter j = it;
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    v[u] = j.e < count2 ? __builtin_nontemporal_load(w4 + j.e) : nt_f4{0.f, 0.f, 0.f, 0.f};
+                    j.next(nt);
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    if (it.e < count2) {
+                        cplx<R>* d = tile + it.row * rg.sp + 2 * it.col;
+                        d[0] = cplx<R>{v[u].x, v[u].y};
+                        d[1] = cplx<R>{v[u].z, v[u].w};
+                    }
+                    it.next(nt);
+                }
+            }
+            return;
+        }
+    }
     for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count;) {
         cplx<R> v[kBatch];
         RowIter j = it;
@@ -391,6 +425,17 @@ __device__ __forceinline__ void load_tile(const cplx<R>* __restrict__ w, int cou
 template <typename R>
 __device__ __forceinline__ void store_tile(cplx<R>* __restrict__ w, int count, const cplx<R>* tile, RowGeom rg) {
     const int nt = blockDim.x;
+    if constexpr (sizeof(cplx<R>) == 8) {
+        // float entries: adjacent pairs as one 16-byte store (as in load_tile)
+        if ((rg.sl & 1) == 0 && (count & 1) == 0 && (reinterpret_cast<uintptr_t>(w) & 15) == 0) {
+            float4* w4 = reinterpret_cast<float4*>(w);
+            for (RowIter it(threadIdx.x, nt, rg.sl >> 1); it.e < (count >> 1); it.next(nt)) {
+                const cplx<R>* s = tile + it.row * rg.sp + 2 * it.col;
+                w4[it.e] = make_float4(s[0].x, s[0].y, s[1].x, s[1].y);
+            }
+            return;
+        }
+    }
     for (RowIter it(threadIdx.x, nt, rg.sl); it.e < count; it.next(nt)) w[it.e] = tile[it.row * rg.sp + it.col];
 }
 
@@ -534,20 +579,44 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     const RowGeom rg{El << lgT, (El + 1) << lgT};
     const int count = sout << lgT;
 
-    // logical element e = row * (El T) + col: outer index o = row El + col / T, column col % T
-    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
-        cplx<R> v[kBatch];
-        RowIter j = it;
+    // logical element e = row * (El T) + col: outer index o = row El + col / T, column col % T.
+    // With an even, whole tile the columns come in pairs that are adjacent in
+    // memory and in LDS (all extents are even, so the pairs stay aligned):
+    // they move as one access each, twice the bytes in flight per load.
+    const bool pairs = (T & 1) == 0 && tw == T;
+    if (pairs) {
+        const int count2 = count >> 1;
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < count2;) {
+            CPair<R> v[kBatch];
+            RowIter j = it;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            int o = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
-            v[u] = (j.e < count && tt < tw) ? w[o * sin_ + tt] : cplx<R>{R(0), R(0)};
-            j.next(blockDim.x);
+            for (int u = 0; u < kBatch; ++u) {
+                const int col = 2 * j.col;
+                const int o = j.row * El + (col >> lgT), tt = col & (T - 1);
+                v[u] = j.e < count2 ? *reinterpret_cast<const CPair<R>*>(w + o * sin_ + tt) : CPair<R>{};
+                j.next(blockDim.x);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count2) *reinterpret_cast<CPair<R>*>(tile + it.row * rg.sp + 2 * it.col) = v[u];
+                it.next(blockDim.x);
+            }
         }
+    } else {
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
+            cplx<R> v[kBatch];
+            RowIter j = it;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
-            it.next(blockDim.x);
+            for (int u = 0; u < kBatch; ++u) {
+                int o = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
+                v[u] = (j.e < count && tt < tw) ? w[o * sin_ + tt] : cplx<R>{R(0), R(0)};
+                j.next(blockDim.x);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
+                it.next(blockDim.x);
+            }
         }
     }
     __syncthreads();
@@ -574,9 +643,19 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
         run_axis<-1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
-        int o = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
-        if (tt < tw) w[o * sin_ + tt] = tile[it.row * rg.sp + it.col];
+    if (pairs) {
+        const int count2 = count >> 1;
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < count2; it.next(blockDim.x)) {
+            const int col = 2 * it.col;
+            const int o = it.row * El + (col >> lgT), tt = col & (T - 1);
+            *reinterpret_cast<CPair<R>*>(w + o * sin_ + tt) =
+                *reinterpret_cast<const CPair<R>*>(tile + it.row * rg.sp + col);
+        }
+    } else {
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
+            int o = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
+            if (tt < tw) w[o * sin_ + tt] = tile[it.row * rg.sp + it.col];
+        }
     }
 }
 
