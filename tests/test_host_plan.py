@@ -207,3 +207,19 @@ def test_dense_heev_lowest_degenerate_cluster(real):
     assert np.allclose(P @ V, V, atol=1e-12)
     with pytest.raises(lib.IwfpmError):
         lib.dense_heev_lowest(A, 13)
+
+
+def test_eigenfunction_argument_checks_on_host_plan():
+    """iwfpm_eigenfunction validates before any device work: NULL pointers and
+    empty axes are ERR_ARG, a host-only plan is ERR_NODEVICE."""
+    import ctypes
+    prob = W.paper_example_1d(2.5, 2, 2)
+    with lib.Plan.from_problem(prob, device=-1) as p:
+        L = lib.load_library()
+        o = (ctypes.c_double * 1)(0.0)
+        h = (ctypes.c_double * 1)(0.1)
+        n = (ctypes.c_int32 * 1)(4)
+        fake = ctypes.c_void_p(16)  # never dereferenced: every path below returns first
+        assert L.iwfpm_eigenfunction(p._h, None, o, h, n, fake, None) == -1
+        assert L.iwfpm_eigenfunction(p._h, fake, o, h, None, fake, None) == -1
+        assert L.iwfpm_eigenfunction(p._h, fake, o, h, n, fake, None) == -10
