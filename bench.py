@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-pm", action="store_true")
     ap.add_argument("--no-ef", action="store_true")
+    ap.add_argument("--paper-3d", action="store_true",
+                    help="also solve Ex. 4.3 at K = 5, L = 10, 20, 30 (up to 2.16e8 DOF, ~4 minutes)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
@@ -183,6 +185,8 @@ def main():
         out["pm_vs_iwfpm"] = run_pm_compare(lib, W)
     if not a.no_ef:
         out["eigenfunction"] = run_eigenfunction(lib, W)
+    if a.paper_3d:
+        out["paper_3d"] = run_paper_3d(lib, W)
     if not a.no_sweep:
         out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
@@ -335,6 +339,30 @@ def run_pm_compare(lib, W):
         row["time_ratio"] = row["pm"]["seconds"] / row["iwfpm"]["seconds"]
         row["E0_rel_diff"] = abs(row["pm"]["E0"] - row["iwfpm"]["E0"]) / abs(row["iwfpm"]["E0"])
         res.append(row)
+    return res
+
+
+def run_paper_3d(lib, W):
+    """Ex. 4.3 (3D lifted to 6D) at the paper's truncations K = 5, L = 10, 20,
+    30 (8e6, 6.4e7 and 2.16e8 window points; L >= 20 runs the five-pass
+    schedule), ground state to eta <= 1e-9 with the float32 convolution.  The
+    paper's reference E0* (L = 40) is beyond one GPU here, so it is inferred
+    from the printed E_v(30), and E_v(10), E_v(20) follow from it (Table 9)."""
+    import math
+    printed = {"I": {10: 6.82e-4, 20: 1.58e-4, 30: 4.34e-5}, "II": {10: 4.08e-3, 20: 9.91e-4, 30: 2.71e-4}}
+    res = {}
+    for case, beta in (("I", math.pi), ("II", 0.5 * math.pi)):
+        rows = {}
+        for L in (10, 20, 30):
+            prob = W.paper_example_3d(beta, 5, L)
+            with lib.Plan.from_problem(prob, precision="fp32") as plan:
+                r, t = _timed(lambda: plan.eigs(1, tol=1e-9, maxit=4000, want_vectors=False))
+                rows[L] = {"N": plan.N, "E0": float(r.evals[0]), "iterations": r.iterations, "seconds": t}
+        e_star = rows[30]["E0"] / (1.0 + printed[case][30])
+        for L in (10, 20):
+            rows[L]["E_v_from_printed_E_v30"] = (rows[L]["E0"] - e_star) / e_star
+            rows[L]["E_v_printed"] = printed[case][L]
+        res[case] = rows
     return res
 
 

@@ -99,8 +99,13 @@ const char* iwfpm_status_string(int status);
  * iwfpm_plan - Alg. 1 steps 1-2 set-up: builds K_{K,L}, K*_{K,L} and the
  * per-slice offsets of rho^{-1} (eq:inverse1-3), the kinetic tables, the
  * potential on G_{K,L} (eq:G_KL) and the FFT schedule, and uploads them to
- * the device.  Host inputs (P, K, L, modes, vhat) are copied; the caller may
- * free them on return.  opts may be NULL (defaults).  Blocking.
+ * the device.  The schedule is one fused kernel for grids that fit one
+ * workgroup, else three passes (trailing axes, leading axes with the
+ * potential, trailing axes with the kinetic term), else, when the leading
+ * block fits no workgroup either (e.g. 40^3 x 10^3), five: a further pass
+ * transforms the axes between the two groups before and after the middle
+ * one.  Host inputs (P, K, L, modes, vhat) are copied; the caller may free
+ * them on return.  opts may be NULL (defaults).  Blocking.
  * Errors: ERR_ARG (d < 1, n <= d, n > 8, K/L < 1, grid extent unsupported),
  * ERR_SINGULAR_PI, ERR_NONHERMITIAN, ERR_DEVICE / ERR_ALLOC.
  */
@@ -198,7 +203,8 @@ int iwfpm_batch_destroy(iwfpm_batch_t batch);
 /*
  * iwfpm_tune - autotuner: times every feasible apply schedule of the plan on
  * its device (fused, or three-pass over every axis split x middle-pass tile
- * width x slabs per workgroup) on nvec scratch vectors with HIP events on
+ * width x slabs per workgroup; a grid that only the five-pass schedule fits
+ * keeps it untimed, best_us = -1) on nvec scratch vectors with HIP events on
  * `stream`, and keeps the fastest for `precision` (IWFPM_PREC_*, or -1 for the
  * plan's).  With the environment variable IWFPM_TUNE_CACHE naming a file,
  * earlier results for the same (precision, order, potential form, d, nvec,

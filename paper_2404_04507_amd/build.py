@@ -40,7 +40,7 @@ HOST_SOURCES = ["plan.cpp", "batch.cpp", "lobpcg.cpp", "learned.cpp"]
 HOST_FAST = {"lobpcg.cpp", "learned.cpp"}
 FAST_FLAGS = ["-O3", "-fcx-limited-range", "-ffp-contract=fast"]
 DEVICE_SOURCES = ["blas_kernels.hip", "learned_kernels.hip", "eigfun.hip"]
-APPLY_TUS = [(k, r, m) for k in range(5) for r in ("float", "double") for m in (16, 32, 64)]
+APPLY_TUS = [(k, r, m) for k in range(6) for r in ("float", "double") for m in (16, 32, 64)]
 
 
 def _jobs():

@@ -659,6 +659,64 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     }
 }
 
+// pass M: the DFT (SIGN) along axes [a, b) alone, a = split_mid and b = split,
+// on a tile of `tile_mid` consecutive columns (the index over the axes from b
+// on) of one outer index (the axes before a) of one vector.  The LDS tile has
+// pass 2's layout with the axes [a, b) in place of the leading block.
+template <int SIGN, typename R, int MAXS>
+__device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd, cplx<R>* __restrict__ ws,
+                                           int bid_raw, int nblocks, unsigned char* smem) {
+    cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
+    const int a = pd.split_mid, b = pd.split;
+    const int T = pd.tile_mid, lgT = __ffs(T) - 1;
+    const int cols = pd.s_in;                       // product of the extents from b on
+    const int mid = g.stride[a - 1] / cols;         // product of the extents in [a, b)
+    const int outer = g.N / (mid * cols);           // product of the extents before a
+    const int ntile = (cols + T - 1) / T;
+    const int bid = remap_block(bid_raw, nblocks, pd.xcd_remap);
+    const int vec = bid / (outer * ntile);
+    const int rem = bid - vec * outer * ntile;
+    const int o = rem / ntile;
+    const int c0 = (rem - o * ntile) * T;
+    const int tw = min(T, cols - c0);
+    cplx<R>* __restrict__ w = ws + (long long)vec * g.N + (long long)o * mid * cols + c0;
+    const int El = g.ext[b - 1];
+    const RowGeom rg{El << lgT, (El + 1) << lgT};
+    const int count = mid << lgT;
+    // element e = row * (El T) + col: index within [a, b) = row El + col / T, column col % T
+    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
+        cplx<R> v[kBatch];
+        RowIter j = it;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int q = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
+            v[u] = (j.e < count && tt < tw) ? w[q * cols + tt] : cplx<R>{R(0), R(0)};
+            j.next(blockDim.x);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
+            it.next(blockDim.x);
+        }
+    }
+    __syncthreads();
+    for (int ax = a; ax < b; ++ax) {
+        const int es = (g.stride[ax] / cols) << lgT;
+        run_axis<SIGN, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
+        __syncthreads();
+    }
+    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
+        const int q = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
+        if (tt < tw) w[q * cols + tt] = tile[it.row * rg.sp + it.col];
+    }
+}
+
+template <int SIGN, typename R, int MAXS>
+__global__ void __launch_bounds__(256) k_passm(DevGeom g, PassDesc pd, cplx<R>* __restrict__ ws) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    passm_body<SIGN, R, MAXS>(g, pd, ws, blockIdx.x, gridDim.x, smem);
+}
+
 template <typename R, int MAXS>
 __global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem[];

@@ -31,6 +31,24 @@ inline size_t lds_columns(const DevGeom& g, const PassDesc& pd, size_t esz) {
     return (size_t)(pd.s_out / El) * (El + 1) * pd.tile * esz;
 }
 
+// the further pass over axes [split_mid, split): rows of (extent of axis
+// split - 1) x tile_mid columns, padded by tile_mid
+inline size_t lds_mid(const DevGeom& g, const PassDesc& pd, size_t esz) {
+    int El = g.ext[pd.split - 1];
+    int mid = g.stride[pd.split_mid - 1] / pd.s_in;
+    return (size_t)(mid / El) * (El + 1) * pd.tile_mid * esz;
+}
+// the middle pass's descriptor when a further pass takes axes [split_mid, split)
+inline PassDesc middle_desc(const DevGeom& g, const PassDesc& pd) {
+    PassDesc q = pd;
+    if (pd.split_mid > 0) {
+        q.split = pd.split_mid;
+        q.s_in = g.stride[pd.split_mid - 1];
+        q.s_out = g.N / q.s_in;
+    }
+    return q;
+}
+
 template <typename R, int MAXS>
 hipError_t launch_fused(const DevGeom& g, const DevTabs& t, int threads, const void* psi, void* hpsi, int nvec,
                         hipStream_t st);
@@ -42,6 +60,11 @@ hipError_t launch_pass2(const DevGeom& g, const DevTabs& t, const PassDesc& pd, 
 template <typename R, int MAXS>
 hipError_t launch_pass3(const DevGeom& g, const DevTabs& t, const PassDesc& pd, const void* psi, const void* ws,
                         void* hpsi, int nvec, hipStream_t st);
+// the further pass (sign +1: inverse, -1: forward)
+template <typename R, int MAXS>
+hipError_t launch_passm(const DevGeom& g, const PassDesc& pd, int sign, void* ws, int nvec, hipStream_t st);
+template <typename R, int MAXS>
+hipError_t prepare_passm(int lds_bytes);
 // persistent batched pass over the work table (head, items in device memory)
 template <typename R, int MAXS>
 hipError_t launch_batch(const void* head, const void* items, int grid, size_t lds, int pass, hipStream_t st);

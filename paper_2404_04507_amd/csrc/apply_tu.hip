@@ -1,6 +1,7 @@
 // apply_tu.hip - one (kernel, precision) pair of the apply, selected at
 // build time by IWFPM_TU_KERNEL (0 fused, 1 pass 1, 2 pass 2, 3 pass 3, 4 the
-// persistent batched pass) and
+// persistent batched pass, 5 the further pass over the axes between the
+// middle pass and pass 1) and
 // IWFPM_TU_REAL (float or double) and IWFPM_TU_MAXS, the largest
 // axis extent the instantiated kernels transform (16, 32 or 64).
 #include "apply_kernels.hpp"
@@ -92,6 +93,27 @@ hipError_t prepare_batch<R, M>(int lds_bytes) {
 template <>
 hipError_t occupancy_batch<R, M>(size_t lds, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_pass<R, M>, 256, lds);
+}
+#elif IWFPM_TU_KERNEL == 5
+template <>
+hipError_t launch_passm<R, M>(const DevGeom& g, const PassDesc& pd, int sign, void* ws, int nvec, hipStream_t st) {
+    const int cols = pd.s_in;
+    const int outer = g.N / g.stride[pd.split_mid - 1];
+    const long long nb = (long long)((cols + pd.tile_mid - 1) / pd.tile_mid) * outer * nvec;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    size_t lds = lds_mid(g, pd, sizeof(cplx<R>));
+    if (sign > 0)
+        k_passm<1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, pd, reinterpret_cast<cplx<R>*>(ws));
+    else
+        k_passm<-1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, pd, reinterpret_cast<cplx<R>*>(ws));
+    return hipGetLastError();
+}
+template <>
+hipError_t prepare_passm<R, M>(int lds_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_passm<1, R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_passm<-1, R, M>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 #else
 #error "IWFPM_TU_KERNEL out of range"

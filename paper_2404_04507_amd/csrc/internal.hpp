@@ -42,6 +42,13 @@ struct PassDesc {
     int threads_inner;  // block size of passes 1 and 3
     int threads_outer;  // block size of pass 2
     int xcd_remap;      // remap workgroup ids so that one XCD walks adjacent tiles
+    // grids whose leading block does not fit one workgroup: the middle pass
+    // keeps axes [0, split_mid) (with the potential) and a further pass
+    // transforms axes [split_mid, split) on its own, once before and once after
+    // it (0: no such pass)
+    int split_mid;
+    int tile_mid;       // that pass: columns per workgroup (a power of two)
+    int threads_mid;    // that pass: block size
 };
 
 // LDS layout of a tile whose last axis (extent sl) is padded to an odd pitch sp

@@ -315,6 +315,7 @@ static const size_t kLdsMax = 160 * 1024;
 
 static int round64(int x) { return ((x + 63) / 64) * 64; }
 static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc);
+static int choose_mid_schedule(iwfpm_plan_s* p, int prec);
 
 static int choose_schedule(iwfpm_plan_s* p, int prec) {
     Schedule& sc = p->sched[prec];
@@ -364,9 +365,10 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
                 split = s;
             }
         }
-        if (split == 0) return IWFPM_ERR_UNSUPPORTED;
+        if (split == 0) return choose_mid_schedule(p, prec);
     }
     pd.split = split;
+    pd.split_mid = 0;
     pd.s_in = g.stride[split - 1];
     pd.s_out = g.N / pd.s_in;
     // middle pass: `tile` consecutive columns (a power of two)
@@ -423,6 +425,109 @@ static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc) {
     sc.ok = true;
 }
 
+// threads and extent classes of a schedule with the further pass
+static void finalize_mid(const iwfpm_plan_s* p, Schedule& sc) {
+    const DevGeom& g = p->geom;
+    PassDesc& pd = sc.pd;
+    const PassDesc q = middle_desc(g, pd);
+    const int mid = g.stride[pd.split_mid - 1] / pd.s_in;
+    int maxpi = 0, maxpo = 0, maxpm = 0, mi = 0, mo = 0;
+    for (int ax = pd.split; ax < p->n; ++ax) {
+        maxpi = std::max(maxpi, pd.slabs_per_wg * pd.s_in / g.ext[ax]);
+        mi = std::max(mi, g.ext[ax]);
+    }
+    for (int ax = 0; ax < pd.split_mid; ++ax) {
+        maxpo = std::max(maxpo, q.s_out * pd.tile / g.ext[ax]);
+        mo = std::max(mo, g.ext[ax]);
+    }
+    for (int ax = pd.split_mid; ax < pd.split; ++ax) {
+        maxpm = std::max(maxpm, mid * pd.tile_mid / g.ext[ax]);
+        mo = std::max(mo, g.ext[ax]);
+    }
+    pd.threads_inner = std::min(256, round64(maxpi));
+    pd.threads_outer = std::min(256, round64(maxpo));
+    pd.threads_mid = std::min(256, round64(maxpm));
+    sc.maxs_inner = extent_class(mi);
+    sc.maxs_outer = extent_class(mo);
+    sc.fused = false;
+    sc.ok = true;
+}
+
+// Grids whose leading block fits no single middle pass (e.g. 40^3 x 10^3):
+// passes 1 and 3 keep the trailing axes [split, n), the middle pass the
+// leading axes [0, s1) with the potential, and a further pass the axes
+// [s1, split) in between (five launches per apply instead of three).
+static int choose_mid_schedule(iwfpm_plan_s* p, int prec) {
+    Schedule& sc = p->sched[prec];
+    const DevGeom& g = p->geom;
+    const int n = p->n;
+    const size_t esz = prec == 1 ? 8 : 16;
+    const int hi = p->opts.order == IWFPM_ORDER_WINDOW ? n - p->d : n - 1;
+    PassDesc& pd = sc.pd;
+    pd = PassDesc{};
+    pd.xcd_remap = 1;
+    // the largest slab that fits (fewest axes in the outer passes), then the
+    // most balanced cut of the leading block
+    for (int split = hi; split >= 2; --split) {
+        PassDesc t{};
+        t.split = split;
+        t.s_in = g.stride[split - 1];
+        t.s_out = g.N / t.s_in;
+        t.slabs_per_wg = 1;
+        t.tile = 1;
+        t.tile_mid = 1;
+        if (lds_slabs(g, t, esz) > kLdsMax) continue;
+        int best_s1 = 0;
+        double best = 1e300;
+        for (int s1 = 1; s1 < split; ++s1) {
+            t.split_mid = s1;
+            if (lds_columns(g, middle_desc(g, t), esz) > kLdsMax || lds_mid(g, t, esz) > kLdsMax) continue;
+            const double outer = (double)(g.N / g.stride[s1 - 1]);
+            const double mid = (double)(g.stride[s1 - 1] / t.s_in);
+            const double cost = std::fabs(std::log(outer) - std::log(mid));
+            if (cost < best) {
+                best = cost;
+                best_s1 = s1;
+            }
+        }
+        if (best_s1 == 0) continue;
+        pd.split = split;
+        pd.s_in = t.s_in;
+        pd.s_out = t.s_out;
+        pd.split_mid = best_s1;
+        break;
+    }
+    if (pd.split == 0) return IWFPM_ERR_UNSUPPORTED;
+    // widest tiles (<= 16 columns) of which two workgroups fit one CU's LDS
+    const PassDesc q0 = middle_desc(g, pd);
+    int T = 1;
+    for (;;) {
+        pd.tile = 2 * T;
+        if (2 * T > 16 || 2 * T > q0.s_in || lds_columns(g, middle_desc(g, pd), esz) > kLdsMax / 2) break;
+        T *= 2;
+    }
+    pd.tile = T;
+    int Tm = 1;
+    for (;;) {
+        pd.tile_mid = 2 * Tm;
+        if (2 * Tm > 16 || 2 * Tm > pd.s_in || lds_mid(g, pd, esz) > kLdsMax / 2) break;
+        Tm *= 2;
+    }
+    pd.tile_mid = Tm;
+    int G = 1;
+    for (;;) {
+        pd.slabs_per_wg = 2 * G;
+        if (2 * G > 64 || 2 * G > pd.s_out || lds_slabs(g, pd, esz) > kLdsDefault * 5 / 8) break;
+        G *= 2;
+    }
+    pd.slabs_per_wg = G;
+    if (lds_columns(g, middle_desc(g, pd), esz) > kLdsMax || lds_mid(g, pd, esz) > kLdsMax ||
+        lds_slabs(g, pd, esz) > kLdsMax)
+        return IWFPM_ERR_UNSUPPORTED;
+    finalize_mid(p, sc);
+    return IWFPM_OK;
+}
+
 // every feasible schedule for precision prec
 static std::vector<Schedule> schedule_candidates(const iwfpm_plan_s* p, int prec) {
     std::vector<Schedule> out;
@@ -462,6 +567,8 @@ static std::vector<Schedule> schedule_candidates(const iwfpm_plan_s* p, int prec
             }
         }
     }
+    // no three-pass schedule fits: the plan's own schedule with the further pass
+    if (out.empty() && p->sched[prec].ok && p->sched[prec].pd.split_mid > 0) out.push_back(p->sched[prec]);
     return out;
 }
 
@@ -481,6 +588,9 @@ static int prepare_kernels() {
     e = prepare_pass3<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_pass3<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_pass3<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_passm<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_passm<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
+    e = prepare_passm<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_batch<R, 16>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_batch<R, 32>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     e = prepare_batch<R, 64>(b); if (e != hipSuccess) return IWFPM_ERR_DEVICE;
@@ -575,13 +685,26 @@ static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTa
     }
     if (ev) (void)hipEventRecord(ev[1], st);
     if (e != hipSuccess) return e;
+    // with the further pass: its inverse half, the middle pass on the leading
+    // axes, its forward half (timed together as the middle stage)
+    const bool mid = sc.pd.split_mid > 0;
+    auto passm = [&](int sign) {
+        switch (sc.maxs_outer) {
+            case 16: return launch_passm<R, 16>(g, sc.pd, sign, ws, nvec, st);
+            case 32: return launch_passm<R, 32>(g, sc.pd, sign, ws, nvec, st);
+            default: return launch_passm<R, 64>(g, sc.pd, sign, ws, nvec, st);
+        }
+    };
+    if (mid && (e = passm(+1)) != hipSuccess) return e;
+    const PassDesc q = middle_desc(g, sc.pd);
     switch (sc.maxs_outer) {
-        case 16: e = launch_pass2<R, 16>(g, t, sc.pd, ws, nvec, st); break;
-        case 32: e = launch_pass2<R, 32>(g, t, sc.pd, ws, nvec, st); break;
-        default: e = launch_pass2<R, 64>(g, t, sc.pd, ws, nvec, st); break;
+        case 16: e = launch_pass2<R, 16>(g, t, q, ws, nvec, st); break;
+        case 32: e = launch_pass2<R, 32>(g, t, q, ws, nvec, st); break;
+        default: e = launch_pass2<R, 64>(g, t, q, ws, nvec, st); break;
     }
-    if (ev) (void)hipEventRecord(ev[2], st);
     if (e != hipSuccess) return e;
+    if (mid && (e = passm(-1)) != hipSuccess) return e;
+    if (ev) (void)hipEventRecord(ev[2], st);
     switch (sc.maxs_inner) {
         case 16: e = launch_pass3<R, 16>(g, t, sc.pd, psi, ws, hpsi, nvec, st); break;
         case 32: e = launch_pass3<R, 32>(g, t, sc.pd, psi, ws, hpsi, nvec, st); break;
@@ -905,6 +1028,11 @@ int iwfpm_tune(iwfpm_plan_t p, int nvec, int precision, void* stream, double* be
     hipStream_t st = (hipStream_t)stream;
     std::vector<Schedule> cands = schedule_candidates(p, prec);
     if (cands.empty()) return IWFPM_ERR_UNSUPPORTED;
+    if (cands.size() == 1 && !cands[0].fused && cands[0].pd.split_mid > 0) {
+        p->sched[prec] = cands[0];  // the one five-pass schedule: nothing to choose
+        if (best_us) *best_us = -1.0;
+        return IWFPM_OK;
+    }
     const std::string key = tune_key(p, prec, nvec);
     const char* cache = std::getenv("IWFPM_TUNE_CACHE");
     if (cache && cache[0]) {

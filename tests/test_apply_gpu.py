@@ -186,3 +186,15 @@ def test_hermitian_batch_and_deterministic():
         b = torch.vdot(HX[0], X[1]).item()
         vs = float(np.abs(prob.vhat).sum())
         assert abs(a - b) <= 8e-6 * vs * (X[0].norm() * X[1].norm()).item()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_five_pass_grid_sampled(prec):
+    """Ex. 4.3 at the paper's K = 5, L = 20 (40^3 x 10^3 = 64,000,000 points):
+    neither the 1,000-point slabs plus the 64,000-point leading block nor any
+    other single split fits a workgroup's LDS, so the plan runs five passes
+    (a further pass over the third leading axis before and after the middle
+    pass).  Sampled entries against the oracle's row-by-row apply."""
+    prob = W.paper_example_3d(math.pi, 5, 20)
+    print(f"case: ex4.3 K=5 L=20 N={prob.N} {prec} five-pass", flush=True)
+    sampled_check(prob, prec, nvec=1, nsample=200)

@@ -254,3 +254,22 @@ def test_status_paths():
         with pytest.raises(lib.IwfpmError) as e:
             p.eigs(4, precond="learned")
         assert e.value.status == -9
+
+
+def test_table9_eigenvalue_differences():
+    """Table 9 (Ex. 4.3 case I, beta = pi, K = 5; 3D lifted to 6D): the printed
+    errors E_v(10) = 6.82e-04 and E_v(20) = 1.58e-04 against the same E0* fix
+    (E0(10) - E0(20)) / E0(20) = (E_v(10) - E_v(20)) / (1 + E_v(20)) = 5.239e-04
+    (both truncations lie above E0*).  L = 20 is 64,000,000 points (40^3 x
+    10^3), which runs the five-pass schedule; float32 convolution, eta <= 1e-9."""
+    e = {}
+    for L in (10, 20):
+        prob = W.paper_example_3d(math.pi, 5, L)
+        print(f"case: ex4.3 I K=5 L={L} N={prob.N}", flush=True)
+        with lib.Plan.from_problem(prob, precision="fp32") as p:
+            r = p.eigs(1, tol=1e-9, maxit=3000, want_vectors=False)
+            e[L] = float(r.evals[0])
+    rel = (e[10] - e[20]) / e[20]
+    want = (6.82e-4 - 1.58e-4) / (1 + 1.58e-4)
+    # printed to 3 digits: each E_v carries +-0.005 of its last digit
+    assert abs(rel - want) <= 0.005e-4 + 0.005e-4 + 1e-7, (e, rel, want)
