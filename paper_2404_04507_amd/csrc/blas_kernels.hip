@@ -725,13 +725,30 @@ static int grid_for(long long N, int threads, int cap = 4096) {
     return (int)std::max(1LL, std::min<long long>(b, cap));
 }
 
+// Workgroups of a single tall Gram: max_blocks, or more for very tall ones.
+// Each wave's loads in flight shrink with the number of columns (every 4-row
+// group moves 64 bytes per column), so a tall Gram with few columns (tens of
+// millions of rows, a handful of vectors) needs more waves to keep HBM busy:
+// one block per 1024 groups (4096 rows), up to 8192 waves and what the partial
+// buffer (max_blocks x kMaxCols^2 complex entries) holds at `per_block`
+// entries each.  At 589,824 rows this stays at max_blocks, which measured
+// faster there than more, smaller blocks.
+static int gram_single_blocks(int p, int per_block, long long N, int max_blocks, long long* gpb) {
+    const int TP = (p + 15) >> 4;
+    const long long G = (N + 3) >> 2;
+    const long long cap = (long long)max_blocks * kMaxCols * kMaxCols / std::max(1, per_block);
+    const long long tall = std::max<long long>(max_blocks, G / 1024);
+    const int want = (int)std::max<long long>(1, std::min<long long>({cap, 8192LL / TP, tall}));
+    return gram_job_blocks(p, N, want, gpb);
+}
+
 hipError_t gram(const ColPtrs& L, int p, const ColPtrs& R, int q, long long N, double2* partial, int max_blocks,
                 double2* C, hipStream_t st) {
     if (p <= 0 || q <= 0) return hipSuccess;
-    // one wave per 16 columns of L, about 2048 waves in all
+    // one wave per 16 columns of L
     const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4;
     long long gpb;
-    const int nb = gram_job_blocks(p, N, max_blocks, &gpb);
+    const int nb = gram_single_blocks(p, p * q, N, max_blocks, &gpb);
     switch (TQ) {
         case 1: k_gram<1><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
         case 2: k_gram<2><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
@@ -765,7 +782,7 @@ hipError_t gram_pairs(const ColPtrs& L, int p, const ColPtrs& R, int q, long lon
     if (p <= 0 || q <= 0) return hipSuccess;
     const int TP = (p + 15) >> 4, TQ = (q + 15) >> 4;
     long long gpb;
-    const int nb = gram_job_blocks(p, N, max_blocks, &gpb);
+    const int nb = gram_single_blocks(p, 2 * p * q, N, max_blocks, &gpb);
     switch (TQ) {
         case 1: k_gram_pairs<1><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
         case 2: k_gram_pairs<2><<<nb, 64 * TP, 0, st>>>(L, p, R, q, N, gpb, partial); break;
@@ -850,7 +867,7 @@ hipError_t precond(const ColPtrs& R, const ColPtrs& W, int m, const double* M, l
 int gram_job_blocks(int p, long long N, int max_blocks, long long* groups_per_block) {
     const int TP = (p + 15) >> 4;
     const long long G = (N + 3) >> 2;
-    const int want = std::max(1, std::min(max_blocks, (2048 + TP - 1) / TP));
+    const int want = std::max(1, std::min(max_blocks, (8192 + TP - 1) / TP));
     long long gpb = (G + want - 1) / want;
     gpb = std::max<long long>(kGramDepth, ((gpb + kGramDepth - 1) / kGramDepth) * kGramDepth);
     *groups_per_block = gpb;
