@@ -466,9 +466,9 @@ static int choose_mid_schedule(iwfpm_plan_s* p, int prec) {
     PassDesc& pd = sc.pd;
     pd = PassDesc{};
     pd.xcd_remap = 1;
-    // the largest slab that fits (fewest axes in the outer passes), then the
-    // most balanced cut of the leading block
-    for (int split = hi; split >= 2; --split) {
+    // the largest slab that fits (the most axes in passes 1 and 3, which move
+    // whole contiguous slabs), then the most balanced cut of the leading block
+    for (int split = 2; split <= hi; ++split) {
         PassDesc t{};
         t.split = split;
         t.s_in = g.stride[split - 1];
