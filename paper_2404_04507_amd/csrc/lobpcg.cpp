@@ -2094,7 +2094,8 @@ static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts&
     } bguard{bat};
     for (int k = 0; k < 2; ++k) {
         bool ok = true;
-        for (auto* p : pl) ok = ok && p->sched[k].ok;
+        // plans on the five-pass schedule are applied one by one
+        for (auto* p : pl) ok = ok && p->sched[k].ok && (p->sched[k].fused || p->sched[k].pd.split_mid == 0);
         if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
             return rc;
     }
@@ -2702,7 +2703,8 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
     } bguard{bat};
     for (int k = 0; k < 2; ++k) {
         bool ok = true;
-        for (auto* p : pl) ok = ok && p->sched[k].ok;
+        // plans on the five-pass schedule are applied one by one
+        for (auto* p : pl) ok = ok && p->sched[k].ok && (p->sched[k].fused || p->sched[k].pd.split_mid == 0);
         if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
             return rc;
     }
