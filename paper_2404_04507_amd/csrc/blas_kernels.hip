@@ -802,8 +802,11 @@ hipError_t lincomb_pairs(const ColPtrs& A, int p, const ColPtrs& Y, int q, const
     const int nb = (int)std::min<long long>(4096, std::max<long long>(1, (N + 127) / 128));
     const int qg = (q + 3) >> 2;
     const double2* C2 = reinterpret_cast<const double2*>(C);
+    // accumulators sized to the outputs per wave (fewer registers, more waves)
     if (qg <= 2) k_lincomb_pairs<2><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
+    else if (qg <= 3) k_lincomb_pairs<3><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
     else if (qg <= 4) k_lincomb_pairs<4><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
+    else if (qg <= 6) k_lincomb_pairs<6><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
     else k_lincomb_pairs<8><<<nb, 256, 0, st>>>(A, p, Y, q, C2, beta, N);
     return hipGetLastError();
 }
