@@ -931,7 +931,9 @@ hipError_t lincomb_pairs_batched(const LinJob* jobs, int njobs, int total_blocks
     if (maxq > 32) return hipErrorInvalidValue;
     const int qg = (maxq + 3) >> 2;
     if (qg <= 2) k_lincomb_pairs_batched<2><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (qg <= 3) k_lincomb_pairs_batched<3><<<total_blocks, 256, 0, st>>>(jobs, njobs);
     else if (qg <= 4) k_lincomb_pairs_batched<4><<<total_blocks, 256, 0, st>>>(jobs, njobs);
+    else if (qg <= 6) k_lincomb_pairs_batched<6><<<total_blocks, 256, 0, st>>>(jobs, njobs);
     else k_lincomb_pairs_batched<8><<<total_blocks, 256, 0, st>>>(jobs, njobs);
     return hipGetLastError();
 }
