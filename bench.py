@@ -119,8 +119,8 @@ def main():
                     help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported by this build "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -316,7 +316,7 @@ def run_pm_compare(lib, W):
     """The paper's comparison of IWFPM with the projection method (the shear
     switched off, rectangle [-K, K)^d x [-L, L)^(n-d)) at equal eigenvalue
     accuracy: the PM truncation that the paper's error tables pair with
-    IWFPM's, at sizes whose axes fit this build (<= 64 points).  Ground state,
+    IWFPM's, at sizes whose axes the library supports (<= 64 points).  Ground state,
     float64 plans, warm plan, eta <= 1e-13; the eigenvalue errors of these rows
     against a converged reference are checked by the GPU tests."""
     import math

@@ -58,7 +58,7 @@ typedef enum {
     IWFPM_ERR_ARG = -1,            /* bad argument (sizes, NULL pointers, ranges) */
     IWFPM_ERR_SINGULAR_PI = -2,    /* P_I not invertible, or P has rank < d (Def. 2.1) */
     IWFPM_ERR_NONHERMITIAN = -3,   /* potential modes do not describe a real V */
-    IWFPM_ERR_UNSUPPORTED = -4,    /* valid input outside what this build implements */
+    IWFPM_ERR_UNSUPPORTED = -4,    /* valid input outside what this library implements */
     IWFPM_ERR_ALLOC = -5,          /* device or host allocation failed */
     IWFPM_ERR_DEVICE = -6,         /* a HIP call failed */
     IWFPM_ERR_NUMERIC = -7,        /* NaN/Inf or a breakdown the solver could not recover */

@@ -785,7 +785,7 @@ const char* iwfpm_status_string(int s) {
         case IWFPM_ERR_ARG: return "invalid argument";
         case IWFPM_ERR_SINGULAR_PI: return "P_I is singular";
         case IWFPM_ERR_NONHERMITIAN: return "potential modes do not describe a real potential";
-        case IWFPM_ERR_UNSUPPORTED: return "unsupported by this build";
+        case IWFPM_ERR_UNSUPPORTED: return "unsupported by this library";
         case IWFPM_ERR_ALLOC: return "allocation failed";
         case IWFPM_ERR_DEVICE: return "HIP error";
         case IWFPM_ERR_NUMERIC: return "numerical breakdown";

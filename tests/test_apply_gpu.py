@@ -4,7 +4,7 @@ Small grids: every entry against the oracle's sparse H~.  Full workload sizes:
 sampled entries against the oracle's one-by-one row evaluation, plus
 properties that hold at any size (Hermiticity, batch = single, determinism).
 
-Tolerances (derived in the design doc from the arithmetic):
+Tolerances (derived from the arithmetic):
   float64 convolution   ||y - y_ref||_2 <= 1e-13 (max Lambda + sum|Vhat|) ||x||_2
   float32 convolution   ||y - y_ref||_2 <= 4e-6  sum|Vhat| ||x||_2  (Lambda psi stays float64)
 """

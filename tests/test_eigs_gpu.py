@@ -177,7 +177,7 @@ def _golden(name):
 @pytest.mark.parametrize("L,printed", [(20, 5.64e-08)])
 def test_table2_on_gpu(L, printed):
     """Table 2 end to end on the GPU: IWFPM K = 5 reaches the printed E_v.
-    (The L = 40 row needs a 2L = 80-point axis, above this build's 64-point
+    (The L = 40 row needs a 2L = 80-point axis, above the library's 64-point
     limit; iwfpm_plan refuses it, see tests/test_host_plan.py, and the row is
     pinned on the oracle in tests/test_oracle_pins.py.)"""
     e0s = _golden("ex1_reference.json")["E0"]
