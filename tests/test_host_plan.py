@@ -223,3 +223,21 @@ def test_eigenfunction_argument_checks_on_host_plan():
         assert L.iwfpm_eigenfunction(p._h, None, o, h, n, fake, None) == -1
         assert L.iwfpm_eigenfunction(p._h, fake, o, h, None, fake, None) == -1
         assert L.iwfpm_eigenfunction(p._h, fake, o, h, n, fake, None) == -10
+
+
+def test_five_pass_grids_plan_on_host():
+    """Ex. 4.3 at K = 5, L = 20 and 30 (40^3 x 10^3 and 60^3 x 10^3): no single
+    split fits both the slab and the leading block in LDS, and the plan takes
+    the five-pass schedule instead of refusing (passes 1 and 3 keep the three
+    10-point axes); at L = 40 the 80-point axes are still refused."""
+    import math
+    for L in (20, 30):
+        prob = W.paper_example_3d(math.pi, 5, L)
+        with lib.Plan.from_problem(prob, device=-1) as p:
+            assert p.N == 1000 * (2 * L) ** 3
+            for prec in ("fp32", "fp64"):
+                sc = p.schedule(prec)
+                assert not sc["fused"] and sc["split"] == 3, sc
+    with pytest.raises(lib.IwfpmError) as e:
+        lib.Plan.from_problem(W.paper_example_3d(math.pi, 5, 40), device=-1)
+    assert e.value.status == -4
