@@ -683,20 +683,43 @@ __device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd,
     const int El = g.ext[b - 1];
     const RowGeom rg{El << lgT, (El + 1) << lgT};
     const int count = mid << lgT;
-    // element e = row * (El T) + col: index within [a, b) = row El + col / T, column col % T
-    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
-        cplx<R> v[kBatch];
-        RowIter j = it;
+    // element e = row * (El T) + col: index within [a, b) = row El + col / T,
+    // column col % T; an even, whole tile moves adjacent column pairs as one
+    // access (as in the middle pass)
+    const bool pairs = (T & 1) == 0 && tw == T;
+    if (pairs) {
+        const int count2 = count >> 1;
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < count2;) {
+            CPair<R> v[kBatch];
+            RowIter j = it;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const int q = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
-            v[u] = (j.e < count && tt < tw) ? w[q * cols + tt] : cplx<R>{R(0), R(0)};
-            j.next(blockDim.x);
+            for (int u = 0; u < kBatch; ++u) {
+                const int col = 2 * j.col;
+                const int q = j.row * El + (col >> lgT), tt = col & (T - 1);
+                v[u] = j.e < count2 ? *reinterpret_cast<const CPair<R>*>(w + q * cols + tt) : CPair<R>{};
+                j.next(blockDim.x);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count2) *reinterpret_cast<CPair<R>*>(tile + it.row * rg.sp + 2 * it.col) = v[u];
+                it.next(blockDim.x);
+            }
         }
+    } else {
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count;) {
+            cplx<R> v[kBatch];
+            RowIter j = it;
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
-            it.next(blockDim.x);
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = j.row * El + (j.col >> lgT), tt = j.col & (T - 1);
+                v[u] = (j.e < count && tt < tw) ? w[q * cols + tt] : cplx<R>{R(0), R(0)};
+                j.next(blockDim.x);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (it.e < count) tile[it.row * rg.sp + it.col] = v[u];
+                it.next(blockDim.x);
+            }
         }
     }
     __syncthreads();
@@ -705,9 +728,18 @@ __device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd,
         run_axis<SIGN, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
-        const int q = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
-        if (tt < tw) w[q * cols + tt] = tile[it.row * rg.sp + it.col];
+    if (pairs) {
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < (count >> 1); it.next(blockDim.x)) {
+            const int col = 2 * it.col;
+            const int q = it.row * El + (col >> lgT), tt = col & (T - 1);
+            *reinterpret_cast<CPair<R>*>(w + q * cols + tt) =
+                *reinterpret_cast<const CPair<R>*>(tile + it.row * rg.sp + col);
+        }
+    } else {
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
+            const int q = it.row * El + (it.col >> lgT), tt = it.col & (T - 1);
+            if (tt < tw) w[q * cols + tt] = tile[it.row * rg.sp + it.col];
+        }
     }
 }
 

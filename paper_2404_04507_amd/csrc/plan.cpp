@@ -498,19 +498,21 @@ static int choose_mid_schedule(iwfpm_plan_s* p, int prec) {
         break;
     }
     if (pd.split == 0) return IWFPM_ERR_UNSUPPORTED;
-    // widest tiles (<= 16 columns) of which two workgroups fit one CU's LDS
+    // widest tiles (<= 64 columns) of which two workgroups fit one CU's LDS:
+    // a short block (one 40-point axis) needs many columns to give every lane
+    // of a wave a pencil
     const PassDesc q0 = middle_desc(g, pd);
     int T = 1;
     for (;;) {
         pd.tile = 2 * T;
-        if (2 * T > 16 || 2 * T > q0.s_in || lds_columns(g, middle_desc(g, pd), esz) > kLdsMax / 2) break;
+        if (2 * T > 64 || 2 * T > q0.s_in || lds_columns(g, middle_desc(g, pd), esz) > kLdsMax / 2) break;
         T *= 2;
     }
     pd.tile = T;
     int Tm = 1;
     for (;;) {
         pd.tile_mid = 2 * Tm;
-        if (2 * Tm > 16 || 2 * Tm > pd.s_in || lds_mid(g, pd, esz) > kLdsMax / 2) break;
+        if (2 * Tm > 64 || 2 * Tm > pd.s_in || lds_mid(g, pd, esz) > kLdsMax / 2) break;
         Tm *= 2;
     }
     pd.tile_mid = Tm;
