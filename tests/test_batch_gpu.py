@@ -178,3 +178,24 @@ def test_eigs_batched_sweep_workload_subset():
         assert np.all(O.backward_error(H, X, r.evals, hn) <= 1e-7)
     for p in plans:
         p.close()
+
+
+def test_eigs_batched_five_pass_plans():
+    """Plans on the five-pass schedule (Ex. 4.3 at K = 4, L = 20: 40^3 x 8^3 =
+    32,768,000 points, whose slabs and leading block both exceed a workgroup's
+    LDS) are applied one by one inside the lock-step solver; the batched
+    ground states equal single-plan solves (float32 convolution, eta <= 1e-9)."""
+    import math
+    probs = [W.paper_example_3d(math.pi, 4, 20), W.paper_example_3d(0.5 * math.pi, 4, 20)]
+    print(f"case: ex4.3 K=4 L=20 N={probs[0].N} x 2, batched five-pass", flush=True)
+    plans = [lib.Plan.from_problem(p, precision="fp32") for p in probs]
+    try:
+        assert all(not p.schedule("fp32")["fused"] and p.schedule("fp32")["split"] == 3 for p in plans)
+        ev, eta, stats, st = lib.eigs_batched(plans, 1, tol=1e-9, maxit=2000)
+        assert st == 0 and np.all(eta <= 1e-9)
+        for i, p in enumerate(plans):
+            r = p.eigs(1, tol=1e-9, maxit=2000, want_vectors=False)
+            assert abs(ev[i, 0] - r.evals[0]) <= 1e-8 * abs(r.evals[0]), (i, ev[i, 0], r.evals[0])
+    finally:
+        for p in plans:
+            p.close()
