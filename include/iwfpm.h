@@ -106,8 +106,10 @@ const char* iwfpm_status_string(int status);
  * transforms the axes between the two groups before and after the middle
  * one.  Host inputs (P, K, L, modes, vhat) are copied; the caller may free
  * them on return.  opts may be NULL (defaults).  Blocking.
- * Errors: ERR_ARG (d < 1, n <= d, n > 8, K/L < 1, grid extent unsupported),
- * ERR_SINGULAR_PI, ERR_NONHERMITIAN, ERR_DEVICE / ERR_ALLOC.
+ * Errors: ERR_ARG (d < 1, n <= d, n > 8, K/L < 1, non-finite P or vhat),
+ * ERR_UNSUPPORTED (a grid extent 2K_j or 2L_j the library has no transform
+ * for, or more than 2^31 - 1 grid points), ERR_SINGULAR_PI, ERR_NONHERMITIAN,
+ * ERR_DEVICE / ERR_ALLOC.
  */
 int iwfpm_plan(int d, int n, const double* P, const int32_t* K, const int32_t* L,
                int n_modes, const int32_t* modes, const double* vhat,

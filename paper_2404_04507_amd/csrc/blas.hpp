@@ -8,6 +8,9 @@
 namespace iwfpm {
 
 constexpr int kMaxCols = 64;
+// double2 entries of the coefficient array the batched real-pair combination
+// stages in LDS (2 p q of them for p input and q output columns)
+constexpr int kLinPairsLds = kMaxCols * 32;
 
 // up to kMaxCols column pointers, passed by value as a kernel argument
 struct ColPtrs {

@@ -680,9 +680,10 @@ __global__ void __launch_bounds__(256) k_gram_batched_pairs(const GramJob* __res
 
 template <int QG>
 __global__ void __launch_bounds__(256) k_lincomb_pairs_batched(const LinJob* __restrict__ jobs, int njobs) {
-    __shared__ double2 sC[kMaxCols * 32];
+    __shared__ double2 sC[kLinPairsLds];
     const int j = find_job(jobs, njobs, blockIdx.x);
     const LinJob& jb = jobs[j];
+    // the host rejects jobs with 2 p q > kLinPairsLds
     for (int e = threadIdx.x; e < 2 * jb.p * jb.q; e += blockDim.x) sC[e] = jb.C[e];
     __syncthreads();
     lincomb_rows_body<QG, true>(jb.A, jb.p, jb.Y, jb.q, sC, jb.beta, jb.N, blockIdx.x - jb.start, jb.nb);

@@ -140,7 +140,11 @@ static inline double pyth(double f, double g) {
 
 // Hermitian eigen-decomposition A = V diag(w) V^H (w ascending) by Householder
 // reduction to a real symmetric tridiagonal matrix followed by the implicit QL
-// iteration with Wilkinson shifts; false if QL does not converge.
+// iteration with Wilkinson shifts; false if QL does not converge.  The QL
+// sweep is the published tql2 procedure of Bowdler, Martin, Reinsch and
+// Wilkinson (Numer. Math. 11, 1968; Handbook for Automatic Computation
+// vol. II, contribution II/3; EISPACK's TQL2), with its usual roles of the
+// shift g, the rotation pair (c, s) and the running values p, r, b.
 static bool householder_ql(std::vector<cd> A, int n, std::vector<double>& w, std::vector<cd>& V) {
     // Q = H_0 H_1 ... accumulates the reflectors (column-major, column loops innermost)
     std::vector<cd> Q((size_t)n * n, 0.0);
@@ -2618,6 +2622,9 @@ static int batch_lincomb_real(BatchOps& bo, const std::vector<LinReqR>& reqs) {
         jb.p = (int)Ap.back().cols.size();
         jb.q = (int)Yp.back().cols.size();
         if (jb.p > kMaxCols || jb.q > 32) return IWFPM_ERR_ARG;
+        // the kernel stages the 2p x q coefficient pairs in an LDS array of
+        // kLinPairsLds double2 entries
+        if (2 * jb.p * jb.q > kLinPairsLds) return IWFPM_ERR_ARG;
         for (int i = 0; i < jb.p; ++i) jb.A.p[i] = Ap.back().cols[i];
         for (int j = 0; j < jb.q; ++j) jb.Y.p[j] = Yp.back().cols[j];
         jb.beta = r.beta;

@@ -366,3 +366,108 @@ def test_eigenfunction_grid_is_separable_product():
             x = np.array([origin[0] + step[0] * i, origin[1] + step[1] * j])
             ref = sum(U[t] * np.exp(2j * math.pi * f[t] @ x) for t in range(len(U)))
             assert abs(u[i, j] - ref) <= 1e-12 * np.abs(U).sum()
+
+
+# --- the stopping criterion: backward error and the norm bound ---------------
+#
+# The convergence test of Sec. 4.1 ("convergence error") is read as the
+# backward error eta = ||H x - theta x|| / ((||H||_est + |theta|) ||x||) with
+# ||H||_est = max Lambda + sum |Vhat_m|.  These pins fix both functions by
+# facts that do not depend on how the oracle writes them: the spectral norm of
+# the dense H~ (LAPACK), equality cases of the bound, and the closed form of
+# the residual of a mixture of two exact eigenvectors.
+
+def _dense(prob, variant="exact"):
+    return O.hamiltonian_dense(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, variant)
+
+
+def _bound(prob, variant="exact"):
+    return O.norm_bound(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, variant)
+
+
+def _with_potential(prob, modes, vhat):
+    return W.Problem(prob.name, prob.d, prob.P, prob.K, prob.L, np.asarray(modes), np.asarray(vhat))
+
+
+@pytest.mark.parametrize("make", [lambda: W.c1_1d(lam=1.0), lambda: W.c1_1d(lam=40.0),
+                                  lambda: W.c2_2d(lam=0.5, K=3, L=4), lambda: W.c2_2d(lam=5.0, K=3, L=4),
+                                  lambda: W.c3_3d(K=2, L=2)])
+def test_norm_bound_bounds_the_spectral_norm(make):
+    """norm_bound >= ||H~||_2 = max |eigenvalue| of the dense Hermitian H~."""
+    prob = make()
+    H = _dense(prob)
+    w = np.linalg.eigvalsh(H)
+    assert _bound(prob) >= np.max(np.abs(w)) * (1 - 1e-14)
+
+
+@pytest.mark.parametrize("make", [lambda: W.c1_1d(), lambda: W.c2_2d(K=3, L=4), lambda: W.c3_3d(K=2, L=2)])
+def test_norm_bound_is_attained_without_modes_and_with_a_constant(make):
+    """Equality cases: with no potential H~ = diag(Lambda), so ||H~||_2 = max Lambda
+    (Lambda >= 0); with a positive constant c only, H~ = diag(Lambda) + c I and
+    ||H~||_2 = max Lambda + c.  A bound with a missing 2 pi, a missing 1/2 or a
+    dropped potential term differs from these."""
+    prob = make()
+    n = prob.d + len(prob.L)
+    free = _with_potential(prob, np.zeros((0, n), dtype=np.int64), np.zeros(0))
+    w = np.linalg.eigvalsh(_dense(free))
+    assert abs(_bound(free) - np.max(np.abs(w))) <= 1e-12 * np.max(np.abs(w))
+    const = _with_potential(prob, np.zeros((1, n), dtype=np.int64), np.array([2.75]))
+    w = np.linalg.eigvalsh(_dense(const))
+    assert abs(_bound(const) - np.max(np.abs(w))) <= 1e-12 * np.max(np.abs(w))
+
+
+def test_norm_bound_sums_every_mode():
+    """With a strong cosine potential the norm exceeds max Lambda plus the largest
+    single coefficient (the delta function at y = 0 on the grid, a flat
+    coefficient vector, has Rayleigh quotient mean(Lambda) + V(0) and
+    V(0) = sum Vhat_m), so only a bound that sums all |Vhat_m| holds."""
+    prob = W.c2_2d(lam=400.0, K=3, L=4)
+    H = _dense(prob)
+    nrm = np.max(np.abs(np.linalg.eigvalsh(H)))
+    lam = O.kinetic(prob.P, O.grid_labels(prob.P, prob.d, prob.K, prob.L))
+    assert nrm > lam.max() + np.max(np.abs(prob.vhat))
+    assert _bound(prob) >= nrm
+    flat = np.ones(prob.N) / math.sqrt(prob.N)
+    assert np.real(flat @ H @ flat) == pytest.approx(lam.mean() + np.sum(prob.vhat).real, rel=1e-12)
+
+
+@pytest.mark.parametrize("make", [lambda: W.c1_1d(lam=1.0), lambda: W.c2_2d(lam=5.0, K=3, L=4)])
+def test_backward_error_of_lapack_pairs_is_rounding(make):
+    """Exact eigenpairs (LAPACK on the dense H~) have backward error at the
+    rounding level, for every returned column."""
+    prob = make()
+    H = _dense(prob)
+    w, V = np.linalg.eigh(H)
+    eta = O.backward_error(H, V[:, :12], w[:12], _bound(prob))
+    assert eta.shape == (12,)
+    assert np.all(eta <= 1e-14), eta
+
+
+def test_backward_error_closed_form_for_two_eigenvector_mixture():
+    """x = v_i + delta v_j (orthonormal exact eigenvectors, eigenvalues a, b),
+    theta = Rayleigh quotient = (a + delta^2 b) / (1 + delta^2):
+    H x - theta x = (a - theta) v_i + delta (b - theta) v_j, whose norm is
+    delta |b - a| / sqrt(1 + delta^2), and ||x|| = sqrt(1 + delta^2), so
+    eta = delta |b - a| / ((||H||_est + |theta|) (1 + delta^2)).
+    The potential carries a large constant so that |theta| is a sizeable part
+    of the denominator; columns have different delta and pairs so that a norm
+    taken over the wrong axis or a dropped |theta| fails."""
+    base = W.c2_2d(lam=2.0, K=3, L=4)
+    n = base.d + len(base.L)
+    modes = np.concatenate([base.modes, np.zeros((1, n), dtype=np.int64)])
+    vhat = np.concatenate([base.vhat, [30.0]])
+    prob = _with_potential(base, modes, vhat)
+    H = _dense(prob)
+    w, V = np.linalg.eigh(H)
+    hn = _bound(prob)
+    cases = [(0, 5, 1e-3), (1, 40, 0.3), (3, 200, 2.0), (7, 7 + 300, 1e-6)]
+    X = np.stack([V[:, i] + dl * V[:, j] for i, j, dl in cases], axis=1)
+    theta = np.array([(w[i] + dl * dl * w[j]) / (1 + dl * dl) for i, j, dl in cases])
+    want = np.array([dl * abs(w[j] - w[i]) / ((hn + abs(th)) * (1 + dl * dl))
+                     for (i, j, dl), th in zip(cases, theta)])
+    got = O.backward_error(H, X, theta, hn)
+    assert np.allclose(got, want, rtol=1e-9, atol=0), (got, want)
+    # the |theta| term matters at this size: leaving it out changes eta by > 1 %
+    assert np.all(np.abs(theta) > 0.05 * hn)
+    # scaling x does not change eta
+    assert np.allclose(O.backward_error(H, 3.5 * X, theta, hn), want, rtol=1e-9, atol=0)
