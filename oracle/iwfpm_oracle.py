@@ -267,6 +267,31 @@ def apply_points(P, d, K, L, modes, vhat, psi, positions, variant="exact") -> np
     return out
 
 
+def apply_shifts(P, d, K, L, modes, vhat, psi, variant="exact") -> np.ndarray:
+    """H psi for a block of columns psi (N x m, grid order) without forming H:
+    Lambda psi plus the wrapped convolution written as cyclic shifts of the
+    grid array, (C psi)[k*] = sum_m Vhat_m psi[(k* - m) mod ext] (Sec. 4.1;
+    the aliasing identity of Appendix C).  One column at a time, so memory
+    stays at a few copies of one vector even on the 16^6 grid."""
+    n = len(K) + len(L)
+    modes, vhat = check_modes(modes, vhat, n)
+    d_, nd = len(K), len(L)
+    shape = grid_extents(K, L)
+    lam = kinetic(P, grid_labels(P, d, K, L, variant))
+    psi = np.asarray(psi, dtype=np.complex128)
+    cols = psi.reshape(psi.shape[0], -1)
+    out = np.empty_like(cols)
+    # paper index j of a mode -> axis of the grid array (k_II axes first)
+    axis = [nd + j if j < d_ else j - d_ for j in range(n)]
+    for c in range(cols.shape[1]):
+        x = cols[:, c].reshape(shape)
+        y = lam.reshape(shape) * x
+        for m, v in zip(modes, vhat):
+            y = y + v * np.roll(x, shift=tuple(int(t) for t in m), axis=tuple(axis))
+        out[:, c] = y.reshape(-1)
+    return out.reshape(psi.shape)
+
+
 # ---------------------------------------------------------------------------
 # Sec. 3.3: the same operator through explicit DFT matrices (F = T F*)
 # ---------------------------------------------------------------------------
@@ -310,6 +335,42 @@ def hamiltonian_via_dft(P, d, K, L, modes, vhat, variant="exact") -> np.ndarray:
     Finv, F = dft_matrices(P, d, K, L, variant)
     V = potential_on_grid(K, L, modes, vhat)
     return np.diag(lam).astype(np.complex128) + F @ (V[:, None] * Finv)
+
+
+def fft_apply_setup(P, d, K, L, modes, vhat, variant="exact"):
+    """Alg. 1's set-up for the host FFT route: the kinetic diagonal with the
+    true labels and the potential on G_{K,L}.  Returns (grid shape, Lambda,
+    V on the grid)."""
+    shape = grid_extents(K, L)
+    lam = kinetic(P, grid_labels(P, d, K, L, variant))
+    V = potential_on_grid(K, L, modes, vhat).reshape(shape)
+    return shape, lam, V
+
+
+def apply_fft_prepared(setup, psi, workers: int = 1) -> np.ndarray:
+    """H psi by Alg. 1's route on the host: the coefficients (grid order, i.e.
+    already relabelled by T) go to grid values by the inverse DFT, are
+    multiplied by V(y_l), and return by the forward DFT; the kinetic diagonal
+    is added with the true labels (Sec. 3.3 and Sec. 4.1, eq:F).  With
+    numpy's conventions ifftn carries the 1/N and fftn none, and
+    u(y_l) = N ifftn(psi), so the potential block is fftn(V * ifftn(psi)).
+    ``workers`` is passed to scipy.fft (threads over the batch of columns)."""
+    import scipy.fft as sfft
+    shape, lam, V = setup
+    psi = np.asarray(psi, dtype=np.complex128)
+    cols = psi.reshape(psi.shape[0], -1)
+    m = cols.shape[1]
+    axes = tuple(range(1, len(shape) + 1))
+    g = cols.T.reshape((m,) + shape)
+    u = sfft.ifftn(g, axes=axes, workers=workers)
+    u *= V[None]
+    c = sfft.fftn(u, axes=axes, workers=workers).reshape(m, -1).T
+    return (lam[:, None] * cols + c).reshape(psi.shape)
+
+
+def apply_fft(P, d, K, L, modes, vhat, psi, variant="exact", workers: int = 1) -> np.ndarray:
+    """H psi by the host FFT route (set-up and apply, see apply_fft_prepared)."""
+    return apply_fft_prepared(fft_apply_setup(P, d, K, L, modes, vhat, variant), psi, workers)
 
 
 def discrete_inner_product(K, L, U_vals, V_vals) -> complex:

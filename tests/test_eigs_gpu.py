@@ -242,6 +242,75 @@ def test_full_2d_lifted_4d_fp32(lam):
         assert np.all(np.abs(r.evals - ref) <= 1e-5 * np.maximum(1.0, np.abs(ref))), r.evals - ref
 
 
+class _ShiftOperator:
+    """The oracle's H~ in its cyclic-shift form, usable as ``H @ X``."""
+
+    def __init__(self, prob, window="exact"):
+        self.prob, self.window = prob, window
+
+    def __matmul__(self, X):
+        p = self.prob
+        return O.apply_shifts(p.P, p.d, p.K, p.L, p.modes, p.vhat, X, self.window)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_reduced_window_matches_dense(prec):
+    """3D QSE lifted to 6D (P = [I3 | Q], lam = 3) on the reduced window
+    K = L = 2 (4^6 = 4,096 points): the 16 lowest pairs against dense LAPACK
+    on the oracle's H~, 1e-10 (float64) / 1e-5 (float32 convolution)."""
+    prob = W.c3_3d(K=2, L=2)
+    print(f"case: 3d_lifted_6d K=L=2 16 pairs {prec}", flush=True)
+    with lib.Plan.from_problem(prob, precision=prec) as p:
+        r = p.eigs(16, tol=1e-10, maxit=800)
+    ref = dense_ref(prob, 16)
+    bar = 1e-10 if prec == "fp64" else 1e-5
+    assert np.all(np.abs(r.evals - ref) <= bar * np.maximum(1.0, np.abs(ref))), (r.evals - ref)
+    check_pairs_with_oracle(prob, r, 16, 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c3_three_pass_window_matches_stored_oracle(prec):
+    """The same problem on K = L = 3 (6^6 = 46,656 points: the three-pass
+    schedule over six axes) against the oracle's stored eigenvalues (ARPACK on
+    the sparse H~, cross-checked by the oracle's LOBPCG to 4e-13)."""
+    ref = np.array(_golden("c3_small_eigs.json")["evals"][:16])
+    prob = W.c3_3d(K=3, L=3)
+    print(f"case: 3d_lifted_6d K=L=3 16 pairs {prec}", flush=True)
+    with lib.Plan.from_problem(prob, precision=prec) as p:
+        assert p.schedule(prec)["fused"] is False
+        r = p.eigs(16, tol=1e-10, maxit=1500)
+    bar = 1e-10 if prec == "fp64" else 1e-5
+    assert np.all(np.abs(r.evals - ref) <= bar * np.maximum(1.0, np.abs(ref))), (r.evals - ref)
+    check_pairs_with_oracle(prob, r, 16, 1e-10)
+
+
+@pytest.mark.timeout(900)
+def test_full_3d_lifted_6d_fp32():
+    """The 3D/6D workload at full size (16^6 = 16,777,216 points, lam = 3): 16
+    pairs at eta <= 1e-8 with float32 convolution.  Every returned pair is
+    checked on the CPU with the oracle's H~ in its cyclic-shift form:
+    backward error, Rayleigh quotient against the returned eigenvalue, and
+    orthonormality of the returned block."""
+    prob = W.c3_3d()
+    print(f"case: 3d_lifted_6d full N={prob.N} fp32", flush=True)
+    with lib.Plan.from_problem(prob, precision="fp32") as p:
+        r = p.eigs(16, tol=1e-8, maxit=1000)
+        print("iterations", r.iterations, "matvecs", r.matvecs, "polished", r.polished, flush=True)
+        X = r.evecs.cpu().numpy().T  # N x 16, grid order
+    assert r.converged == 16 and np.all(r.eta <= 1e-8)
+    H = _ShiftOperator(prob)
+    HX = H @ X
+    hn = O.norm_bound(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat)
+    nx = np.linalg.norm(X, axis=0)
+    eta = np.linalg.norm(HX - X * r.evals[None, :], axis=0) / ((hn + np.abs(r.evals)) * nx)
+    print("oracle eta", eta, flush=True)
+    assert np.all(eta <= 1e-7), eta
+    rq = np.real(np.sum(X.conj() * HX, axis=0)) / nx ** 2
+    assert np.allclose(rq, r.evals, rtol=0, atol=1e-9 * max(1.0, np.abs(r.evals).max())), rq - r.evals
+    G = X.conj().T @ X
+    assert np.allclose(G, np.eye(16), atol=1e-10)
+
+
 def test_status_paths():
     prob = W.c1_1d()
     print("case: eigs status paths", flush=True)

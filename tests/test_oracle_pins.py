@@ -471,3 +471,37 @@ def test_backward_error_closed_form_for_two_eigenvector_mixture():
     assert np.all(np.abs(theta) > 0.05 * hn)
     # scaling x does not change eta
     assert np.allclose(O.backward_error(H, 3.5 * X, theta, hn), want, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("make", [lambda: W.c1_1d(lam=1.0), lambda: W.c2_2d(lam=5.0, K=2, L=2),
+                                  lambda: W.c3_3d(lam=3.0, K=1, L=1),
+                                  lambda: W.paper_example_2d(0.8 * math.pi, 0.2 * math.pi, 3, 4),
+                                  lambda: _complex_potential_problem()])
+def test_shift_form_apply_equals_dft_construction(make):
+    """The cyclic-shift form of H psi (used for residual checks on grids far too
+    large for a matrix) and the host FFT route (scipy.fft, the paper's Alg. 1
+    design) equal Lambda + F diag(V) F^{-1} built from dense DFT matrices with
+    the true labels (Sec. 4.1, eq:F), column by column."""
+    prob = make()
+    H = O.hamiltonian_via_dft(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat)
+    X = W.random_block(prob.N, 3, seed=11)
+    Y = O.apply_shifts(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, X)
+    assert np.linalg.norm(Y - H @ X) <= 1e-12 * np.linalg.norm(H @ X)
+    # the host FFT route of Alg. 1 (the paper's own design) gives the same
+    Z = O.apply_fft(prob.P, prob.d, prob.K, prob.L, prob.modes, prob.vhat, X, workers=2)
+    assert np.linalg.norm(Z - H @ X) <= 1e-12 * np.linalg.norm(H @ X)
+
+
+def _complex_potential_problem():
+    """A 2D/4D window with complex conjugate-pair coefficients on oblique modes,
+    so that the direction of every shift matters (V_m != V_{-m})."""
+    rng = np.random.default_rng(7)
+    modes, vhat = [[0, 0, 0, 0]], [0.7]
+    for _ in range(4):
+        m = rng.integers(-2, 3, size=4)
+        if not m.any():
+            continue
+        c = complex(rng.standard_normal(), rng.standard_normal())
+        modes += [list(m), list(-m)]
+        vhat += [c, c.conjugate()]
+    return W.Problem("complex", 2, W.rot_pair_P(), [2, 3], [2, 2], np.array(modes), np.array(vhat))
