@@ -149,6 +149,7 @@ int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* 
 int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
                      int precision, void* stream);
 
+
 /* The potential block alone, out = F V F^{-1} psi (Sec. 4.1), same arguments
  * as iwfpm_apply_prec (used by the learned preconditioner's convolution
  * layers). */
@@ -205,7 +206,8 @@ int iwfpm_batch_destroy(iwfpm_batch_t batch);
 /*
  * iwfpm_tune - autotuner: times every feasible apply schedule of the plan on
  * its device (fused, or three-pass over every axis split x middle-pass tile
- * width x slabs per workgroup; a grid that only the five-pass schedule fits
+ * width x slabs per workgroup x middle-pass workgroup size (256, 512 or
+ * 1024 threads); a grid that only the five-pass schedule fits
  * keeps it untimed, best_us = -1) on nvec scratch vectors with HIP events on
  * `stream`, and keeps the fastest for `precision` (IWFPM_PREC_*, or -1 for the
  * plan's).  With the environment variable IWFPM_TUNE_CACHE naming a file,
@@ -213,8 +215,9 @@ int iwfpm_batch_destroy(iwfpm_batch_t batch);
  * extents) are reused and new ones appended (one line per key).  best_us
  * (may be NULL) receives the best time per apply in microseconds, or -1 when
  * the cache answered.  Allocates 2 x nvec vectors of scratch; blocking.
- * iwfpm_schedule - the current schedule for `precision`: out[4] = {fused,
- * split, tile, slabs per workgroup}.
+ * iwfpm_schedule - the current schedule for `precision`: out[5] = {fused,
+ * split, tile, slabs per workgroup, threads of the middle pass's workgroups
+ * (of the fused kernel's when fused)}.
  * Errors: ERR_ARG, ERR_NODEVICE, ERR_UNSUPPORTED, ERR_ALLOC, ERR_DEVICE.
  */
 int iwfpm_tune(iwfpm_plan_t plan, int nvec, int precision, void* stream, double* best_us);

@@ -567,10 +567,11 @@ class Plan:
         return best.value
 
     def schedule(self, precision=None) -> dict:
-        out = np.zeros(4, dtype=np.int32)
+        out = np.zeros(5, dtype=np.int32)
         prec = -1 if precision is None else PREC[precision]
         _check(_lib().iwfpm_schedule(self._h, prec, _ptr(out, ctypes.c_int32)), "iwfpm_schedule")
-        return {"fused": bool(out[0]), "split": int(out[1]), "tile": int(out[2]), "slabs_per_wg": int(out[3])}
+        return {"fused": bool(out[0]), "split": int(out[1]), "tile": int(out[2]), "slabs_per_wg": int(out[3]),
+                "threads": int(out[4])}
 
     def profile(self, enable: bool):
         _check(_lib().iwfpm_profile(self._h, int(bool(enable))), "iwfpm_profile")

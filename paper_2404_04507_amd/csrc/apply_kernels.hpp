@@ -128,6 +128,112 @@ __device__ __forceinline__ void run_axis(cplx<R>* lds, int S, int npencil, int e
 }
 
 // ---------------------------------------------------------------------------
+// long axes: S = f_0 f_1 ... f_{m-1} points, more than one register pencil
+// ---------------------------------------------------------------------------
+//
+// The inverse DFT of length S runs in m in-place stages over the LDS tile.
+// Stage i works on blocks of B_i = f_i ... f_{m-1} consecutive points (block
+// b at offset b B_i); within a block it takes the f_i points at stride
+// s_i = B_i / f_i starting at r < s_i, applies an f_i-point DFT, multiplies
+// output k by e^{2 pi i r k / B_i} (not in the last stage, where s_i = 1) and
+// writes the results back to the same positions.  This is the decimation in
+// frequency of the DFT into its factors: afterwards position
+// p = p_0 s_0 + p_1 s_1 + ... + p_{m-1} holds the transform at
+// l = p_0 + f_0 (p_1 + f_1 (p_2 + ...)), the digit-reversed order of p.
+// The forward DFT is the adjoint of the inverse one: the same stages in
+// reverse order, each with the conjugate twiddles applied before an f_i-point
+// DFT of the opposite sign, which returns natural order.  Between the two the
+// axis stays in digit order; only the potential, which is indexed by l, has
+// to know (unperm_pos).
+
+template <typename R>
+__device__ __forceinline__ const cplx<R>* tw_of(const DevTabs& t, const DevGeom& g, int ax);
+template <>
+__device__ __forceinline__ const cplx<float>* tw_of<float>(const DevTabs& t, const DevGeom& g, int ax) {
+    return reinterpret_cast<const cplx<float>*>(t.tw32) + g.twoff[ax];
+}
+template <>
+__device__ __forceinline__ const cplx<double>* tw_of<double>(const DevTabs& t, const DevGeom& g, int ax) {
+    return reinterpret_cast<const cplx<double>*>(t.tw64) + g.twoff[ax];
+}
+
+// digit order -> natural order along a long axis (position c -> index l)
+__device__ __forceinline__ int long_axis_perm(const DevGeom& g, int ax, int c) {
+    int l = 0, mult = 1, B = g.ext[ax];
+    for (int i = 0; i < g.nfac[ax]; ++i) {
+        const int f = g.fac[ax][i];
+        const int st = B / f;
+        const int k = c / st;
+        c -= k * st;
+        l += mult * k;
+        mult *= f;
+        B = st;
+    }
+    return l;
+}
+
+// storage position of the grid (long axes in digit order) -> grid position
+__device__ __forceinline__ int unperm_pos(const DevGeom& g, int pos) {
+    int out = pos;
+    for (int ax = 0; ax < g.n; ++ax) {
+        if (g.nfac[ax] <= 1) continue;
+        const int c = (pos / g.stride[ax]) % g.ext[ax];
+        out += (long_axis_perm(g, ax, c) - c) * g.stride[ax];
+    }
+    return out;
+}
+
+template <int SIGN, typename R, int MAXS>
+__device__ __forceinline__ void run_axis_long(const DevGeom& g, const DevTabs& t, int ax, cplx<R>* lds,
+                                              int npencil, int es, RowGeom rg) {
+    const int S = g.ext[ax], m = g.nfac[ax];
+    const int pes = es < rg.sl ? es : (es / rg.sl) * rg.sp;
+    const cplx<R>* tw = tw_of<R>(t, g, ax);
+    for (int st = 0; st < m; ++st) {
+        const int i = SIGN > 0 ? st : m - 1 - st;
+        int B = S;
+        for (int j = 0; j < i; ++j) B /= g.fac[ax][j];
+        const int f = g.fac[ax][i], sst = B / f, mult = S / B, nsub = S / f;
+        const bool last = i == m - 1;
+        const int total = npencil * nsub;
+        // consecutive lanes take consecutive pencils (as in run_axis)
+        for (int w = threadIdx.x; w < total; w += blockDim.x) {
+            const int sub = w / npencil, p = w - sub * npencil;
+            const int b = sub / sst, r = sub - b * sst;
+            const int hi = p / es, lo = p - hi * es;
+            cplx<R>* base = lds + phys(hi * es * S + lo + (b * B + r) * es, rg);
+            const int step = sst * pes, tstep = r * mult;
+            // the twiddles touch only this thread's own sub-pencil: after the
+            // inverse DFT, before the forward one
+            if (SIGN < 0 && !last && tstep) {
+                for (int k = 1; k < f; ++k) {
+                    const cplx<R> w = tw[k * tstep];
+                    cplx<R>& v = base[k * step];
+                    v = cplx<R>{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
+                }
+            }
+            dispatch_fft<SIGN, R, MAXS>(f, base, step);
+            if (SIGN > 0 && !last && tstep) {
+                for (int k = 1; k < f; ++k) {
+                    const cplx<R> w = tw[k * tstep];
+                    cplx<R>& v = base[k * step];
+                    v = cplx<R>{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+                }
+            }
+        }
+        if (st + 1 < m) __syncthreads();
+    }
+}
+
+// the transform along axis ax of every pencil in the tile
+template <int SIGN, typename R, int MAXS>
+__device__ __forceinline__ void run_axis_any(const DevGeom& g, const DevTabs& t, int ax, cplx<R>* lds,
+                                             int npencil, int es, RowGeom rg) {
+    if (g.nfac[ax] > 1) run_axis_long<SIGN, R, MAXS>(g, t, ax, lds, npencil, es, rg);
+    else run_axis<SIGN, R, MAXS>(lds, g.ext[ax], npencil, es, rg);
+}
+
+// ---------------------------------------------------------------------------
 // index maps (Sec. 3.2)
 // ---------------------------------------------------------------------------
 
@@ -250,6 +356,7 @@ __device__ __forceinline__ R vsum_except(const DevGeom& g, const R* __restrict__
 template <typename R>
 __device__ __forceinline__ VPencil<R> make_vpencil(const DevGeom& g, const DevTabs& t, int ax, int gbase) {
     VPencil<R> vp;
+    gbase = unperm_pos(g, gbase);  // the other axes may be long and in digit order
     vp.gbase = gbase;
     vp.gstep = g.stride[ax];
     if (g.vmode == 1) {
@@ -263,6 +370,14 @@ __device__ __forceinline__ VPencil<R> make_vpencil(const DevGeom& g, const DevTa
         vp.vb = vsum_except<R>(g, vt, gbase, ax);
     }
     return vp;
+}
+
+// V / N at a storage position of the grid (long axes in digit order)
+template <typename R>
+__device__ __forceinline__ R v_at_storage(const DevGeom& g, const DevTabs& t, int pos) {
+    const int gp = unperm_pos(g, pos);
+    if (g.vmode == 1) return vgrid_of<R>(t)[gp];
+    return vsum_except<R>(g, vtab_of<R>(t), gp, -1);
 }
 
 __device__ __forceinline__ int remap_block(int bid, int nblocks, int on) {
@@ -493,10 +608,22 @@ __device__ __forceinline__ void fused_body(const DevGeom& g, const DevTabs& t, R
     load_gather<R>(g, t, x, 0, N, tile, rg, reinterpret_cast<int*>(extra));
     __syncthreads();
     for (int ax = 0; ax < g.n - 1; ++ax) {
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], g.stride[ax], rg);
+        run_axis_any<+1, R, MAXS>(g, t, ax, tile, N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
-    {
+    if (g.nfac[g.n - 1] > 1) {
+        // a long last axis: its inverse stages, the potential at every point,
+        // its forward stages
+        run_axis_long<+1, R, MAXS>(g, t, g.n - 1, tile, rows, 1, rg);
+        __syncthreads();
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < N; it.next(blockDim.x)) {
+            cplx<R>& c = tile[it.row * rg.sp + it.col];
+            c = cscale(c, v_at_storage<R>(g, t, it.e));
+        }
+        __syncthreads();
+        run_axis_long<-1, R, MAXS>(g, t, g.n - 1, tile, rows, 1, rg);
+        __syncthreads();
+    } else {
         // last axis (contiguous, es = 1): inverse, potential, forward
         const int S = rg.sl;
         for (int p = threadIdx.x; p < rows; p += blockDim.x) {
@@ -506,7 +633,7 @@ __device__ __forceinline__ void fused_body(const DevGeom& g, const DevTabs& t, R
         __syncthreads();
     }
     for (int ax = g.n - 2; ax >= 0; --ax) {
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], N / g.ext[ax], g.stride[ax], rg);
+        run_axis_any<-1, R, MAXS>(g, t, ax, tile, N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
     kinetic_scatter<R>(g, t, x, y, 0, N, tile, rg, row_table_at(extra, rows, g.d));
@@ -544,7 +671,7 @@ __device__ __forceinline__ void pass1_body(const DevGeom& g, const DevTabs& t, c
     load_gather<R>(g, t, psi + off, r0, count, tile, rg, reinterpret_cast<int*>(extra));
     __syncthreads();
     for (int ax = pd.split; ax < g.n; ++ax) {
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], g.stride[ax], rg);
+        run_axis_any<+1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
     store_tile<R>(ws + off + r0, count, tile, rg);
@@ -622,10 +749,26 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     __syncthreads();
     for (int ax = 0; ax < split - 1; ++ax) {
         int es = (g.stride[ax] / sin_) << lgT;
-        run_axis<+1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
+        run_axis_any<+1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    {
+    if (g.nfac[split - 1] > 1) {
+        // a long last leading axis: its inverse stages, the potential at
+        // every point of the tile, its forward stages
+        const int ax = split - 1;
+        run_axis_long<+1, R, MAXS>(g, t, ax, tile, count / El, T, rg);
+        __syncthreads();
+        for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
+            const int i = it.col >> lgT, tt = it.col & (T - 1);
+            if (tt < tw) {
+                cplx<R>& c = tile[it.row * rg.sp + it.col];
+                c = cscale(c, v_at_storage<R>(g, t, (it.row * El + i) * sin_ + c0 + tt));
+            }
+        }
+        __syncthreads();
+        run_axis_long<-1, R, MAXS>(g, t, ax, tile, count / El, T, rg);
+        __syncthreads();
+    } else {
         const int ax = split - 1;
         const int S = El;
         const int es = T;
@@ -640,7 +783,7 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     }
     for (int ax = split - 2; ax >= 0; --ax) {
         int es = (g.stride[ax] / sin_) << lgT;
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
+        run_axis_any<-1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
     }
     if (pairs) {
@@ -664,8 +807,9 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
 // on) of one outer index (the axes before a) of one vector.  The LDS tile has
 // pass 2's layout with the axes [a, b) in place of the leading block.
 template <int SIGN, typename R, int MAXS>
-__device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd, cplx<R>* __restrict__ ws,
-                                           int bid_raw, int nblocks, unsigned char* smem) {
+__device__ __forceinline__ void passm_body(const DevGeom& g, const DevTabs& t, const PassDesc& pd,
+                                           cplx<R>* __restrict__ ws, int bid_raw, int nblocks,
+                                           unsigned char* smem) {
     cplx<R>* tile = reinterpret_cast<cplx<R>*>(smem);
     const int a = pd.split_mid, b = pd.split;
     const int T = pd.tile_mid, lgT = __ffs(T) - 1;
@@ -725,7 +869,7 @@ __device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd,
     __syncthreads();
     for (int ax = a; ax < b; ++ax) {
         const int es = (g.stride[ax] / cols) << lgT;
-        run_axis<SIGN, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], es, rg);
+        run_axis_any<SIGN, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
     }
     if (pairs) {
@@ -743,14 +887,30 @@ __device__ __forceinline__ void passm_body(const DevGeom& g, const PassDesc& pd,
     }
 }
 
+// Largest workgroup of the middle pass and of the further pass.  Their LDS
+// tile is large (up to 160 KB), so often one workgroup holds a CU alone, and
+// then only a large workgroup gives the CU enough waves to keep its loads in
+// flight.  That case is a leading block of many short axes (16^3 on the 6D
+// grid: 1,024 pencils per axis in a 4-column tile); 1024 threads cap a thread
+// at 128 VGPRs and 512 at 256, which 16-point pencils fit without spilling
+// (float32: 1024, float64: 512).  Longer pencils keep 256: their blocks have
+// fewer pencils than that per axis, and a kernel bound for more threads than
+// it can use measured slower.
+template <typename R, int MAXS>
+constexpr int wide_pass_threads() {
+    return MAXS <= 16 ? (sizeof(R) == 4 ? 1024 : 512) : 256;
+}
+
 template <int SIGN, typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_passm(DevGeom g, PassDesc pd, cplx<R>* __restrict__ ws) {
+__global__ void __launch_bounds__((wide_pass_threads<R, MAXS>()))
+    k_passm(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem[];
-    passm_body<SIGN, R, MAXS>(g, pd, ws, blockIdx.x, gridDim.x, smem);
+    passm_body<SIGN, R, MAXS>(g, t, pd, ws, blockIdx.x, gridDim.x, smem);
 }
 
 template <typename R, int MAXS>
-__global__ void __launch_bounds__(256) k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
+__global__ void __launch_bounds__((wide_pass_threads<R, MAXS>()))
+    k_pass2(DevGeom g, DevTabs t, PassDesc pd, cplx<R>* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem[];
     pass2_body<R, MAXS>(g, t, pd, ws, blockIdx.x, gridDim.x, smem);
 }
@@ -776,7 +936,7 @@ __device__ __forceinline__ void pass3_body(const DevGeom& g, const DevTabs& t, c
     load_tile<R>(ws + off + r0, count, tile, rg);
     __syncthreads();
     for (int ax = g.n - 1; ax >= pd.split; --ax) {
-        run_axis<-1, R, MAXS>(tile, g.ext[ax], count / g.ext[ax], g.stride[ax], rg);
+        run_axis_any<-1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
     kinetic_scatter<R>(g, t, psi + off, hpsi + off, r0, count, tile, rg,

@@ -62,7 +62,8 @@ hipError_t launch_pass3(const DevGeom& g, const DevTabs& t, const PassDesc& pd, 
                         void* hpsi, int nvec, hipStream_t st);
 // the further pass (sign +1: inverse, -1: forward)
 template <typename R, int MAXS>
-hipError_t launch_passm(const DevGeom& g, const PassDesc& pd, int sign, void* ws, int nvec, hipStream_t st);
+hipError_t launch_passm(const DevGeom& g, const DevTabs& t, const PassDesc& pd, int sign, void* ws, int nvec,
+                        hipStream_t st);
 template <typename R, int MAXS>
 hipError_t prepare_passm(int lds_bytes);
 // persistent batched pass over the work table (head, items in device memory)

@@ -96,16 +96,19 @@ hipError_t occupancy_batch<R, M>(size_t lds, int* blocks_per_cu) {
 }
 #elif IWFPM_TU_KERNEL == 5
 template <>
-hipError_t launch_passm<R, M>(const DevGeom& g, const PassDesc& pd, int sign, void* ws, int nvec, hipStream_t st) {
+hipError_t launch_passm<R, M>(const DevGeom& g, const DevTabs& t, const PassDesc& pd, int sign, void* ws, int nvec,
+                              hipStream_t st) {
     const int cols = pd.s_in;
     const int outer = g.N / g.stride[pd.split_mid - 1];
     const long long nb = (long long)((cols + pd.tile_mid - 1) / pd.tile_mid) * outer * nvec;
     if (nb > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     size_t lds = lds_mid(g, pd, sizeof(cplx<R>));
     if (sign > 0)
-        k_passm<1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, pd, reinterpret_cast<cplx<R>*>(ws));
+        k_passm<1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, t, pd,
+                                                                               reinterpret_cast<cplx<R>*>(ws));
     else
-        k_passm<-1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, pd, reinterpret_cast<cplx<R>*>(ws));
+        k_passm<-1, R, M><<<dim3((unsigned)nb), dim3(pd.threads_mid), lds, st>>>(g, t, pd,
+                                                                                reinterpret_cast<cplx<R>*>(ws));
     return hipGetLastError();
 }
 template <>

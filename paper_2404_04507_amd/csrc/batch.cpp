@@ -86,7 +86,7 @@ int iwfpm_batch_create(int B, const iwfpm_plan_t* plans, int precision, int use_
         const Schedule& sc = p->sched[prec];
         if (!sc.ok) return IWFPM_ERR_UNSUPPORTED;
         if (!sc.fused && sc.pd.split_mid > 0) return IWFPM_ERR_UNSUPPORTED;  // five-pass grids: apply one by one
-        for (int ax = 0; ax < p->n; ++ax) maxe = std::max(maxe, p->geom.ext[ax]);
+        for (int ax = 0; ax < p->n; ++ax) maxe = std::max(maxe, axis_class(p->geom, ax));
         if (sc.fused) lds = std::max(lds, lds_fused(p->geom, esz));
         else lds = std::max({lds, lds_slabs(p->geom, sc.pd, esz), lds_columns(p->geom, sc.pd, esz)});
     }

@@ -6,6 +6,7 @@
 namespace iwfpm {
 
 constexpr int kMaxAxes = 8;
+constexpr int kMaxFactors = 3;
 
 // Geometry of the lifted grid K*_{K,L} (Sec. 3.2) as the kernels see it.
 // Storage axes: 0..n-d-1 are the k_II axes, n-d..n-1 the k_I axes (fastest).
@@ -20,6 +21,14 @@ struct DevGeom {
     int nkI;                        // points per k_I slice (product of the d fastest extents)
     int voff[kMaxAxes];             // offset of axis ax's potential table
     double P1[kMaxAxes * kMaxAxes]; // 2 pi P_I, d x d row-major
+    // Axes longer than one register pencil are transformed in nfac > 1
+    // stages of fac[0] x fac[1] (x fac[2]) points; between the inverse and
+    // the forward transform such an axis is stored in the stages' digit
+    // order (see long_axis_perm).  twoff: offset of its twiddle table
+    // e^{+2 pi i j / ext}, j < ext.  nfac = 1 for every other axis.
+    int nfac[kMaxAxes];
+    int fac[kMaxAxes][kMaxFactors];
+    int twoff[kMaxAxes];
 };
 
 // Device pointers owned by the plan.
@@ -30,6 +39,8 @@ struct DevTabs {
     const double* vtab64;
     const float* vgrid32;     // potential on G_{K,L} divided by N (vmode 1)
     const double* vgrid64;
+    const float* tw32;        // twiddle tables of the long axes (complex, interleaved)
+    const double* tw64;
 };
 
 // Three-pass schedule (see apply_kernels.hip).

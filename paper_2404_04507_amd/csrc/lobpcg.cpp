@@ -3227,6 +3227,8 @@ int iwfpm_destroy(iwfpm_plan_t p) {
         dev_free(p->d_vtab64);
         dev_free(p->d_vgrid32);
         dev_free(p->d_vgrid64);
+        dev_free(p->d_tw32);
+        dev_free(p->d_tw64);
         dev_free(p->d_ws);
         dev_free(p->d_ef_freq);
         dev_free(p->d_ef_ws);

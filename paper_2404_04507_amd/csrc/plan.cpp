@@ -22,7 +22,7 @@ namespace iwfpm {
 
 static const double kTwoPi = 6.283185307179586476925286766559;
 
-static bool extent_supported(int e) {
+static bool pencil_compiled(int e) {
     switch (e) {
 #define IWFPM_CASE(s) \
     case s: return true;
@@ -32,8 +32,69 @@ static bool extent_supported(int e) {
     }
 }
 
+// Stages of an axis transform: one register pencil when the extent is
+// compiled, else the most balanced split into two (then three) compiled
+// pencil sizes > 1, the largest stage last; 0 stages if there is none.
+int axis_factors(int e, int* fac) {
+    if (e < 1) return 0;
+    if (pencil_compiled(e)) {
+        fac[0] = e;
+        return 1;
+    }
+    int best = 0, bmax = 1 << 30;
+    for (int a = 2; a * a <= e; ++a) {
+        if (e % a || !pencil_compiled(a) || !pencil_compiled(e / a)) continue;
+        if (e / a < bmax) {
+            bmax = e / a;
+            fac[0] = a;
+            fac[1] = e / a;
+            best = 2;
+        }
+    }
+    if (best) return best;
+    for (int a = 2; a * a * a <= e; ++a) {
+        if (e % a || !pencil_compiled(a)) continue;
+        const int r = e / a;
+        for (int b = a; b * b <= r; ++b) {
+            if (r % b || !pencil_compiled(b) || !pencil_compiled(r / b)) continue;
+            if (r / b < bmax) {
+                bmax = r / b;
+                fac[0] = a;
+                fac[1] = b;
+                fac[2] = r / b;
+                best = 3;
+            }
+        }
+    }
+    return best;
+}
+
+static bool extent_supported(int e) {
+    int f[kMaxFactors];
+    return axis_factors(e, f) > 0;
+}
+
 static int extent_class(int e) { return e <= 16 ? 16 : (e <= 32 ? 32 : 64); }
 int extent_class_of(int e) { return extent_class(e); }
+
+// the register pencils an axis needs: its largest stage
+int axis_class(const DevGeom& g, int ax) {
+    int m = 0;
+    for (int i = 0; i < g.nfac[ax]; ++i) m = std::max(m, g.fac[ax][i]);
+    return extent_class(m);
+}
+
+// largest workgroup of the middle and further passes for an extent class
+// (the device rule of wide_pass_threads)
+static int wide_pass_threads(int prec, int maxs) { return maxs <= 16 ? (prec == 1 ? 1024 : 512) : 256; }
+
+// pencils (or, for long axes, sub-pencils of the most numerous stage) that
+// one transform along axis ax of a tile of `count` points has to process
+static int axis_items(const DevGeom& g, int ax, long long count) {
+    int mn = g.ext[ax];
+    for (int i = 0; i < g.nfac[ax]; ++i) mn = std::min(mn, g.fac[ax][i]);
+    return (int)(count / mn);
+}
 
 int dev_alloc(DeviceBuf& b, size_t bytes) {
     dev_free(b);
@@ -170,6 +231,23 @@ static int build_geometry(iwfpm_plan_s* p) {
         if (st > (1LL << 31) - 1) return IWFPM_ERR_UNSUPPORTED;
     }
     g.N = st;
+    // stages of the long axes and their twiddle tables e^{+2 pi i j / ext}
+    p->tw.clear();
+    for (int ax = 0; ax < n; ++ax) {
+        g.nfac[ax] = axis_factors(g.ext[ax], g.fac[ax]);
+        if (g.nfac[ax] == 0) return IWFPM_ERR_UNSUPPORTED;
+        g.twoff[ax] = 0;
+        if (g.nfac[ax] > 1) {
+            g.twoff[ax] = (int)(p->tw.size() / 2);
+            const int E = g.ext[ax];
+            for (int j = 0; j < E; ++j) {
+                // in long double, then rounded once
+                const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)E;
+                p->tw.push_back((double)std::cos(a));
+                p->tw.push_back((double)std::sin(a));
+            }
+        }
+    }
     g.nkI = 1;
     for (int ax = n - d; ax < n; ++ax) g.nkI *= g.ext[ax];
     for (int j = 0; j < d; ++j)
@@ -314,7 +392,7 @@ static const size_t kLdsDefault = 64 * 1024;
 static const size_t kLdsMax = 160 * 1024;
 
 static int round64(int x) { return ((x + 63) / 64) * 64; }
-static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc);
+static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc, int prec, int outer_threads = 0);
 static int choose_mid_schedule(iwfpm_plan_s* p, int prec);
 
 static int choose_schedule(iwfpm_plan_s* p, int prec) {
@@ -322,9 +400,9 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
     const DevGeom& g = p->geom;
     const int n = p->n;
     const size_t esz = prec == 1 ? 8 : 16;
-    int maxall = 0;
-    for (int ax = 0; ax < n; ++ax) maxall = std::max(maxall, g.ext[ax]);
-    sc.maxs_fused = extent_class(maxall);
+    int maxcls = 16;
+    for (int ax = 0; ax < n; ++ax) maxcls = std::max(maxcls, axis_class(g, ax));
+    sc.maxs_fused = maxcls;
     const size_t lf = lds_fused(g, esz);
     bool want_fused = p->opts.schedule == IWFPM_SCHED_FUSED ||
                       (p->opts.schedule == IWFPM_SCHED_AUTO && lf <= kLdsDefault);
@@ -332,7 +410,7 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
         if (lf > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
         sc.fused = true;
         int maxp = 0;
-        for (int ax = 0; ax < n; ++ax) maxp = std::max(maxp, g.N / g.ext[ax]);
+        for (int ax = 0; ax < n; ++ax) maxp = std::max(maxp, axis_items(g, ax, g.N));
         sc.threads_fused = std::min(256, round64(maxp));
         return IWFPM_OK;
     }
@@ -399,56 +477,58 @@ static int choose_schedule(iwfpm_plan_s* p, int prec) {
     }
     pd.slabs_per_wg = G;
     if (lds_slabs(g, pd, esz) > kLdsMax) return IWFPM_ERR_UNSUPPORTED;
-    finalize_threepass(p, sc);
+    finalize_threepass(p, sc, prec);
     return IWFPM_OK;
 }
 
 // threads and extent classes of a three-pass schedule whose split, tile and
-// slabs per workgroup are set
-static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc) {
+// slabs per workgroup are set; the middle pass gets outer_threads threads
+// (0: as many as it has pencils, up to its class's largest workgroup)
+static void finalize_threepass(const iwfpm_plan_s* p, Schedule& sc, int prec, int outer_threads) {
     const DevGeom& g = p->geom;
     PassDesc& pd = sc.pd;
-    int maxpi = 0, maxpo = 0, mi = 0, mo = 0;
+    int maxpi = 0, maxpo = 0, mi = 16, mo = 16;
     for (int ax = pd.split; ax < p->n; ++ax) {
-        maxpi = std::max(maxpi, pd.slabs_per_wg * pd.s_in / g.ext[ax]);
-        mi = std::max(mi, g.ext[ax]);
+        maxpi = std::max(maxpi, axis_items(g, ax, (long long)pd.slabs_per_wg * pd.s_in));
+        mi = std::max(mi, axis_class(g, ax));
     }
     for (int ax = 0; ax < pd.split; ++ax) {
-        maxpo = std::max(maxpo, pd.s_out * pd.tile / g.ext[ax]);
-        mo = std::max(mo, g.ext[ax]);
+        maxpo = std::max(maxpo, axis_items(g, ax, (long long)pd.s_out * pd.tile));
+        mo = std::max(mo, axis_class(g, ax));
     }
     pd.threads_inner = std::min(256, round64(maxpi));
-    pd.threads_outer = std::min(256, round64(maxpo));
-    sc.maxs_inner = extent_class(mi);
-    sc.maxs_outer = extent_class(mo);
+    const int cap = wide_pass_threads(prec, mo);
+    pd.threads_outer = std::min(outer_threads > 0 ? std::min(outer_threads, cap) : cap, round64(maxpo));
+    sc.maxs_inner = mi;
+    sc.maxs_outer = mo;
     sc.fused = false;
     sc.ok = true;
 }
 
 // threads and extent classes of a schedule with the further pass
-static void finalize_mid(const iwfpm_plan_s* p, Schedule& sc) {
+static void finalize_mid(const iwfpm_plan_s* p, Schedule& sc, int prec) {
     const DevGeom& g = p->geom;
     PassDesc& pd = sc.pd;
     const PassDesc q = middle_desc(g, pd);
     const int mid = g.stride[pd.split_mid - 1] / pd.s_in;
-    int maxpi = 0, maxpo = 0, maxpm = 0, mi = 0, mo = 0;
+    int maxpi = 0, maxpo = 0, maxpm = 0, mi = 16, mo = 16;
     for (int ax = pd.split; ax < p->n; ++ax) {
-        maxpi = std::max(maxpi, pd.slabs_per_wg * pd.s_in / g.ext[ax]);
-        mi = std::max(mi, g.ext[ax]);
+        maxpi = std::max(maxpi, axis_items(g, ax, (long long)pd.slabs_per_wg * pd.s_in));
+        mi = std::max(mi, axis_class(g, ax));
     }
     for (int ax = 0; ax < pd.split_mid; ++ax) {
-        maxpo = std::max(maxpo, q.s_out * pd.tile / g.ext[ax]);
-        mo = std::max(mo, g.ext[ax]);
+        maxpo = std::max(maxpo, axis_items(g, ax, (long long)q.s_out * pd.tile));
+        mo = std::max(mo, axis_class(g, ax));
     }
     for (int ax = pd.split_mid; ax < pd.split; ++ax) {
-        maxpm = std::max(maxpm, mid * pd.tile_mid / g.ext[ax]);
-        mo = std::max(mo, g.ext[ax]);
+        maxpm = std::max(maxpm, axis_items(g, ax, (long long)mid * pd.tile_mid));
+        mo = std::max(mo, axis_class(g, ax));
     }
     pd.threads_inner = std::min(256, round64(maxpi));
-    pd.threads_outer = std::min(256, round64(maxpo));
-    pd.threads_mid = std::min(256, round64(maxpm));
-    sc.maxs_inner = extent_class(mi);
-    sc.maxs_outer = extent_class(mo);
+    pd.threads_outer = std::min(wide_pass_threads(prec, mo), round64(maxpo));
+    pd.threads_mid = std::min(wide_pass_threads(prec, mo), round64(maxpm));
+    sc.maxs_inner = mi;
+    sc.maxs_outer = mo;
     sc.fused = false;
     sc.ok = true;
 }
@@ -526,7 +606,7 @@ static int choose_mid_schedule(iwfpm_plan_s* p, int prec) {
     if (lds_columns(g, middle_desc(g, pd), esz) > kLdsMax || lds_mid(g, pd, esz) > kLdsMax ||
         lds_slabs(g, pd, esz) > kLdsMax)
         return IWFPM_ERR_UNSUPPORTED;
-    finalize_mid(p, sc);
+    finalize_mid(p, sc, prec);
     return IWFPM_OK;
 }
 
@@ -538,14 +618,14 @@ static std::vector<Schedule> schedule_candidates(const iwfpm_plan_s* p, int prec
     const size_t esz = prec == 1 ? 8 : 16;
     if (lds_fused(g, esz) <= kLdsMax) {
         Schedule f = p->sched[prec];
-        int maxall = 0, maxp = 0;
+        int maxcls = 16, maxp = 0;
         for (int ax = 0; ax < n; ++ax) {
-            maxall = std::max(maxall, g.ext[ax]);
-            maxp = std::max(maxp, g.N / g.ext[ax]);
+            maxcls = std::max(maxcls, axis_class(g, ax));
+            maxp = std::max(maxp, axis_items(g, ax, g.N));
         }
         f.fused = true;
         f.ok = true;
-        f.maxs_fused = extent_class(maxall);
+        f.maxs_fused = maxcls;
         f.threads_fused = std::min(256, round64(maxp));
         out.push_back(f);
     }
@@ -564,8 +644,16 @@ static std::vector<Schedule> schedule_candidates(const iwfpm_plan_s* p, int prec
                 pd.xcd_remap = 1;
                 if (T > pd.s_in || G > pd.s_out) continue;
                 if (lds_columns(g, pd, esz) > kLdsMax || lds_slabs(g, pd, esz) > kLdsMax) continue;
-                finalize_threepass(p, c);
-                out.push_back(c);
+                // middle-pass workgroups of 256, 512 and 1024 threads (as far
+                // as the class and the pencils allow; duplicates dropped)
+                int last = 0;
+                for (int th = 256; th <= 1024; th *= 2) {
+                    Schedule t = c;
+                    finalize_threepass(p, t, prec, th);
+                    if (t.pd.threads_outer == last) continue;
+                    last = t.pd.threads_outer;
+                    out.push_back(t);
+                }
             }
         }
     }
@@ -624,6 +712,13 @@ static int upload_tables(iwfpm_plan_s* p) {
         f32.assign(p->vgrid.begin(), p->vgrid.end());
         if ((rc = upload(p->d_vgrid32, f32)) != IWFPM_OK) return rc;
     }
+    if (!p->tw.empty()) {
+        if ((rc = upload(p->d_tw64, p->tw)) != IWFPM_OK) return rc;
+        f32.assign(p->tw.begin(), p->tw.end());
+        if ((rc = upload(p->d_tw32, f32)) != IWFPM_OK) return rc;
+    }
+    p->tabs.tw32 = (const float*)p->d_tw32.ptr;
+    p->tabs.tw64 = (const double*)p->d_tw64.ptr;
     p->tabs.slice_a = (const int*)p->d_slice_a.ptr;
     p->tabs.slice_g = (const double*)p->d_slice_g.ptr;
     p->tabs.vtab32 = (const float*)p->d_vtab32.ptr;
@@ -692,9 +787,9 @@ static hipError_t launch_sched(const Schedule& sc, const DevGeom& g, const DevTa
     const bool mid = sc.pd.split_mid > 0;
     auto passm = [&](int sign) {
         switch (sc.maxs_outer) {
-            case 16: return launch_passm<R, 16>(g, sc.pd, sign, ws, nvec, st);
-            case 32: return launch_passm<R, 32>(g, sc.pd, sign, ws, nvec, st);
-            default: return launch_passm<R, 64>(g, sc.pd, sign, ws, nvec, st);
+            case 16: return launch_passm<R, 16>(g, t, sc.pd, sign, ws, nvec, st);
+            case 32: return launch_passm<R, 32>(g, t, sc.pd, sign, ws, nvec, st);
+            default: return launch_passm<R, 64>(g, t, sc.pd, sign, ws, nvec, st);
         }
     };
     if (mid && (e = passm(+1)) != hipSuccess) return e;
@@ -730,7 +825,8 @@ int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st) {
     return IWFPM_OK;
 }
 
-int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st, int kinetic) {
+int plan_apply_ws(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st,
+                  int kinetic, void* ws, size_t ws_bytes) {
     if (nvec == 0) return IWFPM_OK;
     const int prec = precision == IWFPM_PREC_FP32 ? 1 : 0;
     const Schedule& sc = p->sched[prec];
@@ -739,13 +835,9 @@ int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int preci
     const long long N = p->geom.N;
     int chunk = nvec;
     if (!sc.fused) {
-        size_t per = (size_t)N * esz;
-        chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nvec, kWorkspaceCap / per));
-        size_t need = per * chunk;
-        if (p->d_ws.bytes < need) {
-            if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
-            if (dev_alloc(p->d_ws, need) != IWFPM_OK) return IWFPM_ERR_ALLOC;
-        }
+        const size_t per = (size_t)N * esz;
+        if (per > ws_bytes || !ws) return IWFPM_ERR_ARG;
+        chunk = (int)std::min<size_t>((size_t)nvec, ws_bytes / per);
     }
     const double2* x = reinterpret_cast<const double2*>(psi);
     double2* y = reinterpret_cast<double2*>(hpsi);
@@ -754,12 +846,31 @@ int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int preci
         DevGeom g = p->geom;
         g.kin = kinetic ? 1 : 0;
         hipError_t e = prec ? launch_sched<float>(sc, g, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                  p->d_ws.ptr, nv, st, kinetic ? &p->prof : nullptr)
+                                                  ws, nv, st, kinetic ? &p->prof : nullptr)
                             : launch_sched<double>(sc, g, p->tabs, x + (size_t)v0 * N, y + (size_t)v0 * N,
-                                                   p->d_ws.ptr, nv, st, kinetic ? &p->prof : nullptr);
+                                                   ws, nv, st, kinetic ? &p->prof : nullptr);
         if (e != hipSuccess) return IWFPM_ERR_DEVICE;
     }
     return IWFPM_OK;
+}
+
+int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st, int kinetic) {
+    if (nvec == 0) return IWFPM_OK;
+    const int prec = precision == IWFPM_PREC_FP32 ? 1 : 0;
+    const Schedule& sc = p->sched[prec];
+    if (!sc.ok) return IWFPM_ERR_UNSUPPORTED;
+    if (!sc.fused) {
+        // the plan's own workspace, grown to the vectors of one chunk
+        const size_t per = (size_t)p->geom.N * (prec ? 8 : 16);
+        const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)nvec, kWorkspaceCap / per));
+        const size_t need = per * chunk;
+        if (p->d_ws.bytes < need) {
+            if (hipStreamSynchronize(st) != hipSuccess) return IWFPM_ERR_DEVICE;
+            if (dev_alloc(p->d_ws, need) != IWFPM_OK) return IWFPM_ERR_ALLOC;
+        }
+        return plan_apply_ws(p, psi, hpsi, nvec, precision, st, kinetic, p->d_ws.ptr, need);
+    }
+    return plan_apply_ws(p, psi, hpsi, nvec, precision, st, kinetic, nullptr, 0);
 }
 
 }  // namespace iwfpm
@@ -990,15 +1101,17 @@ static std::string tune_key(const iwfpm_plan_s* p, int prec, int nvec) {
     return k;
 }
 
-static bool tune_cache_lookup(const char* path, const std::string& key, Schedule& sc, const iwfpm_plan_s* p) {
+static bool tune_cache_lookup(const char* path, const std::string& key, Schedule& sc, const iwfpm_plan_s* p,
+                              int prec) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char line[1024];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[512];
-        int fused, split, tile, G;
-        if (std::sscanf(line, "%511s %d %d %d %d", k, &fused, &split, &tile, &G) != 5) continue;
+        int fused, split, tile, G, threads = 0;
+        double us = 0.0;
+        if (std::sscanf(line, "%511s %d %d %d %d %lf %d", k, &fused, &split, &tile, &G, &us, &threads) < 5) continue;
         if (key != k) continue;
         if (fused) {
             found = false;  // re-derive below
@@ -1012,7 +1125,7 @@ static bool tune_cache_lookup(const char* path, const std::string& key, Schedule
             c.pd.tile = tile;
             c.pd.slabs_per_wg = G;
             c.pd.xcd_remap = 1;
-            finalize_threepass(p, c);
+            finalize_threepass(p, c, prec, threads);
             sc = c;
             found = true;
         }
@@ -1039,7 +1152,7 @@ int iwfpm_tune(iwfpm_plan_t p, int nvec, int precision, void* stream, double* be
     const char* cache = std::getenv("IWFPM_TUNE_CACHE");
     if (cache && cache[0]) {
         Schedule sc{};
-        if (tune_cache_lookup(cache, key, sc, p)) {
+        if (tune_cache_lookup(cache, key, sc, p, prec)) {
             if (sc.fused) {
                 for (auto& c : cands)
                     if (c.fused) sc = c;
@@ -1098,8 +1211,8 @@ int iwfpm_tune(iwfpm_plan_t p, int nvec, int precision, void* stream, double* be
     if (best_us) *best_us = best;
     if (cache && cache[0]) {
         if (FILE* f = std::fopen(cache, "a")) {
-            std::fprintf(f, "%s %d %d %d %d %.3f\n", key.c_str(), best_sc.fused ? 1 : 0, best_sc.pd.split,
-                         best_sc.pd.tile, best_sc.pd.slabs_per_wg, best);
+            std::fprintf(f, "%s %d %d %d %d %.3f %d\n", key.c_str(), best_sc.fused ? 1 : 0, best_sc.pd.split,
+                         best_sc.pd.tile, best_sc.pd.slabs_per_wg, best, best_sc.pd.threads_outer);
             std::fclose(f);
         }
     }
@@ -1115,6 +1228,7 @@ int iwfpm_schedule(iwfpm_plan_t p, int precision, int32_t* out) {
     out[1] = sc.pd.split;
     out[2] = sc.pd.tile;
     out[3] = sc.pd.slabs_per_wg;
+    out[4] = sc.fused ? sc.threads_fused : sc.pd.threads_outer;
     return IWFPM_OK;
 }
 

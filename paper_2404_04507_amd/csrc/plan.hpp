@@ -62,6 +62,7 @@ struct iwfpm_plan_s {
     std::vector<double> slice_g;  // nslice x d
     std::vector<double> vtab;     // per-axis tables / N (vmode 0)
     std::vector<double> vgrid;    // V on the grid / N (vmode 1)
+    std::vector<double> tw;       // twiddle tables of the long axes (re, im interleaved)
     double vhat0 = 0.0;           // coefficient of the zero mode
     double vsum_nonzero = 0.0;    // sum over m != 0 of |Vhat_m|
     double vsum_abs = 0.0;        // sum over all m of |Vhat_m|
@@ -70,7 +71,7 @@ struct iwfpm_plan_s {
     iwfpm::Schedule sched[2];
     // device
     bool host_only = true;
-    iwfpm::DeviceBuf d_slice_a, d_slice_g, d_vtab32, d_vtab64, d_vgrid32, d_vgrid64;
+    iwfpm::DeviceBuf d_slice_a, d_slice_g, d_vtab32, d_vtab64, d_vgrid32, d_vgrid64, d_tw32, d_tw64;
     iwfpm::DeviceBuf d_ws;        // apply workspace
     iwfpm::DeviceBuf d_ef_freq;   // eigenfunction output: (P k)_j per window point (d x N)
     iwfpm::DeviceBuf d_ef_ws;     // eigenfunction output: per-axis tables and slice partials
@@ -102,9 +103,19 @@ void dev_free(DeviceBuf& b);
 // grow the plan's apply workspace for nvec vectors of precision prec
 int plan_ensure_ws(iwfpm_plan_s* p, int nvec, int prec, hipStream_t st);
 int extent_class_of(int e);
+// stages of an axis transform (fac[0..return)), 0 if the extent is unsupported
+int axis_factors(int e, int* fac);
+// extent class (16, 32, 64) of the register pencils axis ax needs
+int axis_class(const DevGeom& g, int ax);
 
-// apply on a plan (precision 0 = float64 convolution, 1 = float32)
+// apply on a plan (precision 0 = float64 convolution, 1 = float32), with the
+// plan's own workspace (grown as needed)
 int plan_apply(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st, int kinetic = 1);
+// the same with a caller's workspace of ws_bytes (vectors applied in chunks
+// whose intermediate grids fit; ERR_ARG if one vector's does not); allocates
+// nothing
+int plan_apply_ws(iwfpm_plan_s* p, const void* psi, void* hpsi, int nvec, int precision, hipStream_t st,
+                  int kinetic, void* ws, size_t ws_bytes);
 
 // grid position -> true label k (paper order) and vector position
 void host_label(const iwfpm_plan_s* p, long long gpos, int* k_out);

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "iw
 
 def declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(iwfpm_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|void|const char\*)\s+(iwfpm_\w+)\s*\(", src, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -104,11 +104,8 @@ def test_status_codes():
         lib.Plan(P, [0], [4], modes, vhat, device=-1)
     assert e.value.status == -1
     with pytest.raises(lib.IwfpmError) as e:
-        lib.Plan(P, [4], [4096], modes, vhat, device=-1)
-    assert e.value.status == -4  # extent 8192 is not compiled
-    with pytest.raises(lib.IwfpmError) as e:
-        lib.Plan(P, [5], [40], modes, vhat, device=-1)
-    assert e.value.status == -4  # Table 2's L = 40 row: a 2L = 80-point axis, above the 64-point limit
+        lib.Plan(P, [4], [37], modes, vhat, device=-1)
+    assert e.value.status == -4  # 2L = 74 = 2 x 37: no compiled pencil of 37 points
     p = lib.Plan(P, [4], [4], modes, vhat, device=-1)
     so = lib.load_library()
     st = so.iwfpm_apply(p._h, ctypes.c_void_p(8), ctypes.c_void_p(1 << 20), 1, ctypes.c_void_p())
@@ -226,18 +223,39 @@ def test_eigenfunction_argument_checks_on_host_plan():
 
 
 def test_five_pass_grids_plan_on_host():
-    """Ex. 4.3 at K = 5, L = 20 and 30 (40^3 x 10^3 and 60^3 x 10^3): no single
+    """Ex. 4.3 at K = 5, L = 20, 30 and 40 (40^3, 60^3 and 80^3 x 10^3): no single
     split fits both the slab and the leading block in LDS, and the plan takes
     the five-pass schedule instead of refusing (passes 1 and 3 keep the three
-    10-point axes); at L = 40 the 80-point axes are still refused."""
+    10-point axes; L = 40 has 80-point axes, transformed in two stages)."""
     import math
-    for L in (20, 30):
+    for L in (20, 30, 40):
         prob = W.paper_example_3d(math.pi, 5, L)
         with lib.Plan.from_problem(prob, device=-1) as p:
             assert p.N == 1000 * (2 * L) ** 3
             for prec in ("fp32", "fp64"):
                 sc = p.schedule(prec)
                 assert not sc["fused"] and sc["split"] == 3, sc
-    with pytest.raises(lib.IwfpmError) as e:
-        lib.Plan.from_problem(W.paper_example_3d(math.pi, 5, 40), device=-1)
-    assert e.value.status == -4
+
+
+@pytest.mark.parametrize("ext,ok", [(34, True), (38, True), (42, True), (44, True), (46, True), (50, True),
+                                    (52, True), (54, True), (56, True), (58, True), (62, True), (80, True),
+                                    (84, True), (100, True), (120, True), (160, True), (1024, True),
+                                    (8192, True), (74, False), (82, False), (86, False), (94, False),
+                                    (106, False), (118, False), (122, False)])
+def test_axis_extents_supported(ext, ok):
+    """Every even extent whose factors are compiled pencil sizes (at most three
+    stages) plans, on either kind of axis, with labels equal to the oracle's;
+    an extent with a prime factor above 32 (37, 41, 43, 47, 53, 59, 61) is
+    refused with ERR_UNSUPPORTED."""
+    P = np.array([[1.0, W.GOLDEN]])
+    modes, vhat = W.cosine_modes(2, [1.0, 1.0])
+    for K, L in (([3], [ext // 2]), ([ext // 2], [3])):
+        if ok:
+            with lib.Plan(P, K, L, modes, vhat, device=-1) as p:
+                assert p.N == 6 * ext
+                if p.N <= 4096:
+                    assert np.array_equal(p.indices(), O.grid_labels(P, 1, K, L))
+        else:
+            with pytest.raises(lib.IwfpmError) as e:
+                lib.Plan(P, K, L, modes, vhat, device=-1)
+            assert e.value.status == -4
