@@ -64,7 +64,8 @@ typedef enum {
     IWFPM_ERR_NUMERIC = -7,        /* NaN/Inf or a breakdown the solver could not recover */
     IWFPM_ERR_NOCONV = -8,         /* maxit reached; partial results are returned */
     IWFPM_ERR_WEIGHTS = -9,        /* learned preconditioner weights missing or invalid */
-    IWFPM_ERR_NODEVICE = -10       /* the plan was created host-only (device = -1) */
+    IWFPM_ERR_NODEVICE = -10,      /* the plan was created host-only (device = -1) */
+    IWFPM_ERR_TOO_LARGE = -11      /* input beyond iwfpm_apply_noalloc's static scratch */
 } iwfpm_status;
 
 enum { IWFPM_PREC_FP64 = 0, IWFPM_PREC_FP32 = 1 };
@@ -149,6 +150,28 @@ int iwfpm_apply(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* 
 int iwfpm_apply_prec(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec,
                      int precision, void* stream);
 
+/*
+ * iwfpm_apply_noalloc - iwfpm_apply for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and ordering as iwfpm_apply (the
+ * same kernels on the plan's precision), but the multi-pass schedules'
+ * intermediate grid lives in a static device array of
+ * iwfpm_noalloc_scratch_bytes() bytes (128 MiB) that each GPU the library
+ * runs on holds until the process ends, instead of the plan's workspace; the
+ * call allocates nothing (the first call on a device also resolves the
+ * array's address there).  Vectors are applied in chunks whose intermediate
+ * grids fit the array.  All calls on one GPU share its array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * undefined results; serialise them.
+ * Errors: ERR_ARG (NULL pointers, nvec < 0, overlapping buffers),
+ * ERR_NODEVICE, ERR_UNSUPPORTED, ERR_TOO_LARGE (one vector's intermediate
+ * grid, N x 8 B in float32 or N x 16 B in float64, exceeds the array),
+ * ERR_DEVICE.
+ */
+int iwfpm_apply_noalloc(iwfpm_plan_t plan, const void* psi, void* hpsi, int nvec, void* stream);
+
+/* Size in bytes of iwfpm_apply_noalloc's static scratch array. */
+int64_t iwfpm_noalloc_scratch_bytes(void);
 
 /* The potential block alone, out = F V F^{-1} psi (Sec. 4.1), same arguments
  * as iwfpm_apply_prec (used by the learned preconditioner's convolution

@@ -31,7 +31,8 @@ EXPORTED = ["iwfpm_default_opts", "iwfpm_status_string", "iwfpm_plan", "iwfpm_de
             "iwfpm_conv", "iwfpm_default_learned_opts", "iwfpm_default_train_opts", "iwfpm_learned_create",
             "iwfpm_learned_destroy", "iwfpm_learned_nparams", "iwfpm_learned_get", "iwfpm_learned_set",
             "iwfpm_learned_attach", "iwfpm_learned_shells", "iwfpm_learned_forward", "iwfpm_learned_grad",
-            "iwfpm_learned_step", "iwfpm_learned_train", "iwfpm_eigenfunction"]
+            "iwfpm_learned_step", "iwfpm_learned_train", "iwfpm_eigenfunction", "iwfpm_apply_noalloc",
+            "iwfpm_noalloc_scratch_bytes"]
 
 _VOID_FUNCS = ("iwfpm_default_opts", "iwfpm_status_string", "iwfpm_default_eigs_opts",
                "iwfpm_default_learned_opts", "iwfpm_default_train_opts")
@@ -110,6 +111,9 @@ def load_library():
     lib.iwfpm_norm_bound.argtypes = [vp, dp]
     lib.iwfpm_apply.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.iwfpm_apply_prec.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.iwfpm_apply_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.iwfpm_noalloc_scratch_bytes.argtypes = []
+    lib.iwfpm_noalloc_scratch_bytes.restype = ctypes.c_int64
     lib.iwfpm_profile.argtypes = [vp, ctypes.c_int]
     lib.iwfpm_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.iwfpm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
@@ -476,6 +480,16 @@ class Plan:
         st = _lib().iwfpm_apply_prec(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                      nvec, prec, _stream_handle(stream))
         _check(st, "iwfpm_apply")
+        return out
+
+    def apply_noalloc(self, psi, out, stream=None):
+        """H psi through iwfpm_apply_noalloc (the library's static scratch, no
+        device allocation); `out` must be given."""
+        nvec = self._check_block(psi)
+        self._check_block(out)
+        st = _lib().iwfpm_apply_noalloc(self._h, ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        nvec, _stream_handle(stream))
+        _check(st, "iwfpm_apply_noalloc")
         return out
 
     def eigenfunction(self, u, origin, step, npts, out=None, stream=None):

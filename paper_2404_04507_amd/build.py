@@ -39,7 +39,7 @@ HOST_SOURCES = ["plan.cpp", "batch.cpp", "lobpcg.cpp", "learned.cpp"]
 # plan keeps exact, uncontracted arithmetic for its window ties
 HOST_FAST = {"lobpcg.cpp", "learned.cpp"}
 FAST_FLAGS = ["-O3", "-fcx-limited-range", "-ffp-contract=fast"]
-DEVICE_SOURCES = ["blas_kernels.hip", "learned_kernels.hip", "eigfun.hip"]
+DEVICE_SOURCES = ["blas_kernels.hip", "learned_kernels.hip", "eigfun.hip", "noalloc.hip"]
 APPLY_TUS = [(k, r, m) for k in range(6) for r in ("float", "double") for m in (16, 32, 64)]
 
 

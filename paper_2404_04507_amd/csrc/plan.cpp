@@ -905,6 +905,7 @@ const char* iwfpm_status_string(int s) {
         case IWFPM_ERR_NOCONV: return "not converged";
         case IWFPM_ERR_WEIGHTS: return "learned preconditioner weights missing or invalid";
         case IWFPM_ERR_NODEVICE: return "host-only plan";
+        case IWFPM_ERR_TOO_LARGE: return "one vector's intermediate grid exceeds the static scratch array";
         default: return "unknown status";
     }
 }
