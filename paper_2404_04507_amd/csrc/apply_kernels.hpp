@@ -108,23 +108,34 @@ __device__ __forceinline__ void dispatch_conv(int S, cplx<R>* base, int es, cons
     }
 }
 
+// Division by a divisor d that is the same for the whole workgroup, for
+// dividends and divisors below 2^16 (every position inside an LDS tile: a
+// tile holds at most 20,480 float entries).  The float quotient a * rcp(d),
+// with rcp(d) within one ulp of 1/d, is within a/d * 2^-22 < 2^-6 of a/d, so
+// its truncation is off by at most one, and one integer correction step
+// makes it exact (checked for every d < 2^16 with reciprocals one ulp off
+// either way).  The integer division it replaces takes some thirty
+// instructions; this takes about six.
+struct Div16 {
+    int d;
+    float inv;
+    __device__ __forceinline__ explicit Div16(int dd) : d(dd), inv(__builtin_amdgcn_rcpf((float)dd)) {}
+    __device__ __forceinline__ int div(int a) const {
+        int q = (int)((float)a * inv);
+        const int r = a - q * d;
+        q += (r >= d) - (r < 0);
+        return q;
+    }
+};
+
 // Pencil p of an axis with extent S and logical element stride es starts at
 // the logical offset (p / es) * es * S + p % es.  A logical offset L maps to
 // (L / sl) * sp + L % sl in a tile whose rows of sl elements are padded to a
 // pitch sp; a pencil either stays inside one row (es < sl) or steps by whole
 // rows (es a multiple of sl).
-__device__ __forceinline__ int phys(int L, RowGeom rg) {
-    int r = L / rg.sl;
+__device__ __forceinline__ int phys(int L, RowGeom rg, const Div16& dsl) {
+    const int r = dsl.div(L);
     return r * rg.sp + (L - r * rg.sl);
-}
-
-template <int SIGN, typename R, int MAXS>
-__device__ __forceinline__ void run_axis(cplx<R>* lds, int S, int npencil, int es, RowGeom rg) {
-    const int pes = es < rg.sl ? es : (es / rg.sl) * rg.sp;
-    for (int p = threadIdx.x; p < npencil; p += blockDim.x) {
-        int hi = p / es, lo = p - hi * es;
-        dispatch_fft<SIGN, R, MAXS>(S, lds + phys(hi * es * S + lo, rg), pes);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -183,54 +194,73 @@ __device__ __forceinline__ int unperm_pos(const DevGeom& g, int pos) {
     return out;
 }
 
+// npencil pencils of S points at logical element stride es, each one DFT in
+// registers
 template <int SIGN, typename R, int MAXS>
-__device__ __forceinline__ void run_axis_long(const DevGeom& g, const DevTabs& t, int ax, cplx<R>* lds,
-                                              int npencil, int es, RowGeom rg) {
-    const int S = g.ext[ax], m = g.nfac[ax];
+__device__ __forceinline__ void run_axis(cplx<R>* lds, int S, int npencil, int es, RowGeom rg) {
     const int pes = es < rg.sl ? es : (es / rg.sl) * rg.sp;
-    const cplx<R>* tw = tw_of<R>(t, g, ax);
-    for (int st = 0; st < m; ++st) {
-        const int i = SIGN > 0 ? st : m - 1 - st;
-        int B = S;
-        for (int j = 0; j < i; ++j) B /= g.fac[ax][j];
-        const int f = g.fac[ax][i], sst = B / f, mult = S / B, nsub = S / f;
-        const bool last = i == m - 1;
-        const int total = npencil * nsub;
-        // consecutive lanes take consecutive pencils (as in run_axis)
-        for (int w = threadIdx.x; w < total; w += blockDim.x) {
-            const int sub = w / npencil, p = w - sub * npencil;
-            const int b = sub / sst, r = sub - b * sst;
-            const int hi = p / es, lo = p - hi * es;
-            cplx<R>* base = lds + phys(hi * es * S + lo + (b * B + r) * es, rg);
-            const int step = sst * pes, tstep = r * mult;
-            // the twiddles touch only this thread's own sub-pencil: after the
-            // inverse DFT, before the forward one
-            if (SIGN < 0 && !last && tstep) {
-                for (int k = 1; k < f; ++k) {
-                    const cplx<R> w = tw[k * tstep];
-                    cplx<R>& v = base[k * step];
-                    v = cplx<R>{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
-                }
-            }
-            dispatch_fft<SIGN, R, MAXS>(f, base, step);
-            if (SIGN > 0 && !last && tstep) {
-                for (int k = 1; k < f; ++k) {
-                    const cplx<R> w = tw[k * tstep];
-                    cplx<R>& v = base[k * step];
-                    v = cplx<R>{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
-                }
-            }
-        }
-        if (st + 1 < m) __syncthreads();
+    const Div16 des(es), dsl(rg.sl);
+    for (int p = threadIdx.x; p < npencil; p += blockDim.x) {
+        const int hi = des.div(p), lo = p - hi * es;
+        dispatch_fft<SIGN, R, MAXS>(S, lds + phys(hi * es * S + lo, rg, dsl), pes);
     }
 }
 
-// the transform along axis ax of every pencil in the tile
+// The twiddles of one stage of a long axis, on the pencils of run_axis with
+// the same arguments and the same pencil-to-thread assignment (so every
+// thread touches only what it transforms itself, and no barrier is needed
+// between the two): entry k of the pencil with offset r = (p mod es) / es_tw
+// in its block is multiplied by tw[r k mult] (conjugated for SIGN < 0).  A
+// loop of its own, so that run_axis keeps the bare pencil loop.
+template <int SIGN, typename R>
+__device__ __forceinline__ void twiddle_axis(cplx<R>* lds, int S, int npencil, int es, RowGeom rg,
+                                             const cplx<R>* __restrict__ tw, int es_tw, int mult) {
+    const int pes = es < rg.sl ? es : (es / rg.sl) * rg.sp;
+    const Div16 des(es), dsl(rg.sl), dtw(es_tw);
+    for (int p = threadIdx.x; p < npencil; p += blockDim.x) {
+        const int hi = des.div(p), lo = p - hi * es;
+        const int tstep = dtw.div(lo) * mult;
+        if (!tstep) continue;
+        cplx<R>* base = lds + phys(hi * es * S + lo, rg, dsl);
+        for (int k = 1; k < S; ++k) {
+            const cplx<R> w = tw[k * tstep];
+            cplx<R>& v = base[k * pes];
+            if (SIGN > 0) v = cplx<R>{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+            else v = cplx<R>{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
+        }
+    }
+}
+
+// The transform along axis ax of every pencil of the tile (npencil pencils at
+// logical element stride es).  A long axis runs its stages as sweeps of
+// run_axis (and twiddle_axis): stage i has sub-pencils of f_i points at stride (B_i / f_i) es,
+// and sub-pencil (block b, offset r) of the axis' pencil (hi, lo) starts at
+// hi es S + lo + (b B_i + r) es = hi' (B_i / f_i) es f_i + lo' with
+// lo' = r es + lo, i.e. exactly where run_axis puts pencil (hi', lo').
 template <int SIGN, typename R, int MAXS>
-__device__ __forceinline__ void run_axis_any(const DevGeom& g, const DevTabs& t, int ax, cplx<R>* lds,
-                                             int npencil, int es, RowGeom rg) {
-    if (g.nfac[ax] > 1) run_axis_long<SIGN, R, MAXS>(g, t, ax, lds, npencil, es, rg);
-    else run_axis<SIGN, R, MAXS>(lds, g.ext[ax], npencil, es, rg);
+__device__ __forceinline__ void run_axis_any(const DevGeom& g, const DevTabs& t, int ax, cplx<R>* lds, int npencil,
+                                             int es, RowGeom rg) {
+    const int S = g.ext[ax], m = g.nfac[ax];
+    for (int st = 0; st < m; ++st) {
+        // one call site of run_axis, so that the kernel inlines the register
+        // pencils once; a one-stage axis does none of the stage arithmetic
+        int f = S, np = npencil, esf = es, mult = 0;
+        const cplx<R>* tw = nullptr;
+        if (m > 1) {
+            const int i = SIGN > 0 ? st : m - 1 - st;
+            int B = S;
+            for (int j = 0; j < i; ++j) B /= g.fac[ax][j];
+            f = g.fac[ax][i];
+            np = npencil * (S / f);
+            esf = (B / f) * es;
+            mult = S / B;
+            if (i < m - 1) tw = tw_of<R>(t, g, ax);
+        }
+        if (SIGN < 0 && tw) twiddle_axis<SIGN, R>(lds, f, np, esf, rg, tw, es, mult);
+        run_axis<SIGN, R, MAXS>(lds, f, np, esf, rg);
+        if (SIGN > 0 && tw) twiddle_axis<SIGN, R>(lds, f, np, esf, rg, tw, es, mult);
+        if (st + 1 < m) __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -607,32 +637,29 @@ __device__ __forceinline__ void fused_body(const DevGeom& g, const DevTabs& t, R
 
     load_gather<R>(g, t, x, 0, N, tile, rg, reinterpret_cast<int*>(extra));
     __syncthreads();
-    for (int ax = 0; ax < g.n - 1; ++ax) {
+    // A long last axis takes its inverse stages with the other axes, then the
+    // potential at every point, then its forward stages; a short one keeps
+    // inverse, potential and forward DFT of each line in registers.
+    const bool long_last = g.nfac[g.n - 1] > 1;
+    const int n_inv = long_last ? g.n : g.n - 1;
+    for (int ax = 0; ax < n_inv; ++ax) {
         run_axis_any<+1, R, MAXS>(g, t, ax, tile, N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
-    if (g.nfac[g.n - 1] > 1) {
-        // a long last axis: its inverse stages, the potential at every point,
-        // its forward stages
-        run_axis_long<+1, R, MAXS>(g, t, g.n - 1, tile, rows, 1, rg);
-        __syncthreads();
+    if (long_last) {
         for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < N; it.next(blockDim.x)) {
             cplx<R>& c = tile[it.row * rg.sp + it.col];
             c = cscale(c, v_at_storage<R>(g, t, it.e));
         }
-        __syncthreads();
-        run_axis_long<-1, R, MAXS>(g, t, g.n - 1, tile, rows, 1, rg);
-        __syncthreads();
     } else {
-        // last axis (contiguous, es = 1): inverse, potential, forward
         const int S = rg.sl;
         for (int p = threadIdx.x; p < rows; p += blockDim.x) {
             VPencil<R> vp = make_vpencil<R>(g, t, g.n - 1, p * S);
             dispatch_conv<R, MAXS>(S, tile + p * rg.sp, 1, vp);
         }
-        __syncthreads();
     }
-    for (int ax = g.n - 2; ax >= 0; --ax) {
+    __syncthreads();
+    for (int ax = n_inv - 1; ax >= 0; --ax) {
         run_axis_any<-1, R, MAXS>(g, t, ax, tile, N / g.ext[ax], g.stride[ax], rg);
         __syncthreads();
     }
@@ -747,17 +774,17 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
         }
     }
     __syncthreads();
-    for (int ax = 0; ax < split - 1; ++ax) {
+    // as in the fused kernel: a long last leading axis takes its inverse
+    // stages with the other leading axes, then the potential at every point of
+    // the tile, then its forward stages
+    const bool long_last = g.nfac[split - 1] > 1;
+    const int n_inv = long_last ? split : split - 1;
+    for (int ax = 0; ax < n_inv; ++ax) {
         int es = (g.stride[ax] / sin_) << lgT;
         run_axis_any<+1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    if (g.nfac[split - 1] > 1) {
-        // a long last leading axis: its inverse stages, the potential at
-        // every point of the tile, its forward stages
-        const int ax = split - 1;
-        run_axis_long<+1, R, MAXS>(g, t, ax, tile, count / El, T, rg);
-        __syncthreads();
+    if (long_last) {
         for (RowIter it(threadIdx.x, blockDim.x, rg.sl); it.e < count; it.next(blockDim.x)) {
             const int i = it.col >> lgT, tt = it.col & (T - 1);
             if (tt < tw) {
@@ -765,9 +792,50 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
                 c = cscale(c, v_at_storage<R>(g, t, (it.row * El + i) * sin_ + c0 + tt));
             }
         }
+    } else if (g.vmode == 0) {
+        // per-axis potential tables: the sum over the axes other than the
+        // convolution axis splits into a part fixed by the tile row (the
+        // other leading axes) and a part fixed by the column (the trailing
+        // axes); both are tabulated per tile (after the tile), so a pencil
+        // reads two entries instead of decomposing its grid position
+        const int ax = split - 1;
+        const int S = El;
+        const int np = count / S;
+        const int nrow = count / rg.sl;
+        R* vrow = reinterpret_cast<R*>(smem + (size_t)nrow * rg.sp * sizeof(cplx<R>));
+        R* vcol = vrow + nrow;
+        const R* vt = vtab_of<R>(t);
+        for (int e = threadIdx.x; e < nrow + T; e += blockDim.x) {
+            R acc = R(0);
+            if (e < nrow) {
+                // row e: leading position e El (convolution axis at 0)
+                const int o = e * El;
+                for (int a = 0; a < ax; ++a) {
+                    int c = (o / (g.stride[a] / sin_)) % g.ext[a];
+                    if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
+                    acc += vt[g.voff[a] + c];
+                }
+            } else {
+                const int cc = c0 + min(e - nrow, tw - 1);
+                for (int a = split; a < g.n; ++a) {
+                    int c = (cc / g.stride[a]) % g.ext[a];
+                    if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
+                    acc += vt[g.voff[a] + c];
+                }
+            }
+            vrow[e] = acc;
+        }
         __syncthreads();
-        run_axis_long<-1, R, MAXS>(g, t, ax, tile, count / El, T, rg);
-        __syncthreads();
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            const int hi = p >> lgT, lo = p & (T - 1);  // hi: row, lo: column
+            VPencil<R> vp;
+            vp.vgrid = nullptr;
+            vp.vaxis = vt + g.voff[ax];
+            vp.vb = vrow[hi] + vcol[lo];
+            vp.gbase = 0;
+            vp.gstep = 0;
+            dispatch_conv<R, MAXS>(S, tile + hi * rg.sp + lo, T, vp);
+        }
     } else {
         const int ax = split - 1;
         const int S = El;
@@ -779,9 +847,9 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
             VPencil<R> vp = make_vpencil<R>(g, t, ax, gb);
             dispatch_conv<R, MAXS>(S, tile + hi * rg.sp + lo, es, vp);
         }
-        __syncthreads();
     }
-    for (int ax = split - 2; ax >= 0; --ax) {
+    __syncthreads();
+    for (int ax = n_inv - 1; ax >= 0; --ax) {
         int es = (g.stride[ax] / sin_) << lgT;
         run_axis_any<-1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();

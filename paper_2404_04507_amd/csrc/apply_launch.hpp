@@ -25,10 +25,12 @@ inline size_t lds_slabs(const DevGeom& g, const PassDesc& pd, size_t esz) {
     int rows = pd.slabs_per_wg * pd.s_in / rg.sl;
     return (size_t)rows * rg.sp * esz + row_table_bytes(rows, g.d);
 }
-// pass 2 tile: rows of (last leading extent) x tile columns, padded by `tile`
+// pass 2 tile: rows of (last leading extent) x tile columns, padded by `tile`,
+// then the potential's per-row and per-column sums (one real each)
 inline size_t lds_columns(const DevGeom& g, const PassDesc& pd, size_t esz) {
     int El = g.ext[pd.split - 1];
-    return (size_t)(pd.s_out / El) * (El + 1) * pd.tile * esz;
+    const size_t rows = (size_t)(pd.s_out / El);
+    return rows * (El + 1) * pd.tile * esz + (rows + pd.tile) * (esz / 2);
 }
 
 // the further pass over axes [split_mid, split): rows of (extent of axis
