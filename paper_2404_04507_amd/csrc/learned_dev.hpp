@@ -11,7 +11,7 @@
 
 namespace iwfpm {
 
-// ---- dense layers of the shell MLP: bfloat16 weights, float32 arithmetic ----
+// ---- dense layers of the shell MLP: bfloat16 weights on the bf16 matrix cores, float32 accumulation ----
 // Y[s][o] = act(sum_i X[s][i] W[i][o] + b[o]) for s < S; Z (optional) keeps the pre-activation
 hipError_t lp_dense_fwd(const float* X, const uint16_t* W, const float* b, float* Z, float* Y, int S, int in, int out,
                         int act, hipStream_t st);

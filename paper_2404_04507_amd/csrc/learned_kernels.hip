@@ -42,20 +42,92 @@ __device__ __forceinline__ float gelu_grad(float x) {
 }
 
 // ---------------------------------------------------------------------------
-// dense layers (the MLP runs over ~10^3 shells: a few MFLOP per layer)
+// dense layers of the shell MLP on the matrix cores (v_mfma_f32_16x16x16_bf16,
+// float32 accumulation).  The weights are bfloat16; an operand held in
+// float32 (activations, gradients) is split into three bfloat16 terms
+// x = h + m + l (each the round-to-nearest of what the previous ones left),
+// which carry its full 24-bit significand, and products of bfloat16 terms are
+// exact in float32, so each layer computes what a float32 loop over the
+// bf16-rounded weights would, up to the order of the float32 additions.
+// Lane l of a wave holds A[l%16][4(l/16) .. 4(l/16)+3] and
+// B[4(l/16) .. 4(l/16)+3][l%16] of a 16 x 16 x 16 step and ends with
+// D[4(l/16) + v][l%16], v < 4; one wave per 16 x 16 tile of the output.
 // ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// one thread per output; weights read along o (coalesced across the wavefront)
-__global__ void k_dense_fwd(const float* __restrict__ X, const uint16_t* __restrict__ W, const float* __restrict__ b,
-                            float* __restrict__ Z, float* __restrict__ Y, int S, int in, int out, int act) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= S * out) return;
-    int s = e / out, o = e - s * out;
-    float acc = b[o];
-    const float* x = X + (size_t)s * in;
-    for (int i = 0; i < in; ++i) acc = fmaf(x[i], bf2f(W[(size_t)i * out + o]), acc);
-    if (Z) Z[e] = acc;
-    Y[e] = act ? gelu(acc) : acc;
+// operand element (r, c) at p[r * sr + c * sc], float32 or (bf16 != 0) bfloat16
+struct MatOp {
+    const void* p;
+    int sr, sc, bf16;
+};
+
+__device__ __forceinline__ float op_at(const MatOp& o, int r, int c) {
+    const size_t e = (size_t)r * o.sr + (size_t)c * o.sc;
+    return o.bf16 ? bf2f(reinterpret_cast<const uint16_t*>(o.p)[e]) : reinterpret_cast<const float*>(o.p)[e];
+}
+
+// x = h + m + l in bfloat16 (exact for normal float32 x)
+__device__ __forceinline__ void split3(float x, short& h, short& m, short& l) {
+    const uint16_t a = f2bf(x);
+    const float r1 = x - bf2f(a);
+    const uint16_t b = f2bf(r1);
+    const float r2 = r1 - bf2f(b);
+    h = (short)a;
+    m = (short)b;
+    l = (short)f2bf(r2);
+}
+
+// C (M x N, row-major, ldc) = A (M x K) B (K x N) [+ bias[n]]; Z (optional)
+// receives C, Y = act(C).  Terms: 3 for A (float32) x B (bfloat16), the six
+// largest of the nine for float32 x float32 (what is left is below 2^-23 of
+// each product).
+__global__ void __launch_bounds__(256) k_mlp_gemm(MatOp A, MatOp B, const float* __restrict__ bias, float* __restrict__ Z,
+                                                  float* __restrict__ Y, int M, int N, int K, int act) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_n = (N + 15) >> 4;
+    const int tile = blockIdx.x * 4 + wave;
+    const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
+    if (tm * 16 >= M) return;
+    const int li = lane & 15, lk = 4 * (lane >> 4);
+    const int row = tm * 16 + li, col = tn * 16 + li;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 ah, am, al, bh, bm, bl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + lk + q;
+            const float a = (row < M && k < K) ? op_at(A, row, k) : 0.f;
+            const float b = (col < N && k < K) ? op_at(B, k, col) : 0.f;
+            short h, m, l;
+            split3(a, h, m, l);
+            ah[q] = h;
+            am[q] = m;
+            al[q] = l;
+            split3(b, h, m, l);
+            bh[q] = h;
+            bm[q] = m;
+            bl[q] = l;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+        if (!B.bf16) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bm, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = tm * 16 + lk + v, c = tn * 16 + li;
+        if (r < M && c < N) {
+            float z = acc[v] + (bias ? bias[c] : 0.f);
+            const size_t e = (size_t)r * N + c;
+            if (Z) Z[e] = z;
+            Y[e] = act ? gelu(z) : z;
+        }
+    }
 }
 
 __global__ void k_act_bwd(const float* __restrict__ dY, const float* __restrict__ Z, float* __restrict__ dZ, int n,
@@ -65,34 +137,13 @@ __global__ void k_act_bwd(const float* __restrict__ dY, const float* __restrict_
     dZ[e] = act ? dY[e] * gelu_grad(Z[e]) : dY[e];
 }
 
-// dX[s][i] = sum_o dZ[s][o] W[i][o]
-__global__ void k_dense_bwd_data(const float* __restrict__ dZ, const uint16_t* __restrict__ W, float* __restrict__ dX,
-                                 int S, int in, int out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= S * in) return;
-    int s = e / in, i = e - s * in;
+// db[o] = sum_s dZ[s][o] (fixed summation order)
+__global__ void k_bias_grad(const float* __restrict__ dZ, float* __restrict__ db, int S, int out) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= out) return;
     float acc = 0.f;
-    const float* dz = dZ + (size_t)s * out;
-    const uint16_t* w = W + (size_t)i * out;
-    for (int o = 0; o < out; ++o) acc = fmaf(dz[o], bf2f(w[o]), acc);
-    dX[e] = acc;
-}
-
-// dW[i][o] = sum_s X[s][i] dZ[s][o];  db[o] = sum_s dZ[s][o]  (fixed summation order)
-__global__ void k_dense_bwd_weight(const float* __restrict__ X, const float* __restrict__ dZ, float* __restrict__ dW,
-                                   float* __restrict__ db, int S, int in, int out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < in * out) {
-        int i = e / out, o = e - i * out;
-        float acc = 0.f;
-        for (int s = 0; s < S; ++s) acc = fmaf(X[(size_t)s * in + i], dZ[(size_t)s * out + o], acc);
-        dW[e] = acc;
-    } else if (e < in * out + out) {
-        int o = e - in * out;
-        float acc = 0.f;
-        for (int s = 0; s < S; ++s) acc += dZ[(size_t)s * out + o];
-        db[o] = acc;
-    }
+    for (int s = 0; s < S; ++s) acc += dZ[(size_t)s * out + o];
+    db[o] = acc;
 }
 
 __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
@@ -264,9 +315,16 @@ static int blocks_for(long long n, int cap) {
 constexpr int kGridCap = 4096;
 constexpr int kNoCap = 1 << 30;
 
+static int mlp_blocks(int M, int N) {
+    const long long tiles = (long long)((M + 15) / 16) * ((N + 15) / 16);
+    return (int)((tiles + 3) / 4);
+}
+
 hipError_t lp_dense_fwd(const float* X, const uint16_t* W, const float* b, float* Z, float* Y, int S, int in, int out,
                         int act, hipStream_t st) {
-    k_dense_fwd<<<blocks_for((long long)S * out, kNoCap), 256, 0, st>>>(X, W, b, Z, Y, S, in, out, act);
+    // A = X (S x in, row-major), B = W (in x out, row-major, bfloat16)
+    const MatOp A{X, in, 1, 0}, B{W, out, 1, 1};
+    k_mlp_gemm<<<mlp_blocks(S, out), 256, 0, st>>>(A, B, b, Z, Y, S, out, in, act);
     return hipGetLastError();
 }
 hipError_t lp_act_bwd(const float* dY, const float* Z, float* dZ, int n, int act, hipStream_t st) {
@@ -275,8 +333,17 @@ hipError_t lp_act_bwd(const float* dY, const float* Z, float* dZ, int n, int act
 }
 hipError_t lp_dense_bwd(const float* X, const float* dZ, const uint16_t* W, float* dX, float* dW, float* db, int S,
                         int in, int out, hipStream_t st) {
-    if (dX) k_dense_bwd_data<<<blocks_for((long long)S * in, kNoCap), 256, 0, st>>>(dZ, W, dX, S, in, out);
-    k_dense_bwd_weight<<<blocks_for((long long)in * out + out, kNoCap), 256, 0, st>>>(X, dZ, dW, db, S, in, out);
+    if (dX) {
+        // dX (S x in) = dZ (S x out) W^T: B[k][n] = W[n][k]
+        const MatOp A{dZ, out, 1, 0}, B{W, 1, out, 1};
+        k_mlp_gemm<<<mlp_blocks(S, in), 256, 0, st>>>(A, B, nullptr, nullptr, dX, S, in, out, 0);
+    }
+    {
+        // dW (in x out) = X^T (in x S) dZ (S x out): A[r][k] = X[k][r]
+        const MatOp A{X, 1, in, 0}, B{dZ, out, 1, 0};
+        k_mlp_gemm<<<mlp_blocks(in, out), 256, 0, st>>>(A, B, nullptr, nullptr, dW, in, out, S, 0);
+    }
+    k_bias_grad<<<(out + 255) / 256, 256, 0, st>>>(dZ, db, S, out);
     return hipGetLastError();
 }
 hipError_t lp_adam(float* w, float* m, float* v, const float* g, uint16_t* wbf, int n, float lr, float b1, float b2,
