@@ -387,6 +387,9 @@ static void tridiag_soa(std::vector<cd>& A, int n, std::vector<double>& d, std::
 // the reflectors u_k (unit, rows k+1..n-1) in the columns of U with has[k].
 static void tridiag_real(std::vector<double>& a, int n, std::vector<double>& d, std::vector<double>& e,
                          std::vector<double>& U, std::vector<char>& has) {
+    // small dense algebra: sums may be reassociated (vectorised); the result
+    // is still the same for every run of one build
+#pragma clang fp reassociate(on)
     U.assign((size_t)n * n, 0.0);
     has.assign(n, 0);
     e.assign(n, 0.0);
@@ -476,8 +479,9 @@ static bool tridiag_lowest(std::vector<double> d, std::vector<double> e, int n, 
                         deflated = true;
                         break;
                     }
-                    sn = f / r;
-                    cs = g / r;
+                    const double rinv = 1.0 / r;
+                    sn = f * rinv;
+                    cs = g * rinv;
                     g = d[i + 1] - pp;
                     r = (d[i] - g) * sn + 2.0 * cs * b;
                     pp = sn * r;
@@ -501,12 +505,14 @@ static bool tridiag_lowest(std::vector<double> d, std::vector<double> e, int n, 
     for (int c = 0; c < nv; ++c) Y[(size_t)idx[c] * nv + c] = 1.0;
     for (size_t t = rots.size(); t-- > 0;) {
         const Rot& q = rots[t];
-        double* yi = &Y[(size_t)q.i * nv];
-        double* yi1 = yi + nv;
+        double* __restrict yi = &Y[(size_t)q.i * nv];
+        double* __restrict yi1 = yi + nv;
+        const double qc = q.c, qs = q.s;
+#pragma clang loop vectorize(enable)
         for (int c = 0; c < nv; ++c) {
             const double a = yi[c], b = yi1[c];
-            yi[c] = q.c * a + q.s * b;
-            yi1[c] = q.c * b - q.s * a;
+            yi[c] = qc * a + qs * b;
+            yi1[c] = qc * b - qs * a;
         }
     }
     return true;
@@ -516,6 +522,9 @@ static bool tridiag_lowest(std::vector<double> d, std::vector<double> e, int n, 
 // lowest (V: n x nv): tridiag_real, tridiag_lowest, then the reflectors in
 // reverse order.
 static bool syev_lowest(std::vector<double> A, int n, int nv, std::vector<double>& w, std::vector<double>& V) {
+    // small dense algebra: sums may be reassociated (vectorised); the result
+    // is still the same for every run of one build
+#pragma clang fp reassociate(on)
     nv = std::max(0, std::min(nv, n));
     std::vector<double> d, e, U, Y;
     std::vector<char> has;
@@ -997,6 +1006,9 @@ static int apply_block(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats
 template <class S>
 static int rr_coefficients_t(const std::vector<S>& G, const std::vector<double>& theta, int m, int ns,
                              const std::vector<int>& act, std::vector<double>& th, std::vector<S>& U) {
+    // small dense algebra: sums may be reassociated (vectorised); the result
+    // is still the same for every run of one build
+#pragma clang fp reassociate(on)
     const int ma = (int)act.size();
     std::vector<S> A((size_t)ns * ns, 0.0);
     const int nr = ns - m;
@@ -1080,6 +1092,9 @@ static int rr_coefficients(const std::vector<cd>& G, const std::vector<double>& 
 // or nothing is left (the caller then projects explicitly).
 template <class S>
 static bool ortho_coefficients_t(const std::vector<S>& Gall, int nx, int ma, std::vector<S>& Cm, int& mw) {
+    // small dense algebra: sums may be reassociated (vectorised); the result
+    // is still the same for every run of one build
+#pragma clang fp reassociate(on)
     const int ld = nx + ma;
     std::vector<S> Gc((size_t)ma * ma);
     for (int j = 0; j < ma; ++j)
