@@ -711,6 +711,54 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g
     pass1_body<R, MAXS>(g, t, pd, rg, psi, ws, blockIdx.x, gridDim.x, smem);
 }
 
+// Per-axis potential tables (vmode 0) in the middle pass: the sum over the
+// axes other than the convolution axis (the last leading one) splits into a
+// part fixed by the tile row (the other leading axes) and a part fixed by the
+// column (the trailing axes).  Row e of the tile starts at leading position
+// e El (convolution axis at 0); cc is a column of the trailing block.
+template <typename R>
+__device__ __forceinline__ R p2_row_sum(const DevGeom& g, const R* vt, int split, int sin_, int e) {
+    const int o = e * g.ext[split - 1];
+    R acc = R(0);
+    for (int a = 0; a < split - 1; ++a) {
+        int c = (o / (g.stride[a] / sin_)) % g.ext[a];
+        if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
+        acc += vt[g.voff[a] + c];
+    }
+    return acc;
+}
+template <typename R>
+__device__ __forceinline__ R p2_col_sum(const DevGeom& g, const R* vt, int split, int cc) {
+    R acc = R(0);
+    for (int a = split; a < g.n; ++a) {
+        int c = (cc / g.stride[a]) % g.ext[a];
+        if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
+        acc += vt[g.voff[a] + c];
+    }
+    return acc;
+}
+
+// inverse DFT, x V, forward DFT along the convolution axis (El points at
+// element stride T = 2^lgT) of every pencil of the tile, with the row and
+// column sums tabulated (a pencil reads two entries instead of decomposing
+// its grid position) and vaxis the convolution axis' own table
+template <typename R, int MAXS>
+__device__ __forceinline__ void p2_conv_tables(cplx<R>* tile, RowGeom rg, int count, int El, int lgT, const R* vrow,
+                                               const R* vcol, const R* vaxis) {
+    const int T = 1 << lgT;
+    const int np = count / El;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const int hi = p >> lgT, lo = p & (T - 1);  // hi: row, lo: column
+        VPencil<R> vp;
+        vp.vgrid = nullptr;
+        vp.vaxis = vaxis;
+        vp.vb = vrow[hi] + vcol[lo];
+        vp.gbase = 0;
+        vp.gstep = 0;
+        dispatch_conv<R, MAXS>(El, tile + hi * rg.sp + lo, T, vp);
+    }
+}
+
 // pass 2: inverse DFT along the leading axes, x V, forward DFT, on a tile of
 // `tile` consecutive columns of one vector.  The LDS tile is [outer][column];
 // its rows (one line of the last leading axis times the columns) are padded
@@ -793,49 +841,17 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
             }
         }
     } else if (g.vmode == 0) {
-        // per-axis potential tables: the sum over the axes other than the
-        // convolution axis splits into a part fixed by the tile row (the
-        // other leading axes) and a part fixed by the column (the trailing
-        // axes); both are tabulated per tile (after the tile), so a pencil
-        // reads two entries instead of decomposing its grid position
-        const int ax = split - 1;
-        const int S = El;
-        const int np = count / S;
+        // per-axis potential tables: row and column sums tabulated per tile
+        // (after the tile)
         const int nrow = count / rg.sl;
         R* vrow = reinterpret_cast<R*>(smem + (size_t)nrow * rg.sp * sizeof(cplx<R>));
         R* vcol = vrow + nrow;
         const R* vt = vtab_of<R>(t);
-        for (int e = threadIdx.x; e < nrow + T; e += blockDim.x) {
-            R acc = R(0);
-            if (e < nrow) {
-                // row e: leading position e El (convolution axis at 0)
-                const int o = e * El;
-                for (int a = 0; a < ax; ++a) {
-                    int c = (o / (g.stride[a] / sin_)) % g.ext[a];
-                    if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
-                    acc += vt[g.voff[a] + c];
-                }
-            } else {
-                const int cc = c0 + min(e - nrow, tw - 1);
-                for (int a = split; a < g.n; ++a) {
-                    int c = (cc / g.stride[a]) % g.ext[a];
-                    if (g.nfac[a] > 1) c = long_axis_perm(g, a, c);
-                    acc += vt[g.voff[a] + c];
-                }
-            }
-            vrow[e] = acc;
-        }
+        for (int e = threadIdx.x; e < nrow + T; e += blockDim.x)
+            vrow[e] = e < nrow ? p2_row_sum<R>(g, vt, split, sin_, e)
+                               : p2_col_sum<R>(g, vt, split, c0 + min(e - nrow, tw - 1));
         __syncthreads();
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int hi = p >> lgT, lo = p & (T - 1);  // hi: row, lo: column
-            VPencil<R> vp;
-            vp.vgrid = nullptr;
-            vp.vaxis = vt + g.voff[ax];
-            vp.vb = vrow[hi] + vcol[lo];
-            vp.gbase = 0;
-            vp.gstep = 0;
-            dispatch_conv<R, MAXS>(S, tile + hi * rg.sp + lo, T, vp);
-        }
+        p2_conv_tables<R, MAXS>(tile, rg, count, El, lgT, vrow, vcol, vt + g.voff[split - 1]);
     } else {
         const int ax = split - 1;
         const int S = El;
