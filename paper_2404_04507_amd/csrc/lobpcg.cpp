@@ -975,28 +975,6 @@ static bool rr_transform(const std::vector<cd>& G, int m, std::vector<double>& t
     return true;
 }
 
-static int rr_block(Ctx& c, int m, std::vector<double>& theta) {
-    std::vector<cd> G;
-    std::vector<double2*> XHX = cols(c, B_X, 0, m), HX = cols(c, B_HX, 0, m);
-    XHX.insert(XHX.end(), HX.begin(), HX.end());
-    int rc = host_gram(c, cols(c, B_X, 0, m), XHX, G);
-    if (rc) return rc;
-    std::vector<cd> C;
-    if (!rr_transform(G, m, theta, C)) return IWFPM_ERR_NUMERIC;
-    if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
-    if ((rc = dev_lincomb(c, cols(c, B_HX, 0, m), cols(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
-    std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
-    std::swap(c.s->buf[B_HX], c.s->buf[B_HXN]);
-    return IWFPM_OK;
-}
-
-static int apply_block(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats* stats) {
-    if (cnt <= 0) return IWFPM_OK;
-    int rc = plan_apply(c.p, c.col(bin, 0), c.col(bout, 0), cnt, prec, c.st);
-    if (stats) stats->matvecs += cnt;
-    return rc;
-}
-
 // Rayleigh-Ritz in the coefficient space of the orthonormal basis
 // S = [X W P] (ns columns, the first m are X): G = S^H [HW HP] (ns x (ns - m)),
 // X^H H X = diag(theta).  Returns the Ritz values th (ascending, ns) and U =
@@ -1145,284 +1123,6 @@ static bool force_explicit_ortho() {
     return e && std::strcmp(e, "explicit") == 0;
 }
 
-static int run(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, const void* x0, double* evals, void* evecs, double* eta_out,
-               iwfpm_stats* stats, hipStream_t st, Capture* cap = nullptr) {
-    const int nev = o.nev;
-    int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
-    if (m < nev || m > 32) return IWFPM_ERR_ARG;
-    if (m > p->geom.N) return IWFPM_ERR_ARG;
-    int rc = solver_ensure(p, m);
-    if (rc) return rc;
-    int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
-    if ((rc = solver_precond(p, pk))) return rc;
-    Solver* s = (Solver*)p->solver;
-    Ctx c{p, s, st, p->geom.N};
-    const long long N = c.N;
-    const double hnorm = p->lam_max + p->vsum_abs;
-    int prec = p->opts.precision;
-    if (!p->sched[prec].ok) prec = 1 - prec;
-    if (!p->sched[prec].ok) return IWFPM_ERR_UNSUPPORTED;
-    const bool can64 = p->sched[0].ok;
-    const char* venv = std::getenv("IWFPM_VERBOSE");
-    const bool verbose = venv && venv[0] == '1';
-    const bool explicit_ortho = force_explicit_ortho();
-    LearnedPrecond* lp = nullptr;
-    if (o.precond == IWFPM_PRECOND_LEARNED) {
-        lp = p->learned;
-        if (!lp || !learned_ready(lp, p)) return IWFPM_ERR_WEIGHTS;
-    }
-
-    // start block: orthonormalise, apply H, Rayleigh-Ritz
-    if (x0) {
-        CHECK_HIP(hipMemcpyAsync(c.col(B_X, 0), x0, (size_t)N * m * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    } else {
-        CHECK_HIP(randn(c.col(B_X, 0), N * m, o.seed, st));
-    }
-    {
-        std::vector<cd> G, T;
-        if ((rc = host_gram(c, cols(c, B_X, 0, m), cols(c, B_X, 0, m), G))) return rc;
-        int r = svqb(G, m, T);
-        if (r < m) return IWFPM_ERR_NUMERIC;
-        if ((rc = dev_lincomb(c, cols(c, B_X, 0, m), cols(c, B_XN, 0, m), T, m, 0, 0.0))) return rc;
-        std::swap(s->buf[B_X], s->buf[B_XN]);
-    }
-    if ((rc = apply_block(c, B_X, B_HX, m, prec, stats))) return rc;
-    std::vector<double> theta;
-    if ((rc = rr_block(c, m, theta))) return rc;
-
-    // P holds mp orthonormal columns orthogonal to X (built in coefficient space)
-    int mp = 0;
-    std::vector<double> eta(m, 1.0);
-    int it = 0, polished = 0, fallback = 0, reortho = 0;
-    bool cleaned = false;
-    double best_eta = 1e300;
-    int best_it = 0;
-    int status = IWFPM_OK;
-    const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
-    double* dNorm = (double*)((double2*)s->small.ptr + 96 * 96);
-    for (;;) {
-        // residuals R = HX - X theta and their norms
-        {
-            ColPtrs hx{}, x{}, r{};
-            Reals th{};
-            for (int j = 0; j < m; ++j) {
-                hx.p[j] = c.col(B_HX, j);
-                x.p[j] = c.col(B_X, j);
-                r.p[j] = c.col(B_T1, j);
-                th.v[j] = theta[j];
-            }
-            CHECK_HIP(residual_norm(hx, x, r, th, m, N, (double*)s->partial.ptr, s->max_blocks, dNorm, st));
-            double* h = (double*)(s->hsmall + 96 * 96);
-            CHECK_HIP(hipMemcpyAsync(h, dNorm, m * sizeof(double), hipMemcpyDeviceToHost, st));
-            if ((rc = sync(c))) return rc;
-            for (int j = 0; j < m; ++j) {
-                eta[j] = std::sqrt(std::max(0.0, h[j])) / (hnorm + std::fabs(theta[j]));
-                if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
-            }
-        }
-        if (cap && it > 0 && it % cap->stride == 0 && it != cap->last_it && cap->got < (int)cap->X.size()) {
-            const size_t bytes = (size_t)N * cap->ncol * sizeof(double2);
-            CHECK_HIP(hipMemcpyAsync(cap->X[cap->got], c.col(B_X, 0), bytes, hipMemcpyDeviceToDevice, st));
-            if (!cap->R.empty())
-                CHECK_HIP(hipMemcpyAsync(cap->R[cap->got], c.col(B_T1, 0), bytes, hipMemcpyDeviceToDevice, st));
-            cap->eta.emplace_back(eta.begin(), eta.begin() + cap->ncol);
-            cap->last_it = it;
-            ++cap->got;
-        }
-        int conv = 0;
-        double worst = 0.0;
-        for (int j = 0; j < nev; ++j) {
-            conv += eta[j] <= o.tol;
-            worst = std::max(worst, eta[j]);
-        }
-        if (verbose)
-            std::fprintf(stderr, "[iwfpm_eigs] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n",
-                         it, prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
-        if (conv == nev) {
-            if ((prec == 0 || !can64) && cleaned) break;
-            cleaned = true;
-            if (prec == 0 || !can64) {
-                // re-orthonormalise X and take the Ritz pairs once more, then confirm
-                if ((rc = rr_block(c, m, theta))) return rc;
-                continue;
-            }
-            // confirm with float64 applies (Rayleigh-Ritz of X with the float64 H)
-            prec = 0;
-            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
-            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
-            if ((rc = rr_block(c, m, theta))) return rc;
-            continue;
-        }
-        if (it >= o.maxit) {
-            status = IWFPM_ERR_NOCONV;
-            break;
-        }
-        // float32 convolution: continue with float64 applies once the residuals
-        // reach its noise floor or stop improving
-        bool stalled = false;
-        if (worst < 0.5 * best_eta) {
-            best_eta = worst;
-            best_it = it;
-        } else {
-            stalled = worst < 1e-5 && it - best_it >= 20;
-        }
-        if (lp && it - best_it >= 50) {
-            // learned preconditioner stagnating: continue with M
-            fallback = 1;
-            lp = nullptr;
-            best_it = it;
-        }
-        if (prec == 1 && o.polish && can64 && (worst < floor32 || stalled)) {
-            prec = 0;
-            if ((rc = apply_block(c, B_X, B_HX, m, 0, stats))) return rc;
-            if (mp > 0 && (rc = apply_block(c, B_P, B_HP, mp, 0, stats))) return rc;
-            if ((rc = rr_block(c, m, theta))) return rc;
-            best_eta = 1e300;
-            continue;
-        }
-        ++it;
-        if (prec == 0 && p->opts.precision == 1) ++polished;
-
-        // active set, W = M R_A
-        bool lp_used = false;
-        std::vector<int> act;
-        for (int j = 0; j < m; ++j)
-            if (eta[j] > o.tol) act.push_back(j);
-        const int ma = (int)act.size();
-        {
-            ColPtrs r{}, w{};
-            for (int a = 0; a < ma; ++a) {
-                r.p[a] = c.col(B_T1, act[a]);
-                w.p[a] = c.col(B_W, a);
-            }
-            bool used_learned = false;
-            if (lp) {
-                int lrc = learned_apply(lp, p, r, w, ma, st);
-                if (lrc == IWFPM_OK) used_learned = true;
-                else {
-                    fallback = 1;
-                    lp = nullptr;
-                }
-            }
-            if (!used_learned) CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
-            lp_used = used_learned;
-        }
-        // P: built last iteration from the then-active Ritz vectors only,
-        // orthonormal and orthogonal to X
-        std::vector<double2*> Pa = cols(c, B_P, 0, mp), HPa = cols(c, B_HP, 0, mp);
-        const int mq = mp;
-        // W <- orthonormal basis of the part of W orthogonal to [X P_A]: one
-        // explicit projection with the Gram [X P W]^H W, then the second
-        // projection and SVQB in coefficient space (explicit twice as fallback)
-        int mw = 0;
-        {
-            std::vector<double2*> XP = cols(c, B_X, 0, m);
-            XP.insert(XP.end(), Pa.begin(), Pa.end());
-            const int nx = (int)XP.size();
-            std::vector<double2*> XPW = XP;
-            for (int j = 0; j < ma; ++j) XPW.push_back(c.col(B_W, j));
-            std::vector<cd> Gall, Cm;
-            if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
-            if (lp_used) {
-                // a non-finite learned direction falls back to M for the rest of the solve
-                bool finite = true;
-                for (int j = 0; j < ma; ++j)
-                    finite = finite && std::isfinite(Gall[(size_t)(nx + j) + (size_t)j * (nx + ma)].real());
-                if (!finite) {
-                    fallback = 1;
-                    lp = nullptr;
-                    ColPtrs r{}, w{};
-                    for (int a = 0; a < ma; ++a) {
-                        r.p[a] = c.col(B_T1, act[a]);
-                        w.p[a] = c.col(B_W, a);
-                    }
-                    CHECK_HIP(precond(r, w, ma, (const double*)s->M.ptr, N, st));
-                    if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
-                }
-            }
-            bool done = false;
-            if (!explicit_ortho) {
-                // one explicit projection, then the second one and SVQB in coefficient space
-                const std::vector<cd> G1 = neg_projection(Gall, nx, ma);
-                if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G1, nx, 0, 1.0))) return rc;
-                if ((rc = host_gram(c, XPW, cols(c, B_W, 0, ma), Gall))) return rc;
-                if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
-                    if ((rc = dev_lincomb(c, XPW, cols(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
-                    done = true;
-                }
-            }
-            if (!done) {
-                ++reortho;
-                for (int pass = 0; pass < 2; ++pass) {
-                    std::vector<cd> G;
-                    if ((rc = host_gram(c, XP, cols(c, B_W, 0, ma), G))) return rc;
-                    for (auto& g : G) g = -g;
-                    if ((rc = dev_lincomb(c, XP, cols(c, B_W, 0, ma), G, nx, 0, 1.0))) return rc;
-                }
-                std::vector<cd> G, T;
-                if ((rc = host_gram(c, cols(c, B_W, 0, ma), cols(c, B_W, 0, ma), G))) return rc;
-                mw = svqb(G, ma, T, 1e-10);
-                if ((rc = dev_lincomb(c, cols(c, B_W, 0, ma), cols(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
-            }
-            std::swap(s->buf[B_W], s->buf[B_T1]);
-        }
-        if ((rc = apply_block(c, B_W, B_HW, mw, prec, stats))) return rc;
-        // Rayleigh-Ritz on the orthonormal basis S = [X W P_A]:
-        // A = S^H H S with X^H H X = diag(theta); only [X W P_A]^H [HW HP_A] is formed
-        const int ns = m + mw + mq;
-        std::vector<double2*> S = cols(c, B_X, 0, m), HS = cols(c, B_HX, 0, m);
-        for (int j = 0; j < mw; ++j) {
-            S.push_back(c.col(B_W, j));
-            HS.push_back(c.col(B_HW, j));
-        }
-        S.insert(S.end(), Pa.begin(), Pa.end());
-        HS.insert(HS.end(), HPa.begin(), HPa.end());
-        std::vector<double> th;
-        std::vector<cd> U;
-        int mpn = 0;
-        {
-            std::vector<double2*> HR(HS.begin() + m, HS.end());
-            std::vector<cd> G;
-            if ((rc = host_gram(c, S, HR, G))) return rc;
-            mpn = rr_coefficients(G, theta, m, ns, act, th, U);
-        }
-        // [X_new | P_new] = S U,  [HX_new | HP_new] = HS U
-        {
-            std::vector<double2*> out = cols(c, B_XN, 0, m), hout = cols(c, B_HXN, 0, m);
-            for (int j = 0; j < mpn; ++j) {
-                out.push_back(c.col(B_PN, j));
-                hout.push_back(c.col(B_HPN, j));
-            }
-            if ((rc = dev_lincomb(c, S, out, U, ns, 0, 0.0))) return rc;
-            if ((rc = dev_lincomb(c, HS, hout, U, ns, 0, 0.0))) return rc;
-            std::swap(s->buf[B_X], s->buf[B_XN]);
-            std::swap(s->buf[B_HX], s->buf[B_HXN]);
-            std::swap(s->buf[B_P], s->buf[B_PN]);
-            std::swap(s->buf[B_HP], s->buf[B_HPN]);
-            mp = mpn;
-        }
-        theta.assign(th.begin(), th.begin() + m);
-    }
-    if (stats) {
-        stats->iterations = it;
-        stats->restarts = 0;
-        stats->fallback = fallback;
-        stats->polished = polished;
-        int conv = 0;
-        for (int j = 0; j < nev; ++j) conv += eta[j] <= o.tol;
-        stats->converged = conv;
-    }
-    for (int j = 0; j < nev; ++j) {
-        evals[j] = theta[j];
-        if (eta_out) eta_out[j] = eta[j];
-    }
-    if (evecs)
-        CHECK_HIP(hipMemcpyAsync(evecs, c.col(B_X, 0), (size_t)N * nev * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    CHECK_HIP(hipStreamSynchronize(st));
-    return status;
-}
-
-
 // ---------------------------------------------------------------------------
 // Real-symmetric LOBPCG.  When every Vhat_m is real (Hermiticity then makes
 // V even), H~ is a real symmetric matrix and its eigenvectors can be taken
@@ -1554,287 +1254,6 @@ static ColPtrs colptrs(const std::vector<RVec>& v, unsigned long long* parts) {
 }
 
 // Rayleigh-Ritz on X alone: X <- X C, HX <- HX C (real)
-static int rr_block_real(Ctx& c, int m, std::vector<double>& theta) {
-    std::vector<cd> G;
-    std::vector<RVec> XHX = rvecs(c, B_X, 0, m), HX = rvecs(c, B_HX, 0, m);
-    XHX.insert(XHX.end(), HX.begin(), HX.end());
-    int rc = host_gram_real(c, rvecs(c, B_X, 0, m), XHX, G);
-    if (rc) return rc;
-    std::vector<cd> C;
-    if (!rr_transform(G, m, theta, C)) return IWFPM_ERR_NUMERIC;
-    if ((rc = dev_lincomb_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_XN, 0, m), C, m, 0, 0.0))) return rc;
-    if ((rc = dev_lincomb_real(c, rvecs(c, B_HX, 0, m), rvecs(c, B_HXN, 0, m), C, m, 0, 0.0))) return rc;
-    std::swap(c.s->buf[B_X], c.s->buf[B_XN]);
-    std::swap(c.s->buf[B_HX], c.s->buf[B_HXN]);
-    return IWFPM_OK;
-}
-
-static int apply_real(Ctx& c, int bin, int bout, int cnt, int prec, iwfpm_stats* stats) {
-    if (cnt <= 0) return IWFPM_OK;
-    int rc = plan_apply(c.p, c.col(bin, 0), c.col(bout, 0), (cnt + 1) / 2, prec, c.st);
-    if (stats) stats->matvecs += cnt;
-    return rc;
-}
-
-static int run_real(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, double* evals, void* evecs, double* eta_out,
-                    iwfpm_stats* stats, hipStream_t st) {
-    const int nev = o.nev;
-    int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
-    if (m < nev || m > 32) return IWFPM_ERR_ARG;
-    if (m > p->geom.N) return IWFPM_ERR_ARG;
-    int rc = solver_ensure(p, m);
-    if (rc) return rc;
-    int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
-    if ((rc = solver_precond(p, pk))) return rc;
-    Solver* s = (Solver*)p->solver;
-    Ctx c{p, s, st, p->geom.N};
-    const long long N = c.N;
-    const double hnorm = p->lam_max + p->vsum_abs;
-    int prec = p->opts.precision;
-    if (!p->sched[prec].ok) prec = 1 - prec;
-    if (!p->sched[prec].ok) return IWFPM_ERR_UNSUPPORTED;
-    const bool can64 = p->sched[0].ok;
-    const char* venv = std::getenv("IWFPM_VERBOSE");
-    const bool verbose = venv && venv[0] == '1';
-    const bool explicit_ortho = force_explicit_ortho();
-    LearnedPrecond* lp = nullptr;
-    if (o.precond == IWFPM_PRECOND_LEARNED) {
-        lp = p->learned;
-        if (!lp || !learned_ready(lp, p)) return IWFPM_ERR_WEIGHTS;
-    }
-    const double* Mdiag = (const double*)s->M.ptr;
-
-    // start block: the real and imaginary parts of a seeded complex block
-    CHECK_HIP(randn(c.col(B_X, 0), N * ((m + 1) / 2), o.seed, st));
-    {
-        std::vector<cd> G, T;
-        if ((rc = host_gram_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_X, 0, m), G))) return rc;
-        hermitian_part(G, m);
-        int r = svqb(G, m, T);
-        if (r < m) return IWFPM_ERR_NUMERIC;
-        if ((rc = dev_lincomb_real(c, rvecs(c, B_X, 0, m), rvecs(c, B_XN, 0, m), T, m, 0, 0.0))) return rc;
-        std::swap(s->buf[B_X], s->buf[B_XN]);
-    }
-    if ((rc = apply_real(c, B_X, B_HX, m, prec, stats))) return rc;
-    std::vector<double> theta;
-    if ((rc = rr_block_real(c, m, theta))) return rc;
-
-    int mp = 0;
-    std::vector<double> eta(m, 1.0);
-    int it = 0, polished = 0, fallback = 0, reortho = 0;
-    bool cleaned = false;
-    double best_eta = 1e300;
-    int best_it = 0;
-    int status = IWFPM_OK;
-    const double floor32 = 30.0 * 6e-8 * p->vsum_abs / hnorm;
-    double* dNorm = (double*)((double2*)s->small.ptr + 96 * 96);
-    const int mc = (m + 1) / 2;
-    for (;;) {
-        // residuals R = HX - X theta (two per column) and their norms
-        {
-            ColPtrs hx{}, x{}, r{};
-            Reals th{};
-            for (int j = 0; j < mc; ++j) {
-                hx.p[j] = c.col(B_HX, j);
-                x.p[j] = c.col(B_X, j);
-                r.p[j] = c.col(B_T1, j);
-            }
-            for (int v = 0; v < 2 * mc; ++v) th.v[v] = v < m ? theta[v] : 0.0;
-            CHECK_HIP(residual_norm_pairs(hx, x, r, th, mc, N, (double*)s->partial.ptr, s->max_blocks, dNorm, st));
-            double* h = (double*)(s->hsmall + 96 * 96);
-            CHECK_HIP(hipMemcpyAsync(h, dNorm, 2 * mc * sizeof(double), hipMemcpyDeviceToHost, st));
-            if ((rc = sync(c))) return rc;
-            for (int j = 0; j < m; ++j) {
-                eta[j] = std::sqrt(std::max(0.0, h[j])) / (hnorm + std::fabs(theta[j]));
-                if (!std::isfinite(eta[j]) || !std::isfinite(theta[j])) return IWFPM_ERR_NUMERIC;
-            }
-        }
-        int conv = 0;
-        double worst = 0.0;
-        for (int j = 0; j < nev; ++j) {
-            conv += eta[j] <= o.tol;
-            worst = std::max(worst, eta[j]);
-        }
-        if (verbose)
-            std::fprintf(stderr,
-                         "[iwfpm_eigs real] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n", it,
-                         prec ? "fp32" : "fp64", conv, nev, worst, theta[0], mp, reortho);
-        if (conv == nev) {
-            if ((prec == 0 || !can64) && cleaned) break;
-            cleaned = true;
-            if (prec == 0 || !can64) {
-                if ((rc = rr_block_real(c, m, theta))) return rc;
-                continue;
-            }
-            prec = 0;
-            if ((rc = apply_real(c, B_X, B_HX, m, 0, stats))) return rc;
-            if (mp > 0 && (rc = apply_real(c, B_P, B_HP, mp, 0, stats))) return rc;
-            if ((rc = rr_block_real(c, m, theta))) return rc;
-            continue;
-        }
-        if (it >= o.maxit) {
-            status = IWFPM_ERR_NOCONV;
-            break;
-        }
-        bool stalled = false;
-        if (worst < 0.5 * best_eta) {
-            best_eta = worst;
-            best_it = it;
-        } else {
-            stalled = worst < 1e-5 && it - best_it >= 20;
-        }
-        if (lp && it - best_it >= 50) {
-            fallback = 1;
-            lp = nullptr;
-            best_it = it;
-        }
-        if (prec == 1 && o.polish && can64 && (worst < floor32 || stalled)) {
-            prec = 0;
-            if ((rc = apply_real(c, B_X, B_HX, m, 0, stats))) return rc;
-            if (mp > 0 && (rc = apply_real(c, B_P, B_HP, mp, 0, stats))) return rc;
-            if ((rc = rr_block_real(c, m, theta))) return rc;
-            best_eta = 1e300;
-            continue;
-        }
-        ++it;
-        if (prec == 0 && p->opts.precision == 1) ++polished;
-
-        // active set; W = M R_A (or the learned map of R_A), packed two per column
-        std::vector<int> act;
-        for (int j = 0; j < m; ++j)
-            if (eta[j] > o.tol) act.push_back(j);
-        const int ma = (int)act.size();
-        std::vector<RVec> Ract(ma);
-        for (int a = 0; a < ma; ++a) Ract[a] = {c.col(B_T1, act[a] >> 1), act[a] & 1};
-        unsigned long long rparts = 0;
-        const ColPtrs rsrc = colptrs(Ract, &rparts);
-        const int mac = (ma + 1) / 2;
-        ColPtrs wdst{};
-        for (int j = 0; j < mac; ++j) wdst.p[j] = c.col(B_W, j);
-        bool lp_used = false;
-        if (lp) {
-            // R_A packed into the (still free) HW buffer, then W = T(R_A)
-            ColPtrs rp{};
-            for (int j = 0; j < mac; ++j) rp.p[j] = c.col(B_HW, j);
-            CHECK_HIP(gather_pairs(rsrc, rparts, ma, rp, nullptr, N, st));
-            if (learned_apply(lp, p, rp, wdst, mac, st) == IWFPM_OK) lp_used = true;
-            else {
-                fallback = 1;
-                lp = nullptr;
-            }
-        }
-        if (!lp_used) CHECK_HIP(gather_pairs(rsrc, rparts, ma, wdst, Mdiag, N, st));
-        std::vector<RVec> Pa = rvecs(c, B_P, 0, mp), HPa = rvecs(c, B_HP, 0, mp);
-        const int mq = mp;
-        int mw = 0;
-        {
-            std::vector<RVec> XP = rvecs(c, B_X, 0, m);
-            XP.insert(XP.end(), Pa.begin(), Pa.end());
-            const int nx = (int)XP.size();
-            std::vector<RVec> XPW = XP, Wv = rvecs(c, B_W, 0, ma);
-            XPW.insert(XPW.end(), Wv.begin(), Wv.end());
-            std::vector<cd> Gall, Cm;
-            if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
-            if (lp_used) {
-                bool finite = true;
-                for (int j = 0; j < ma; ++j)
-                    finite = finite && std::isfinite(Gall[(size_t)(nx + j) + (size_t)j * (nx + ma)].real());
-                if (!finite) {
-                    fallback = 1;
-                    lp = nullptr;
-                    CHECK_HIP(gather_pairs(rsrc, rparts, ma, wdst, Mdiag, N, st));
-                    if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
-                }
-            }
-            bool done = false;
-            if (!explicit_ortho) {
-                // one explicit projection, then the second one and SVQB in coefficient space
-                const std::vector<cd> G1 = neg_projection(Gall, nx, ma);
-                if ((rc = dev_lincomb_real(c, XP, Wv, G1, nx, 0, 1.0))) return rc;
-                if ((rc = host_gram_real(c, XPW, Wv, Gall))) return rc;
-                if (ortho_coefficients(Gall, nx, ma, Cm, mw)) {
-                    if ((rc = dev_lincomb_real(c, XPW, rvecs(c, B_T1, 0, mw), Cm, nx + ma, 0, 0.0))) return rc;
-                    done = true;
-                }
-            }
-            if (!done) {
-                ++reortho;
-                for (int pass = 0; pass < 2; ++pass) {
-                    std::vector<cd> G;
-                    if ((rc = host_gram_real(c, XP, Wv, G))) return rc;
-                    for (auto& g : G) g = -g;
-                    if ((rc = dev_lincomb_real(c, XP, Wv, G, nx, 0, 1.0))) return rc;
-                }
-                std::vector<cd> G, T;
-                if ((rc = host_gram_real(c, Wv, Wv, G))) return rc;
-                hermitian_part(G, ma);
-                mw = svqb(G, ma, T, 1e-10);
-                if ((rc = dev_lincomb_real(c, Wv, rvecs(c, B_T1, 0, mw), T, ma, 0, 0.0))) return rc;
-            }
-            std::swap(s->buf[B_W], s->buf[B_T1]);
-        }
-        if ((rc = apply_real(c, B_W, B_HW, mw, prec, stats))) return rc;
-        // Rayleigh-Ritz on S = [X W P_A]
-        const int ns = m + mw + mq;
-        std::vector<RVec> S = rvecs(c, B_X, 0, m), HS = rvecs(c, B_HX, 0, m);
-        {
-            auto Wn = rvecs(c, B_W, 0, mw), HWn = rvecs(c, B_HW, 0, mw);
-            S.insert(S.end(), Wn.begin(), Wn.end());
-            HS.insert(HS.end(), HWn.begin(), HWn.end());
-        }
-        Pa = rvecs(c, B_P, 0, mq);
-        HPa = rvecs(c, B_HP, 0, mq);
-        S.insert(S.end(), Pa.begin(), Pa.end());
-        HS.insert(HS.end(), HPa.begin(), HPa.end());
-        std::vector<double> th;
-        std::vector<cd> U;
-        int mpn = 0;
-        {
-            std::vector<RVec> HR(HS.begin() + m, HS.end());
-            std::vector<cd> G;
-            if ((rc = host_gram_real(c, S, HR, G))) return rc;
-            mpn = rr_coefficients(G, theta, m, ns, act, th, U);
-        }
-        // [X_new | P_new] = S U, [HX_new | HP_new] = HS U
-        {
-            std::vector<RVec> out = rvecs(c, B_XN, 0, m), hout = rvecs(c, B_HXN, 0, m);
-            auto pn = rvecs(c, B_PN, 0, mpn), hpn = rvecs(c, B_HPN, 0, mpn);
-            out.insert(out.end(), pn.begin(), pn.end());
-            hout.insert(hout.end(), hpn.begin(), hpn.end());
-            if ((rc = dev_lincomb_real(c, S, out, U, ns, 0, 0.0))) return rc;
-            if ((rc = dev_lincomb_real(c, HS, hout, U, ns, 0, 0.0))) return rc;
-            std::swap(s->buf[B_X], s->buf[B_XN]);
-            std::swap(s->buf[B_HX], s->buf[B_HXN]);
-            std::swap(s->buf[B_P], s->buf[B_PN]);
-            std::swap(s->buf[B_HP], s->buf[B_HPN]);
-            mp = mpn;
-        }
-        theta.assign(th.begin(), th.begin() + m);
-    }
-    if (stats) {
-        stats->iterations = it;
-        stats->restarts = 0;
-        stats->fallback = fallback;
-        stats->polished = polished;
-        int conv = 0;
-        for (int j = 0; j < nev; ++j) conv += eta[j] <= o.tol;
-        stats->converged = conv;
-    }
-    for (int j = 0; j < nev; ++j) {
-        evals[j] = theta[j];
-        if (eta_out) eta_out[j] = eta[j];
-    }
-    if (evecs) {
-        unsigned long long parts = 0;
-        const ColPtrs src = colptrs(rvecs(c, B_X, 0, nev), &parts);
-        ColPtrs dst{};
-        for (int j = 0; j < nev; ++j) dst.p[j] = (double2*)evecs + (size_t)j * N;
-        CHECK_HIP(unpack_real(src, parts, nev, dst, N, st));
-    }
-    if ((rc = sync(c))) return rc;
-    return status;
-}
-
 // every potential coefficient real: H~ is real symmetric
 static bool real_symmetric(const iwfpm_plan_s* p) {
     for (double v : p->vim)
@@ -1842,11 +1261,6 @@ static bool real_symmetric(const iwfpm_plan_s* p) {
     return true;
 }
 
-int eigs_capture(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, Capture* cap, double* evals, void* evecs,
-                 hipStream_t st) {
-    if (o.nev < 1 || o.nev > p->geom.N || !cap || cap->ncol > o.nev) return IWFPM_ERR_ARG;
-    return run(p, o, nullptr, evals, evecs, nullptr, nullptr, st, cap);
-}
 
 // ---------------------------------------------------------------------------
 // lock-step block LOBPCG for a batch of plans (e.g. a sweep of couplings):
@@ -2044,515 +1458,7 @@ static int batch_lincomb(BatchOps& bo, const std::vector<LinReq>& reqs) {
     return IWFPM_OK;
 }
 
-struct BInst {
-    iwfpm_plan_s* p = nullptr;
-    Solver* s = nullptr;
-    Ctx c{};
-    int prec = 0;
-    bool can64 = false;
-    bool done = false;
-    bool cleaned = false;  // X re-orthonormalised since its pairs converged
-    int status = IWFPM_OK;
-    std::vector<double> theta, eta;
-    int mp = 0, it = 0, polished = 0;
-    long long matvecs = 0;
-    double best_eta = 1e300, floor32 = 0.0, hnorm = 0.0;
-    int best_it = 0;
-    LearnedPrecond* lp = nullptr;  // learned preconditioner while it is in use
-    int fallback = 0;
-    // per-iteration
-    bool active = false;
-    std::vector<int> act;
-    int ma = 0, mq = 0, mw = 0, ns = 0;
-    std::vector<cd> T, U;
-    std::vector<double> th;
-    int mpn = 0;
-};
-
-static int run_batched(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, double* evals, double* eta_out,
-                       iwfpm_stats* stats, hipStream_t st) {
-    const int nev = o.nev;
-    const int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
-    if (m < nev || 3 * m > kMaxCols) return IWFPM_ERR_ARG;
-    const bool explicit_ortho = force_explicit_ortho();
-    std::vector<BInst> in(B);
-    int rc;
-    for (int i = 0; i < B; ++i) {
-        BInst& b = in[i];
-        b.p = plans[i];
-        if (m > b.p->geom.N) return IWFPM_ERR_ARG;
-        if ((rc = solver_ensure(b.p, m))) return rc;
-        int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
-        if ((rc = solver_precond(b.p, pk))) return rc;
-        b.s = (Solver*)b.p->solver;
-        b.c = Ctx{b.p, b.s, st, b.p->geom.N};
-        b.prec = b.p->opts.precision;
-        if (!b.p->sched[b.prec].ok) b.prec = 1 - b.prec;
-        if (!b.p->sched[b.prec].ok) return IWFPM_ERR_UNSUPPORTED;
-        b.can64 = b.p->sched[0].ok;
-        b.hnorm = b.p->lam_max + b.p->vsum_abs;
-        b.floor32 = 30.0 * 6e-8 * b.p->vsum_abs / b.hnorm;
-        b.eta.assign(m, 1.0);
-        if (o.precond == IWFPM_PRECOND_LEARNED) {
-            b.lp = b.p->learned;
-            if (!b.lp || !learned_ready(b.lp, b.p)) return IWFPM_ERR_WEIGHTS;
-        }
-    }
-    BatchOps bo;
-    bo.st = st;
-    CHECK_HIP(hipEventCreateWithFlags(&bo.staged, hipEventDisableTiming));
-    // batched applies, one batch object per convolution precision
-    std::vector<iwfpm_plan_t> pl(plans, plans + B);
-    iwfpm_batch_t bat[2] = {nullptr, nullptr};
-    struct BatchGuard {
-        iwfpm_batch_t* b;
-        ~BatchGuard() {
-            for (int k = 0; k < 2; ++k)
-                if (b[k]) iwfpm_batch_destroy(b[k]);
-        }
-    } bguard{bat};
-    for (int k = 0; k < 2; ++k) {
-        bool ok = true;
-        // plans on the five-pass schedule are applied one by one
-        for (auto* p : pl) ok = ok && p->sched[k].ok && (p->sched[k].fused || p->sched[k].pd.split_mid == 0);
-        if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
-            return rc;
-    }
-    // apply H to `cnt[i]` columns of buffer bin into bout for every instance, by precision
-    auto apply_all = [&](int bin, int bout, const std::vector<int>& cnt, const std::vector<int>& precs) -> int {
-        for (int k = 0; k < 2; ++k) {
-            std::vector<const void*> x(B, nullptr);
-            std::vector<void*> y(B, nullptr);
-            std::vector<int> nv(B, 0);
-            bool any = false;
-            for (int i = 0; i < B; ++i)
-                if (cnt[i] > 0 && precs[i] == k) {
-                    x[i] = in[i].c.col(bin, 0);
-                    y[i] = in[i].c.col(bout, 0);
-                    nv[i] = cnt[i];
-                    in[i].matvecs += cnt[i];
-                    any = true;
-                }
-            if (!any) continue;
-            if (!bat[k]) {
-                for (int i = 0; i < B; ++i)
-                    if (nv[i] && (rc = plan_apply(in[i].p, x[i], y[i], nv[i], k, st))) return rc;
-                continue;
-            }
-            if ((rc = iwfpm_batch_apply(bat[k], x.data(), y.data(), nv.data(), st))) return rc;
-        }
-        return IWFPM_OK;
-    };
-    // start blocks, orthonormalised
-    for (int i = 0; i < B; ++i) CHECK_HIP(randn(in[i].c.col(B_X, 0), in[i].c.N * m, o.seed + (unsigned long long)i, st));
-    {
-        std::vector<GramReq> g(B);
-        for (int i = 0; i < B; ++i) g[i] = {cols(in[i].c, B_X, 0, m), cols(in[i].c, B_X, 0, m), in[i].c.N};
-        std::vector<std::vector<cd>> G;
-        if ((rc = batch_gram(bo, g, G))) return rc;
-        std::vector<int> bad(B, 0);
-        parallel_for(B, [&](int i) { bad[i] = svqb(G[i], m, in[i].T) < m; });
-        for (int i = 0; i < B; ++i)
-            if (bad[i]) return IWFPM_ERR_NUMERIC;
-        std::vector<LinReq> l(B);
-        for (int i = 0; i < B; ++i) l[i] = {cols(in[i].c, B_X, 0, m), cols(in[i].c, B_XN, 0, m), &in[i].T, m, 0, 0.0, in[i].c.N};
-        if ((rc = batch_lincomb(bo, l))) return rc;
-        for (auto& b : in) std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
-    }
-    std::vector<int> all_m(B, m), precs(B);
-    for (int i = 0; i < B; ++i) precs[i] = in[i].prec;
-    if ((rc = apply_all(B_X, B_HX, all_m, precs))) return rc;
-    // Rayleigh-Ritz of the start blocks (and of blocks switched to float64 below)
-    auto rr_blocks = [&](const std::vector<int>& which) -> int {
-        if (which.empty()) return IWFPM_OK;
-        std::vector<GramReq> g;
-        for (int i : which) {
-            std::vector<double2*> XHX = cols(in[i].c, B_X, 0, m), HX = cols(in[i].c, B_HX, 0, m);
-            XHX.insert(XHX.end(), HX.begin(), HX.end());
-            g.push_back({cols(in[i].c, B_X, 0, m), XHX, in[i].c.N});
-        }
-        std::vector<std::vector<cd>> G;
-        if ((rc = batch_gram(bo, g, G))) return rc;
-        std::vector<std::vector<cd>> C(which.size());
-        std::vector<char> okt(which.size(), 1);
-        parallel_for((int)which.size(), [&](int k) { okt[k] = rr_transform(G[k], m, in[which[k]].theta, C[k]); });
-        for (char ok : okt)
-            if (!ok) return IWFPM_ERR_NUMERIC;
-        std::vector<LinReq> l;
-        for (size_t k = 0; k < which.size(); ++k) {
-            BInst& b = in[which[k]];
-            l.push_back({cols(b.c, B_X, 0, m), cols(b.c, B_XN, 0, m), &C[k], m, 0, 0.0, b.c.N});
-            l.push_back({cols(b.c, B_HX, 0, m), cols(b.c, B_HXN, 0, m), &C[k], m, 0, 0.0, b.c.N});
-        }
-        if ((rc = batch_lincomb(bo, l))) return rc;
-        for (int i : which) {
-            std::swap(in[i].s->buf[B_X], in[i].s->buf[B_XN]);
-            std::swap(in[i].s->buf[B_HX], in[i].s->buf[B_HXN]);
-        }
-        return IWFPM_OK;
-    };
-    {
-        std::vector<int> allidx(B);
-        for (int i = 0; i < B; ++i) allidx[i] = i;
-        if ((rc = rr_blocks(allidx))) return rc;
-    }
-    for (;;) {
-        std::vector<int> live;
-        for (int i = 0; i < B; ++i)
-            if (!in[i].done) live.push_back(i);
-        if (live.empty()) break;
-        // residuals and their norms, one launch for all live instances
-        {
-            std::vector<ResJob> jobs;
-            int blocks = 0, outs = 0;
-            long long part = 0;
-            for (int i : live) {
-                BInst& b = in[i];
-                ResJob jb{};
-                for (int j = 0; j < m; ++j) {
-                    jb.HX.p[j] = b.c.col(B_HX, j);
-                    jb.X.p[j] = b.c.col(B_X, j);
-                    jb.R.p[j] = b.c.col(B_T1, j);
-                    jb.theta.v[j] = b.theta[j];
-                }
-                jb.m = m;
-                jb.N = b.c.N;
-                jb.nb = (int)std::min<long long>(256, std::max<long long>(1, (jb.N + 1023) / 1024));
-                jb.rows_per_block = (jb.N + jb.nb - 1) / jb.nb;
-                jb.start = blocks;
-                jb.out_start = outs;
-                jb.part_off = part;
-                blocks += jb.nb;
-                outs += m;
-                part += (long long)jb.nb * m;
-                jobs.push_back(jb);
-            }
-            if ((rc = bo.wait_staged())) return rc;
-            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(ResJob)))) return rc;
-            if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(ResJob)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
-            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(ResJob));
-            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
-            CHECK_HIP(residual_norm_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
-                                            (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, st));
-            CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, outs * sizeof(double), hipMemcpyDeviceToHost, st));
-            CHECK_HIP(hipStreamSynchronize(st));
-            const double* h = (const double*)bo.h_out;
-            for (size_t k = 0; k < live.size(); ++k) {
-                BInst& b = in[live[k]];
-                for (int j = 0; j < m; ++j) {
-                    b.eta[j] = std::sqrt(std::max(0.0, h[k * m + j])) / (b.hnorm + std::fabs(b.theta[j]));
-                    if (!std::isfinite(b.eta[j])) {
-                        b.done = true;
-                        b.status = IWFPM_ERR_NUMERIC;
-                    }
-                }
-            }
-        }
-        // per-instance decisions
-        std::vector<int> to64, iter, to_clean;
-        for (int i : live) {
-            BInst& b = in[i];
-            if (b.done) continue;
-            int conv = 0;
-            double worst = 0.0;
-            for (int j = 0; j < nev; ++j) {
-                conv += b.eta[j] <= o.tol;
-                worst = std::max(worst, b.eta[j]);
-            }
-            if (conv == nev) {
-                if ((b.prec == 0 || !b.can64) && b.cleaned) b.done = true;
-                else if (b.prec == 0 || !b.can64) to_clean.push_back(i);  // re-orthonormalise X once more
-                else to64.push_back(i);  // confirm with float64 applies
-                if (!b.done) b.cleaned = true;
-                continue;
-            }
-            if (b.it >= o.maxit) {
-                b.done = true;
-                b.status = IWFPM_ERR_NOCONV;
-                continue;
-            }
-            bool stalled = false;
-            if (worst < 0.5 * b.best_eta) {
-                b.best_eta = worst;
-                b.best_it = b.it;
-            } else {
-                stalled = worst < 1e-5 && b.it - b.best_it >= 20;
-            }
-            if (b.lp && b.it - b.best_it >= 50) {
-                // learned preconditioner stagnating: continue with M
-                b.fallback = 1;
-                b.lp = nullptr;
-                b.best_it = b.it;
-            }
-            if (b.prec == 1 && o.polish && b.can64 && (worst < b.floor32 || stalled)) {
-                to64.push_back(i);
-                continue;
-            }
-            iter.push_back(i);
-        }
-        if ((rc = rr_blocks(to_clean))) return rc;
-        if (!to64.empty()) {
-            std::vector<int> cx(B, 0), cp(B, 0), p0(B, 0);
-            for (int i : to64) {
-                in[i].prec = 0;
-                in[i].best_eta = 1e300;
-                cx[i] = m;
-                cp[i] = in[i].mp;
-            }
-            if ((rc = apply_all(B_X, B_HX, cx, p0))) return rc;
-            if ((rc = apply_all(B_P, B_HP, cp, p0))) return rc;
-            if ((rc = rr_blocks(to64))) return rc;
-        }
-        if (iter.empty()) continue;
-        for (int i : iter) {
-            BInst& b = in[i];
-            ++b.it;
-            if (b.prec == 0 && b.p->opts.precision == 1) ++b.polished;
-            b.act.clear();
-            for (int j = 0; j < m; ++j)
-                if (b.eta[j] > o.tol) b.act.push_back(j);
-            b.ma = (int)b.act.size();
-            b.mq = b.mp;
-        }
-        // W = T(R_A) (learned, per instance) or M R_A (all plain instances in one launch)
-        {
-            std::vector<PreJob> jobs;
-            int blocks = 0;
-            for (int i : iter) {
-                BInst& b = in[i];
-                if (b.lp) {
-                    ColPtrs r{}, w{};
-                    for (int a = 0; a < b.ma; ++a) {
-                        r.p[a] = b.c.col(B_T1, b.act[a]);
-                        w.p[a] = b.c.col(B_W, a);
-                    }
-                    if (learned_apply(b.lp, b.p, r, w, b.ma, st) == IWFPM_OK) continue;
-                    b.fallback = 1;
-                    b.lp = nullptr;
-                }
-                PreJob jb{};
-                for (int a = 0; a < b.ma; ++a) {
-                    jb.R.p[a] = b.c.col(B_T1, b.act[a]);
-                    jb.W.p[a] = b.c.col(B_W, a);
-                }
-                jb.m = b.ma;
-                jb.M = (const double*)b.s->M.ptr;
-                jb.N = b.c.N;
-                jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
-                jb.start = blocks;
-                blocks += jb.nb;
-                jobs.push_back(jb);
-            }
-            if (!jobs.empty()) {
-                if ((rc = bo.wait_staged())) return rc;
-                if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(PreJob)))) return rc;
-                if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(PreJob)))) return rc;
-                std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(PreJob));
-                CHECK_HIP(
-                    hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(PreJob), hipMemcpyHostToDevice, st));
-                CHECK_HIP(hipEventRecord(bo.staged, st));
-                CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
-            }
-        }
-        // W <- orthonormal basis of the part of W orthogonal to [X P]: one
-        // explicit projection with the Gram [X P W]^H W, then the second
-        // projection and SVQB in coefficient space (explicit twice as fallback)
-        {
-            std::vector<GramReq> g;
-            std::vector<std::vector<double2*>> XPW(iter.size());
-            for (size_t k = 0; k < iter.size(); ++k) {
-                BInst& b = in[iter[k]];
-                XPW[k] = cols(b.c, B_X, 0, m);
-                auto P = cols(b.c, B_P, 0, b.mq);
-                XPW[k].insert(XPW[k].end(), P.begin(), P.end());
-                auto Wc = cols(b.c, B_W, 0, b.ma);
-                XPW[k].insert(XPW[k].end(), Wc.begin(), Wc.end());
-                g.push_back({XPW[k], Wc, b.c.N});
-            }
-            std::vector<std::vector<cd>> Gall;
-            if ((rc = batch_gram(bo, g, Gall))) return rc;
-            std::vector<size_t> two(iter.size());
-            for (size_t k = 0; k < iter.size(); ++k) two[k] = k;
-            if (!two.empty() && !explicit_ortho) {
-                // one explicit projection, then the second one and SVQB in coefficient space
-                std::vector<std::vector<cd>> G1(two.size());
-                std::vector<LinReq> lp1;
-                std::vector<GramReq> g2;
-                for (size_t t = 0; t < two.size(); ++t) {
-                    BInst& b = in[iter[two[t]]];
-                    const int nx = m + b.mq;
-                    G1[t] = neg_projection(Gall[two[t]], nx, b.ma);
-                    std::vector<double2*> XP(XPW[two[t]].begin(), XPW[two[t]].begin() + nx);
-                    lp1.push_back({XP, cols(b.c, B_W, 0, b.ma), &G1[t], nx, 0, 1.0, b.c.N});
-                    g2.push_back({XPW[two[t]], cols(b.c, B_W, 0, b.ma), b.c.N});
-                }
-                if ((rc = batch_lincomb(bo, lp1))) return rc;
-                std::vector<std::vector<cd>> Gall2;
-                if ((rc = batch_gram(bo, g2, Gall2))) return rc;
-                std::vector<char> ok2(two.size(), 0);
-                std::vector<std::vector<cd>> Cm2(two.size());
-                parallel_for((int)two.size(), [&](int t) {
-                    BInst& b = in[iter[two[t]]];
-                    ok2[t] = ortho_coefficients(Gall2[t], m + b.mq, b.ma, Cm2[t], b.mw);
-                });
-                std::vector<LinReq> l2;
-                std::vector<size_t> rest;
-                for (size_t t = 0; t < two.size(); ++t) {
-                    BInst& b = in[iter[two[t]]];
-                    if (ok2[t])
-                        l2.push_back({XPW[two[t]], cols(b.c, B_T1, 0, b.mw), &Cm2[t], m + b.mq + b.ma, 0, 0.0, b.c.N});
-                    else
-                        rest.push_back(two[t]);
-                }
-                if ((rc = batch_lincomb(bo, l2))) return rc;
-                two.swap(rest);
-            }
-            if (!two.empty()) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    std::vector<GramReq> g2;
-                    std::vector<std::vector<double2*>> XP(two.size());
-                    for (size_t t = 0; t < two.size(); ++t) {
-                        BInst& b = in[iter[two[t]]];
-                        XP[t].assign(XPW[two[t]].begin(), XPW[two[t]].begin() + m + b.mq);
-                        g2.push_back({XP[t], cols(b.c, B_W, 0, b.ma), b.c.N});
-                    }
-                    std::vector<std::vector<cd>> G;
-                    if ((rc = batch_gram(bo, g2, G))) return rc;
-                    std::vector<LinReq> l2;
-                    for (size_t t = 0; t < two.size(); ++t) {
-                        for (auto& v : G[t]) v = -v;
-                        BInst& b = in[iter[two[t]]];
-                        l2.push_back({XP[t], cols(b.c, B_W, 0, b.ma), &G[t], (int)XP[t].size(), 0, 1.0, b.c.N});
-                    }
-                    if ((rc = batch_lincomb(bo, l2))) return rc;
-                }
-                std::vector<GramReq> g2;
-                for (size_t k : two) {
-                    BInst& b = in[iter[k]];
-                    g2.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_W, 0, b.ma), b.c.N});
-                }
-                std::vector<std::vector<cd>> G;
-                if ((rc = batch_gram(bo, g2, G))) return rc;
-                parallel_for((int)two.size(), [&](int t) {
-                    BInst& b = in[iter[two[t]]];
-                    b.mw = svqb(G[t], b.ma, b.T, 1e-10);
-                });
-                std::vector<LinReq> l2;
-                for (size_t k : two) {
-                    BInst& b = in[iter[k]];
-                    l2.push_back({cols(b.c, B_W, 0, b.ma), cols(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
-                }
-                if ((rc = batch_lincomb(bo, l2))) return rc;
-            }
-            for (int i : iter) std::swap(in[i].s->buf[B_W], in[i].s->buf[B_T1]);
-        }
-        // HW = H W
-        {
-            std::vector<int> cnt(B, 0), pr(B, 0);
-            for (int i : iter) {
-                cnt[i] = in[i].mw;
-                pr[i] = in[i].prec;
-            }
-            if ((rc = apply_all(B_W, B_HW, cnt, pr))) return rc;
-        }
-        // Rayleigh-Ritz: G = [X W P]^H [HW HP] for all, small problems on host threads
-        std::vector<std::vector<double2*>> S(iter.size()), HS(iter.size());
-        {
-            std::vector<GramReq> g;
-            for (size_t k = 0; k < iter.size(); ++k) {
-                BInst& b = in[iter[k]];
-                S[k] = cols(b.c, B_X, 0, m);
-                HS[k] = cols(b.c, B_HX, 0, m);
-                for (int j = 0; j < b.mw; ++j) {
-                    S[k].push_back(b.c.col(B_W, j));
-                    HS[k].push_back(b.c.col(B_HW, j));
-                }
-                for (int j = 0; j < b.mq; ++j) {
-                    S[k].push_back(b.c.col(B_P, j));
-                    HS[k].push_back(b.c.col(B_HP, j));
-                }
-                b.ns = (int)S[k].size();
-                g.push_back({S[k], std::vector<double2*>(HS[k].begin() + m, HS[k].end()), b.c.N});
-            }
-            std::vector<std::vector<cd>> G;
-            if ((rc = batch_gram(bo, g, G))) return rc;
-            parallel_for((int)iter.size(), [&](int k) {
-                BInst& b = in[iter[k]];
-                b.mpn = rr_coefficients(G[k], b.theta, m, b.ns, b.act, b.th, b.U);
-            });
-        }
-        // [X_new | P_new] = S U, [HX_new | HP_new] = HS U
-        {
-            std::vector<LinReq> l;
-            for (size_t k = 0; k < iter.size(); ++k) {
-                BInst& b = in[iter[k]];
-                std::vector<double2*> out = cols(b.c, B_XN, 0, m), hout = cols(b.c, B_HXN, 0, m);
-                for (int j = 0; j < b.mpn; ++j) {
-                    out.push_back(b.c.col(B_PN, j));
-                    hout.push_back(b.c.col(B_HPN, j));
-                }
-                l.push_back({S[k], out, &b.U, b.ns, 0, 0.0, b.c.N});
-                l.push_back({HS[k], hout, &b.U, b.ns, 0, 0.0, b.c.N});
-            }
-            if ((rc = batch_lincomb(bo, l))) return rc;
-            for (int i : iter) {
-                BInst& b = in[i];
-                std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
-                std::swap(b.s->buf[B_HX], b.s->buf[B_HXN]);
-                std::swap(b.s->buf[B_P], b.s->buf[B_PN]);
-                std::swap(b.s->buf[B_HP], b.s->buf[B_HPN]);
-                b.mp = b.mpn;
-                b.theta.assign(b.th.begin(), b.th.begin() + m);
-            }
-        }
-    }
-    CHECK_HIP(hipStreamSynchronize(st));
-    int worst_status = IWFPM_OK;
-    for (int i = 0; i < B; ++i) {
-        BInst& b = in[i];
-        for (int j = 0; j < nev; ++j) {
-            evals[(size_t)i * nev + j] = b.theta[j];
-            if (eta_out) eta_out[(size_t)i * nev + j] = b.eta[j];
-        }
-        if (stats) {
-            iwfpm_stats& s = stats[i];
-            s.iterations = b.it;
-            s.matvecs = b.matvecs;
-            s.polished = b.polished;
-            s.fallback = b.fallback;
-            int conv = 0;
-            for (int j = 0; j < nev; ++j) conv += b.eta[j] <= o.tol;
-            s.converged = conv;
-        }
-        if (b.status != IWFPM_OK && worst_status == IWFPM_OK) worst_status = b.status;
-    }
-    return worst_status;
-}
-}  // namespace iwfpm
-
-using namespace iwfpm;
-
-extern "C" {
-
-void iwfpm_default_eigs_opts(iwfpm_eigs_opts* o) {
-    if (!o) return;
-    o->nev = 8;
-    o->block = 0;
-    o->tol = 1e-8;
-    o->maxit = 1000;
-    o->precond = IWFPM_PRECOND_PLAIN;
-    o->seed = 2404045070ull;
-    o->polish = 1;
-    o->arith = 0;
-}
-
-// ---------------------------------------------------------------------------
-// Real-symmetric lock-step batched LOBPCG (two real trial vectors per complex
-// column, as run_real), every tall operation one launch over a job table.
-// ---------------------------------------------------------------------------
+// batched Grams and combinations over real trial vectors (two per column)
 
 struct GramReqR {
     std::vector<RVec> L, R;
@@ -2681,13 +1587,362 @@ static int batch_lincomb_real(BatchOps& bo, const std::vector<LinReqR>& reqs) {
     return IWFPM_OK;
 }
 
-static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, double* evals,
-                            double* eta_out, iwfpm_stats* stats, hipStream_t st) {
+
+// ---------------------------------------------------------------------------
+// Block LOBPCG for the lowest eigenpairs of H~ (Knyazev's method with soft
+// locking; the reading of the paper's Alg. 2 is the block method for the
+// smallest eigenvalues of the Hermitian matrix): one iteration body for a
+// single solve (B = 1) and for B plans in lock step, over both ways of holding
+// the trial vectors.
+//   CplxRoute: one trial vector per complex column.
+//   RealRoute: every potential coefficient real, so H~ is real symmetric and
+//              its eigenvectors can be taken real: real trial vectors, two per
+//              complex column (real part, imaginary part); the apply maps a
+//              pair to its image pair, the preconditioners act on both halves
+//              alike, the block algebra runs on the pair kernels (2 x 2 real
+//              coefficient blocks), and the small matrices are complex arrays
+//              with zero imaginary parts, which the host solvers keep real.
+// Every tall operation of a phase runs for all live instances together: a
+// single solve through the one-plan kernels (Grams reduced on the device and
+// read back, combinations with coefficients staged through a ring of slots),
+// a batch through one launch over a job table per phase; the applies of a
+// batch go through its persistent, graph-replayed batched launch; the small
+// dense problems run on host threads, one per instance.
+// ---------------------------------------------------------------------------
+
+struct CplxRoute {
+    using V = double2*;
+    static constexpr bool real = false;
+    static std::vector<V> vecs(Ctx& c, int b, int v0, int cnt) { return cols(c, b, v0, cnt); }
+    static int columns(int nv) { return nv; }
+};
+struct RealRoute {
+    using V = RVec;
+    static constexpr bool real = true;
+    static std::vector<V> vecs(Ctx& c, int b, int v0, int cnt) { return rvecs(c, b, v0, cnt); }
+    static int columns(int nv) { return (nv + 1) / 2; }
+};
+
+// one solve of the batch
+struct BInst {
+    iwfpm_plan_s* p = nullptr;
+    Solver* s = nullptr;
+    Ctx c{};
+    int prec = 0;
+    bool can64 = false;
+    bool done = false;
+    bool cleaned = false;  // X re-orthonormalised since its pairs converged
+    int status = IWFPM_OK;
+    std::vector<double> theta, eta;
+    int mp = 0, it = 0, polished = 0, reortho = 0;
+    long long matvecs = 0;
+    double best_eta = 1e300, floor32 = 0.0, hnorm = 0.0;
+    int best_it = 0;
+    LearnedPrecond* lp = nullptr;  // learned preconditioner while it is in use
+    int fallback = 0;
+    // per-iteration
+    std::vector<int> act;
+    int ma = 0, mq = 0, mw = 0, ns = 0;
+    bool lp_used = false;
+    std::vector<cd> T, U;
+    std::vector<double> th;
+    int mpn = 0;
+};
+
+template <class Rt>
+struct GramQ {
+    Ctx* c;
+    std::vector<typename Rt::V> L, R;
+};
+template <class Rt>
+struct LinQ {
+    Ctx* c;
+    std::vector<typename Rt::V> A, Y;
+    const std::vector<cd>* C;
+    int ldc;
+    double beta;
+};
+
+// the tall operations of one phase, for a single solve or a batch
+struct Tall {
+    BatchOps bo;
+    bool single = true;
+};
+
+template <class Rt>
+static int tall_grams(Tall& t, const std::vector<GramQ<Rt>>& q, std::vector<std::vector<cd>>& out) {
+    if (t.single) {
+        out.assign(q.size(), {});
+        for (size_t k = 0; k < q.size(); ++k) {
+            int rc;
+            if constexpr (Rt::real) rc = host_gram_real(*q[k].c, q[k].L, q[k].R, out[k]);
+            else rc = host_gram(*q[k].c, q[k].L, q[k].R, out[k]);
+            if (rc) return rc;
+        }
+        return IWFPM_OK;
+    }
+    if constexpr (Rt::real) {
+        std::vector<GramReqR> r;
+        for (const auto& x : q) r.push_back({x.L, x.R, x.c->N});
+        return batch_gram_real(t.bo, r, out);
+    } else {
+        std::vector<GramReq> r;
+        for (const auto& x : q) r.push_back({x.L, x.R, x.c->N});
+        return batch_gram(t.bo, r, out);
+    }
+}
+
+template <class Rt>
+static int tall_lincombs(Tall& t, const std::vector<LinQ<Rt>>& q) {
+    if (t.single) {
+        for (const auto& x : q) {
+            int rc;
+            if constexpr (Rt::real) rc = dev_lincomb_real(*x.c, x.A, x.Y, *x.C, x.ldc, 0, x.beta);
+            else rc = dev_lincomb(*x.c, x.A, x.Y, *x.C, x.ldc, 0, x.beta);
+            if (rc) return rc;
+        }
+        return IWFPM_OK;
+    }
+    if constexpr (Rt::real) {
+        std::vector<LinReqR> r;
+        for (const auto& x : q) r.push_back({x.A, x.Y, x.C, x.ldc, 0, x.beta, x.c->N});
+        return batch_lincomb_real(t.bo, r);
+    } else {
+        std::vector<LinReq> r;
+        for (const auto& x : q) r.push_back({x.A, x.Y, x.C, x.ldc, 0, x.beta, x.c->N});
+        return batch_lincomb(t.bo, r);
+    }
+}
+
+// R = HX - X theta and eta_j = |r_j| / ((|H|_est + |theta_j|) |x_j|) (x_j
+// unit) for every live instance; a non-finite value ends that instance
+template <class Rt>
+static int tall_residuals(Tall& t, std::vector<BInst>& in, const std::vector<int>& live, int m) {
+    const int mc = Rt::columns(m);
+    const int per = Rt::real ? 2 * mc : m;  // norms per instance
+    std::vector<double> nrm((size_t)live.size() * per, 0.0);
+    if (t.single) {
+        for (size_t k = 0; k < live.size(); ++k) {
+            BInst& b = in[live[k]];
+            ColPtrs hx{}, x{}, r{};
+            Reals th{};
+            for (int j = 0; j < mc; ++j) {
+                hx.p[j] = b.c.col(B_HX, j);
+                x.p[j] = b.c.col(B_X, j);
+                r.p[j] = b.c.col(B_T1, j);
+            }
+            for (int v = 0; v < per; ++v) th.v[v] = v < m ? b.theta[v] : 0.0;
+            double* dNorm = (double*)((double2*)b.s->small.ptr + 96 * 96);
+            if constexpr (Rt::real)
+                CHECK_HIP(residual_norm_pairs(hx, x, r, th, mc, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks,
+                                              dNorm, b.c.st));
+            else
+                CHECK_HIP(residual_norm(hx, x, r, th, m, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks, dNorm,
+                                        b.c.st));
+            double* h = (double*)(b.s->hsmall + 96 * 96);
+            CHECK_HIP(hipMemcpyAsync(h, dNorm, per * sizeof(double), hipMemcpyDeviceToHost, b.c.st));
+            if (int rc = sync(b.c)) return rc;
+            std::copy(h, h + per, nrm.begin() + (size_t)k * per);
+        }
+    } else {
+        BatchOps& bo = t.bo;
+        std::vector<ResJob> jobs;
+        int blocks = 0, outs = 0;
+        long long part = 0;
+        for (int i : live) {
+            BInst& b = in[i];
+            ResJob jb{};
+            for (int j = 0; j < mc; ++j) {
+                jb.HX.p[j] = b.c.col(B_HX, j);
+                jb.X.p[j] = b.c.col(B_X, j);
+                jb.R.p[j] = b.c.col(B_T1, j);
+            }
+            for (int v = 0; v < per; ++v) jb.theta.v[v] = v < m ? b.theta[v] : 0.0;
+            jb.m = mc;
+            if (Rt::real) jb.width = 2;
+            jb.N = b.c.N;
+            jb.nb = (int)std::min<long long>(256, std::max<long long>(1, (jb.N + 1023) / 1024));
+            jb.rows_per_block = (jb.N + jb.nb - 1) / jb.nb;
+            jb.start = blocks;
+            jb.out_start = outs;
+            jb.part_off = part;
+            blocks += jb.nb;
+            outs += per;
+            part += (long long)jb.nb * per;
+            jobs.push_back(jb);
+        }
+        int rc;
+        if ((rc = bo.wait_staged())) return rc;
+        if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(ResJob)))) return rc;
+        if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
+        if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(ResJob)))) return rc;
+        if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
+        if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
+        std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(ResJob));
+        CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(ResJob), hipMemcpyHostToDevice, bo.st));
+        if constexpr (Rt::real)
+            CHECK_HIP(residual_norm_pairs_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
+                                                  (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, bo.st));
+        else
+            CHECK_HIP(residual_norm_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
+                                            (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, bo.st));
+        CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, outs * sizeof(double), hipMemcpyDeviceToHost, bo.st));
+        CHECK_HIP(hipStreamSynchronize(bo.st));
+        const double* h = (const double*)bo.h_out;
+        std::copy(h, h + outs, nrm.begin());
+    }
+    for (size_t k = 0; k < live.size(); ++k) {
+        BInst& b = in[live[k]];
+        for (int j = 0; j < m; ++j) {
+            b.eta[j] = std::sqrt(std::max(0.0, nrm[k * per + j])) / (b.hnorm + std::fabs(b.theta[j]));
+            if (!std::isfinite(b.eta[j]) || !std::isfinite(b.theta[j])) {
+                b.done = true;
+                b.status = IWFPM_ERR_NUMERIC;
+            }
+        }
+    }
+    return IWFPM_OK;
+}
+
+// W = M R_A of one instance with the plain preconditioner (one-plan kernels)
+template <class Rt>
+static int plain_precondition(BInst& b) {
+    if constexpr (Rt::real) {
+        std::vector<RVec> Ract(b.ma);
+        for (int a = 0; a < b.ma; ++a) Ract[a] = {b.c.col(B_T1, b.act[a] >> 1), b.act[a] & 1};
+        unsigned long long parts = 0;
+        const ColPtrs src = colptrs(Ract, &parts);
+        ColPtrs w{};
+        for (int j = 0; j < (b.ma + 1) / 2; ++j) w.p[j] = b.c.col(B_W, j);
+        CHECK_HIP(gather_pairs(src, parts, b.ma, w, (const double*)b.s->M.ptr, b.c.N, b.c.st));
+    } else {
+        ColPtrs r{}, w{};
+        for (int a = 0; a < b.ma; ++a) {
+            r.p[a] = b.c.col(B_T1, b.act[a]);
+            w.p[a] = b.c.col(B_W, a);
+        }
+        CHECK_HIP(precond(r, w, b.ma, (const double*)b.s->M.ptr, b.c.N, b.c.st));
+    }
+    return IWFPM_OK;
+}
+
+// W = T(R_A) with the learned map where it is in use (per instance), else
+// M R_A (a batch's plain instances in one launch); sets b.lp_used
+template <class Rt>
+static int tall_precondition(Tall& t, std::vector<BInst>& in, const std::vector<int>& iter) {
+    std::vector<int> plain;
+    for (int i : iter) {
+        BInst& b = in[i];
+        b.lp_used = false;
+        if (b.lp) {
+            ColPtrs r{}, w{};
+            int ncol = b.ma;
+            if constexpr (Rt::real) {
+                // R_A packed two per column into the (still free) HW buffer
+                std::vector<RVec> Ract(b.ma);
+                for (int a = 0; a < b.ma; ++a) Ract[a] = {b.c.col(B_T1, b.act[a] >> 1), b.act[a] & 1};
+                unsigned long long parts = 0;
+                const ColPtrs src = colptrs(Ract, &parts);
+                ncol = (b.ma + 1) / 2;
+                for (int j = 0; j < ncol; ++j) {
+                    r.p[j] = b.c.col(B_HW, j);
+                    w.p[j] = b.c.col(B_W, j);
+                }
+                CHECK_HIP(gather_pairs(src, parts, b.ma, r, nullptr, b.c.N, b.c.st));
+            } else {
+                for (int a = 0; a < b.ma; ++a) {
+                    r.p[a] = b.c.col(B_T1, b.act[a]);
+                    w.p[a] = b.c.col(B_W, a);
+                }
+            }
+            if (learned_apply(b.lp, b.p, r, w, ncol, b.c.st) == IWFPM_OK) {
+                b.lp_used = true;
+                continue;
+            }
+            b.fallback = 1;
+            b.lp = nullptr;
+        }
+        plain.push_back(i);
+    }
+    if (plain.empty()) return IWFPM_OK;
+    if (t.single) {
+        for (int i : plain)
+            if (int rc = plain_precondition<Rt>(in[i])) return rc;
+        return IWFPM_OK;
+    }
+    BatchOps& bo = t.bo;
+    int blocks = 0, rc;
+    if constexpr (Rt::real) {
+        std::vector<GatherJob> jobs;
+        for (int i : plain) {
+            BInst& b = in[i];
+            std::vector<RVec> Ract(b.ma);
+            for (int a = 0; a < b.ma; ++a) Ract[a] = {b.c.col(B_T1, b.act[a] >> 1), b.act[a] & 1};
+            GatherJob jb{};
+            jb.src = colptrs(Ract, &jb.parts);
+            jb.n = b.ma;
+            jb.N = b.c.N;
+            for (int j = 0; j < (b.ma + 1) / 2; ++j) jb.dst.p[j] = b.c.col(B_W, j);
+            jb.M = (const double*)b.s->M.ptr;
+            jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
+            jb.start = blocks;
+            blocks += jb.nb;
+            jobs.push_back(jb);
+        }
+        if ((rc = bo.wait_staged())) return rc;
+        if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(GatherJob)))) return rc;
+        if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(GatherJob)))) return rc;
+        std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GatherJob));
+        CHECK_HIP(
+            hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GatherJob), hipMemcpyHostToDevice, bo.st));
+        CHECK_HIP(hipEventRecord(bo.staged, bo.st));
+        CHECK_HIP(gather_pairs_batched((const GatherJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, bo.st));
+    } else {
+        std::vector<PreJob> jobs;
+        for (int i : plain) {
+            BInst& b = in[i];
+            PreJob jb{};
+            for (int a = 0; a < b.ma; ++a) {
+                jb.R.p[a] = b.c.col(B_T1, b.act[a]);
+                jb.W.p[a] = b.c.col(B_W, a);
+            }
+            jb.m = b.ma;
+            jb.M = (const double*)b.s->M.ptr;
+            jb.N = b.c.N;
+            jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
+            jb.start = blocks;
+            blocks += jb.nb;
+            jobs.push_back(jb);
+        }
+        if ((rc = bo.wait_staged())) return rc;
+        if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(PreJob)))) return rc;
+        if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(PreJob)))) return rc;
+        std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(PreJob));
+        CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(PreJob), hipMemcpyHostToDevice, bo.st));
+        CHECK_HIP(hipEventRecord(bo.staged, bo.st));
+        CHECK_HIP(precond_batched((const PreJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, bo.st));
+    }
+    return IWFPM_OK;
+}
+
+// What a single solve adds: a start block, the Ritz vectors out, iterates
+// captured for training the learned preconditioner, per-iteration lines.
+struct SingleIO {
+    const void* x0 = nullptr;  // N x m complex start block (complex route), or null
+    void* evecs = nullptr;     // N x nev complex out, or null
+    Capture* cap = nullptr;
+};
+
+template <class Rt>
+static int lobpcg(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, const SingleIO& io, double* evals,
+                  double* eta_out, iwfpm_stats* stats, hipStream_t st) {
     const int nev = o.nev;
     const int m = o.block > 0 ? o.block : nev + std::max(2, nev / 4);
-    if (m < nev || 3 * m > kMaxCols) return IWFPM_ERR_ARG;
-    const int mc = (m + 1) / 2;
+    if (m < nev || m > 32) return IWFPM_ERR_ARG;
+    if (B > 1 && 3 * m > kMaxCols) return IWFPM_ERR_ARG;
     const bool explicit_ortho = force_explicit_ortho();
+    const char* venv = std::getenv("IWFPM_VERBOSE");
+    const bool verbose = B == 1 && venv && venv[0] == '1';
     std::vector<BInst> in(B);
     int rc;
     for (int i = 0; i < B; ++i) {
@@ -2711,10 +1966,11 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
             if (!b.lp || !learned_ready(b.lp, b.p)) return IWFPM_ERR_WEIGHTS;
         }
     }
-    BatchOps bo;
-    bo.st = st;
-    CHECK_HIP(hipEventCreateWithFlags(&bo.staged, hipEventDisableTiming));
-    std::vector<iwfpm_plan_t> pl(plans, plans + B);
+    Tall t;
+    t.single = B == 1;
+    t.bo.st = st;
+    CHECK_HIP(hipEventCreateWithFlags(&t.bo.staged, hipEventDisableTiming));
+    // a batch's applies: one batch object per convolution precision
     iwfpm_batch_t bat[2] = {nullptr, nullptr};
     struct BatchGuard {
         iwfpm_batch_t* b;
@@ -2723,14 +1979,18 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 if (b[k]) iwfpm_batch_destroy(b[k]);
         }
     } bguard{bat};
-    for (int k = 0; k < 2; ++k) {
-        bool ok = true;
-        // plans on the five-pass schedule are applied one by one
-        for (auto* p : pl) ok = ok && p->sched[k].ok && (p->sched[k].fused || p->sched[k].pd.split_mid == 0);
-        if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
-            return rc;
+    if (B > 1) {
+        std::vector<iwfpm_plan_t> pl(plans, plans + B);
+        for (int k = 0; k < 2; ++k) {
+            bool ok = true;
+            // plans on the five-pass schedule are applied one by one
+            for (auto* p : pl) ok = ok && p->sched[k].ok && (p->sched[k].fused || p->sched[k].pd.split_mid == 0);
+            if (ok && (rc = iwfpm_batch_create(B, pl.data(), k == 1 ? IWFPM_PREC_FP32 : IWFPM_PREC_FP64, 1, &bat[k])))
+                return rc;
+        }
     }
-    // apply H to the first cnt[i] real vectors (ceil(cnt/2) columns) of bin into bout
+    auto V = [&](BInst& b, int buf, int v0, int cnt) { return Rt::vecs(b.c, buf, v0, cnt); };
+    // H applied to the first cnt[i] trial vectors of bin into bout, by precision
     auto apply_all = [&](int bin, int bout, const std::vector<int>& cnt, const std::vector<int>& precs) -> int {
         for (int k = 0; k < 2; ++k) {
             std::vector<const void*> x(B, nullptr);
@@ -2741,7 +2001,7 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 if (cnt[i] > 0 && precs[i] == k) {
                     x[i] = in[i].c.col(bin, 0);
                     y[i] = in[i].c.col(bout, 0);
-                    nv[i] = (cnt[i] + 1) / 2;
+                    nv[i] = Rt::columns(cnt[i]);
                     in[i].matvecs += cnt[i];
                     any = true;
                 }
@@ -2755,116 +2015,96 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
         }
         return IWFPM_OK;
     };
-    // start blocks: real and imaginary parts of seeded complex blocks, orthonormalised
-    for (int i = 0; i < B; ++i)
-        CHECK_HIP(randn(in[i].c.col(B_X, 0), in[i].c.N * mc, o.seed + (unsigned long long)i, st));
-    {
-        std::vector<GramReqR> g(B);
-        for (int i = 0; i < B; ++i) g[i] = {rvecs(in[i].c, B_X, 0, m), rvecs(in[i].c, B_X, 0, m), in[i].c.N};
-        std::vector<std::vector<cd>> G;
-        if ((rc = batch_gram_real(bo, g, G))) return rc;
-        std::vector<int> bad(B, 0);
-        parallel_for(B, [&](int i) { bad[i] = svqb(G[i], m, in[i].T) < m; });
-        for (int i = 0; i < B; ++i)
-            if (bad[i]) return IWFPM_ERR_NUMERIC;
-        std::vector<LinReqR> l(B);
-        for (int i = 0; i < B; ++i)
-            l[i] = {rvecs(in[i].c, B_X, 0, m), rvecs(in[i].c, B_XN, 0, m), &in[i].T, m, 0, 0.0, in[i].c.N};
-        if ((rc = batch_lincomb_real(bo, l))) return rc;
-        for (auto& b : in) std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
-    }
-    std::vector<int> all_m(B, m), precs(B);
-    for (int i = 0; i < B; ++i) precs[i] = in[i].prec;
-    if ((rc = apply_all(B_X, B_HX, all_m, precs))) return rc;
+    // Rayleigh-Ritz on X alone (start blocks, blocks switched to float64, and
+    // a last clean-up): X <- X C, HX <- HX C
     auto rr_blocks = [&](const std::vector<int>& which) -> int {
         if (which.empty()) return IWFPM_OK;
-        std::vector<GramReqR> g;
+        std::vector<GramQ<Rt>> g;
         for (int i : which) {
-            std::vector<RVec> XHX = rvecs(in[i].c, B_X, 0, m), HX = rvecs(in[i].c, B_HX, 0, m);
+            BInst& b = in[i];
+            auto XHX = V(b, B_X, 0, m), HX = V(b, B_HX, 0, m);
             XHX.insert(XHX.end(), HX.begin(), HX.end());
-            g.push_back({rvecs(in[i].c, B_X, 0, m), XHX, in[i].c.N});
+            g.push_back({&b.c, V(b, B_X, 0, m), XHX});
         }
         std::vector<std::vector<cd>> G;
-        if ((rc = batch_gram_real(bo, g, G))) return rc;
+        if ((rc = tall_grams<Rt>(t, g, G))) return rc;
         std::vector<std::vector<cd>> C(which.size());
         std::vector<char> okt(which.size(), 1);
         parallel_for((int)which.size(), [&](int k) { okt[k] = rr_transform(G[k], m, in[which[k]].theta, C[k]); });
         for (char ok : okt)
             if (!ok) return IWFPM_ERR_NUMERIC;
-        std::vector<LinReqR> l;
+        std::vector<LinQ<Rt>> l;
         for (size_t k = 0; k < which.size(); ++k) {
             BInst& b = in[which[k]];
-            l.push_back({rvecs(b.c, B_X, 0, m), rvecs(b.c, B_XN, 0, m), &C[k], m, 0, 0.0, b.c.N});
-            l.push_back({rvecs(b.c, B_HX, 0, m), rvecs(b.c, B_HXN, 0, m), &C[k], m, 0, 0.0, b.c.N});
+            l.push_back({&b.c, V(b, B_X, 0, m), V(b, B_XN, 0, m), &C[k], m, 0.0});
+            l.push_back({&b.c, V(b, B_HX, 0, m), V(b, B_HXN, 0, m), &C[k], m, 0.0});
         }
-        if ((rc = batch_lincomb_real(bo, l))) return rc;
+        if ((rc = tall_lincombs<Rt>(t, l))) return rc;
         for (int i : which) {
             std::swap(in[i].s->buf[B_X], in[i].s->buf[B_XN]);
             std::swap(in[i].s->buf[B_HX], in[i].s->buf[B_HXN]);
         }
         return IWFPM_OK;
     };
+
+    // start blocks (seeded, or the caller's), orthonormalised
+    for (int i = 0; i < B; ++i) {
+        BInst& b = in[i];
+        if (io.x0 && !Rt::real)
+            CHECK_HIP(hipMemcpyAsync(b.c.col(B_X, 0), io.x0, (size_t)b.c.N * m * sizeof(double2),
+                                     hipMemcpyDeviceToDevice, st));
+        else
+            CHECK_HIP(randn(b.c.col(B_X, 0), b.c.N * Rt::columns(m), o.seed + (unsigned long long)i, st));
+    }
     {
-        std::vector<int> allidx(B);
-        for (int i = 0; i < B; ++i) allidx[i] = i;
+        std::vector<GramQ<Rt>> g;
+        for (auto& b : in) g.push_back({&b.c, V(b, B_X, 0, m), V(b, B_X, 0, m)});
+        std::vector<std::vector<cd>> G;
+        if ((rc = tall_grams<Rt>(t, g, G))) return rc;
+        std::vector<int> bad(B, 0);
+        parallel_for(B, [&](int i) {
+            if (Rt::real) hermitian_part(G[i], m);
+            bad[i] = svqb(G[i], m, in[i].T) < m;
+        });
+        for (int i = 0; i < B; ++i)
+            if (bad[i]) return IWFPM_ERR_NUMERIC;
+        std::vector<LinQ<Rt>> l;
+        for (auto& b : in) l.push_back({&b.c, V(b, B_X, 0, m), V(b, B_XN, 0, m), &b.T, m, 0.0});
+        if ((rc = tall_lincombs<Rt>(t, l))) return rc;
+        for (auto& b : in) std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
+    }
+    {
+        std::vector<int> all_m(B, m), precs(B), allidx(B);
+        for (int i = 0; i < B; ++i) {
+            precs[i] = in[i].prec;
+            allidx[i] = i;
+        }
+        if ((rc = apply_all(B_X, B_HX, all_m, precs))) return rc;
         if ((rc = rr_blocks(allidx))) return rc;
     }
+
     for (;;) {
         std::vector<int> live;
         for (int i = 0; i < B; ++i)
             if (!in[i].done) live.push_back(i);
         if (live.empty()) break;
-        // residuals and their norms (one per real vector), one launch for all live instances
-        {
-            std::vector<ResJob> jobs;
-            int blocks = 0, outs = 0;
-            long long part = 0;
-            for (int i : live) {
-                BInst& b = in[i];
-                ResJob jb{};
-                for (int j = 0; j < mc; ++j) {
-                    jb.HX.p[j] = b.c.col(B_HX, j);
-                    jb.X.p[j] = b.c.col(B_X, j);
-                    jb.R.p[j] = b.c.col(B_T1, j);
-                }
-                for (int v = 0; v < 2 * mc; ++v) jb.theta.v[v] = v < m ? b.theta[v] : 0.0;
-                jb.m = mc;
-                jb.width = 2;
-                jb.N = b.c.N;
-                jb.nb = (int)std::min<long long>(256, std::max<long long>(1, (jb.N + 1023) / 1024));
-                jb.rows_per_block = (jb.N + jb.nb - 1) / jb.nb;
-                jb.start = blocks;
-                jb.out_start = outs;
-                jb.part_off = part;
-                blocks += jb.nb;
-                outs += 2 * mc;
-                part += (long long)jb.nb * 2 * mc;
-                jobs.push_back(jb);
-            }
-            if ((rc = bo.wait_staged())) return rc;
-            if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(ResJob)))) return rc;
-            if ((rc = bo.reserve_host((void**)&bo.h_out, bo.out_cap, (size_t)outs * sizeof(double2)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(ResJob)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_partial, (size_t)part * sizeof(double2)))) return rc;
-            if ((rc = bo.reserve_dev(bo.d_out, (size_t)outs * sizeof(double2)))) return rc;
-            std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(ResJob));
-            CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(ResJob), hipMemcpyHostToDevice, st));
-            CHECK_HIP(residual_norm_pairs_batched((const ResJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, outs,
-                                                  (double*)bo.d_partial.ptr, (double*)bo.d_out.ptr, st));
-            CHECK_HIP(hipMemcpyAsync(bo.h_out, bo.d_out.ptr, outs * sizeof(double), hipMemcpyDeviceToHost, st));
-            CHECK_HIP(hipStreamSynchronize(st));
-            const double* h = (const double*)bo.h_out;
-            for (size_t k = 0; k < live.size(); ++k) {
-                BInst& b = in[live[k]];
-                for (int j = 0; j < m; ++j) {
-                    b.eta[j] = std::sqrt(std::max(0.0, h[k * 2 * mc + j])) / (b.hnorm + std::fabs(b.theta[j]));
-                    if (!std::isfinite(b.eta[j])) {
-                        b.done = true;
-                        b.status = IWFPM_ERR_NUMERIC;
-                    }
-                }
+        if ((rc = tall_residuals<Rt>(t, in, live, m))) return rc;
+        if (io.cap) {
+            // iterates (and residuals) for training the learned preconditioner
+            Capture* cap = io.cap;
+            BInst& b = in[0];
+            if (!b.done && b.it > 0 && b.it % cap->stride == 0 && b.it != cap->last_it &&
+                cap->got < (int)cap->X.size()) {
+                const size_t bytes = (size_t)b.c.N * cap->ncol * sizeof(double2);
+                CHECK_HIP(hipMemcpyAsync(cap->X[cap->got], b.c.col(B_X, 0), bytes, hipMemcpyDeviceToDevice, st));
+                if (!cap->R.empty())
+                    CHECK_HIP(hipMemcpyAsync(cap->R[cap->got], b.c.col(B_T1, 0), bytes, hipMemcpyDeviceToDevice, st));
+                cap->eta.emplace_back(b.eta.begin(), b.eta.begin() + cap->ncol);
+                cap->last_it = b.it;
+                ++cap->got;
             }
         }
+        // per-instance decisions
         std::vector<int> to64, iter, to_clean;
         for (int i : live) {
             BInst& b = in[i];
@@ -2875,10 +2115,14 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 conv += b.eta[j] <= o.tol;
                 worst = std::max(worst, b.eta[j]);
             }
+            if (verbose)
+                std::fprintf(stderr, "[iwfpm_eigs%s] it %d prec %s conv %d/%d worst_eta %.3e theta0 %.15g mp %d reortho %d\n",
+                             Rt::real ? " real" : "", b.it, b.prec ? "fp32" : "fp64", conv, nev, worst, b.theta[0],
+                             b.mp, b.reortho);
             if (conv == nev) {
                 if ((b.prec == 0 || !b.can64) && b.cleaned) b.done = true;
-                else if (b.prec == 0 || !b.can64) to_clean.push_back(i);
-                else to64.push_back(i);
+                else if (b.prec == 0 || !b.can64) to_clean.push_back(i);  // re-orthonormalise X, take the pairs once more
+                else to64.push_back(i);  // confirm with float64 applies
                 if (!b.done) b.cleaned = true;
                 continue;
             }
@@ -2887,6 +2131,8 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 b.status = IWFPM_ERR_NOCONV;
                 continue;
             }
+            // float32 convolution: continue with float64 applies once the
+            // residuals reach its noise floor or stop improving
             bool stalled = false;
             if (worst < 0.5 * b.best_eta) {
                 b.best_eta = worst;
@@ -2895,6 +2141,7 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 stalled = worst < 1e-5 && b.it - b.best_it >= 20;
             }
             if (b.lp && b.it - b.best_it >= 50) {
+                // learned preconditioner stagnating: continue with M
                 b.fallback = 1;
                 b.lp = nullptr;
                 b.best_it = b.it;
@@ -2923,142 +2170,129 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
             BInst& b = in[i];
             ++b.it;
             if (b.prec == 0 && b.p->opts.precision == 1) ++b.polished;
+            // active set: the pairs not yet converged (soft locking)
             b.act.clear();
             for (int j = 0; j < m; ++j)
                 if (b.eta[j] > o.tol) b.act.push_back(j);
             b.ma = (int)b.act.size();
-            b.mq = b.mp;
+            b.mq = b.mp;  // P: built last iteration from the then-active Ritz vectors, orthonormal and orthogonal to X
         }
-        // W = T(R_A) (learned, per instance) or M R_A (all plain instances in one launch), packed
+        if ((rc = tall_precondition<Rt>(t, in, iter))) return rc;
+        // W <- orthonormal basis of the part of W orthogonal to [X P]: one
+        // explicit projection with the Gram [X P W]^H W, then the second
+        // projection and SVQB in coefficient space (explicit twice as fallback)
         {
-            std::vector<GatherJob> jobs;
-            int blocks = 0;
-            for (int i : iter) {
-                BInst& b = in[i];
-                std::vector<RVec> Ract(b.ma);
-                for (int a = 0; a < b.ma; ++a) Ract[a] = {b.c.col(B_T1, b.act[a] >> 1), b.act[a] & 1};
-                GatherJob jb{};
-                jb.src = colptrs(Ract, &jb.parts);
-                jb.n = b.ma;
-                jb.N = b.c.N;
-                const int mac = (b.ma + 1) / 2;
-                if (b.lp) {
-                    ColPtrs rp{}, w{};
-                    for (int j = 0; j < mac; ++j) {
-                        rp.p[j] = b.c.col(B_HW, j);
-                        w.p[j] = b.c.col(B_W, j);
-                    }
-                    CHECK_HIP(gather_pairs(jb.src, jb.parts, b.ma, rp, nullptr, b.c.N, st));
-                    if (learned_apply(b.lp, b.p, rp, w, mac, st) == IWFPM_OK) continue;
-                    b.fallback = 1;
-                    b.lp = nullptr;
-                }
-                for (int j = 0; j < mac; ++j) jb.dst.p[j] = b.c.col(B_W, j);
-                jb.M = (const double*)b.s->M.ptr;
-                jb.nb = (int)std::min<long long>(1024, std::max<long long>(1, (jb.N + 255) / 256));
-                jb.start = blocks;
-                blocks += jb.nb;
-                jobs.push_back(jb);
-            }
-            if (!jobs.empty()) {
-                if ((rc = bo.wait_staged())) return rc;
-                if ((rc = bo.reserve_host((void**)&bo.h_jobs, bo.jobs_cap, jobs.size() * sizeof(GatherJob)))) return rc;
-                if ((rc = bo.reserve_dev(bo.d_jobs, jobs.size() * sizeof(GatherJob)))) return rc;
-                std::memcpy(bo.h_jobs, jobs.data(), jobs.size() * sizeof(GatherJob));
-                CHECK_HIP(hipMemcpyAsync(bo.d_jobs.ptr, bo.h_jobs, jobs.size() * sizeof(GatherJob),
-                                         hipMemcpyHostToDevice, st));
-                CHECK_HIP(hipEventRecord(bo.staged, st));
-                CHECK_HIP(gather_pairs_batched((const GatherJob*)bo.d_jobs.ptr, (int)jobs.size(), blocks, st));
-            }
-        }
-        // W <- orthonormal basis of the part of W orthogonal to [X P] (as in the complex solver)
-        {
-            std::vector<GramReqR> g;
-            std::vector<std::vector<RVec>> XPW(iter.size()), Wv(iter.size());
+            std::vector<std::vector<typename Rt::V>> XPW(iter.size());
+            std::vector<GramQ<Rt>> g;
             for (size_t k = 0; k < iter.size(); ++k) {
                 BInst& b = in[iter[k]];
-                XPW[k] = rvecs(b.c, B_X, 0, m);
-                auto P = rvecs(b.c, B_P, 0, b.mq);
+                XPW[k] = V(b, B_X, 0, m);
+                auto P = V(b, B_P, 0, b.mq), Wv = V(b, B_W, 0, b.ma);
                 XPW[k].insert(XPW[k].end(), P.begin(), P.end());
-                Wv[k] = rvecs(b.c, B_W, 0, b.ma);
-                XPW[k].insert(XPW[k].end(), Wv[k].begin(), Wv[k].end());
-                g.push_back({XPW[k], Wv[k], b.c.N});
+                XPW[k].insert(XPW[k].end(), Wv.begin(), Wv.end());
+                g.push_back({&b.c, XPW[k], Wv});
             }
             std::vector<std::vector<cd>> Gall;
-            if ((rc = batch_gram_real(bo, g, Gall))) return rc;
+            if ((rc = tall_grams<Rt>(t, g, Gall))) return rc;
+            // a non-finite learned direction falls back to M for the rest of the solve
+            std::vector<GramQ<Rt>> again;
+            std::vector<size_t> again_k;
+            for (size_t k = 0; k < iter.size(); ++k) {
+                BInst& b = in[iter[k]];
+                if (!b.lp_used) continue;
+                const int nx = m + b.mq;
+                bool finite = true;
+                for (int j = 0; j < b.ma; ++j)
+                    finite = finite && std::isfinite(Gall[k][(size_t)(nx + j) + (size_t)j * (nx + b.ma)].real());
+                if (finite) continue;
+                b.fallback = 1;
+                b.lp = nullptr;
+                if ((rc = plain_precondition<Rt>(b))) return rc;
+                again.push_back(g[k]);
+                again_k.push_back(k);
+            }
+            if (!again.empty()) {
+                std::vector<std::vector<cd>> G2;
+                if ((rc = tall_grams<Rt>(t, again, G2))) return rc;
+                for (size_t a = 0; a < again_k.size(); ++a) Gall[again_k[a]].swap(G2[a]);
+            }
             std::vector<size_t> two(iter.size());
             for (size_t k = 0; k < iter.size(); ++k) two[k] = k;
-            if (!two.empty() && !explicit_ortho) {
-                // one explicit projection, then the second one and SVQB in coefficient space
+            if (!explicit_ortho) {
                 std::vector<std::vector<cd>> G1(two.size());
-                std::vector<LinReqR> lp1;
-                std::vector<GramReqR> g2;
-                for (size_t t = 0; t < two.size(); ++t) {
-                    BInst& b = in[iter[two[t]]];
+                std::vector<LinQ<Rt>> l1;
+                std::vector<GramQ<Rt>> g2;
+                for (size_t u = 0; u < two.size(); ++u) {
+                    BInst& b = in[iter[two[u]]];
                     const int nx = m + b.mq;
-                    G1[t] = neg_projection(Gall[two[t]], nx, b.ma);
-                    std::vector<RVec> XP(XPW[two[t]].begin(), XPW[two[t]].begin() + nx);
-                    lp1.push_back({XP, Wv[two[t]], &G1[t], nx, 0, 1.0, b.c.N});
-                    g2.push_back({XPW[two[t]], Wv[two[t]], b.c.N});
+                    G1[u] = neg_projection(Gall[two[u]], nx, b.ma);
+                    std::vector<typename Rt::V> XP(XPW[two[u]].begin(), XPW[two[u]].begin() + nx);
+                    l1.push_back({&b.c, XP, V(b, B_W, 0, b.ma), &G1[u], nx, 1.0});
+                    g2.push_back({&b.c, XPW[two[u]], V(b, B_W, 0, b.ma)});
                 }
-                if ((rc = batch_lincomb_real(bo, lp1))) return rc;
+                if ((rc = tall_lincombs<Rt>(t, l1))) return rc;
                 std::vector<std::vector<cd>> Gall2;
-                if ((rc = batch_gram_real(bo, g2, Gall2))) return rc;
+                if ((rc = tall_grams<Rt>(t, g2, Gall2))) return rc;
                 std::vector<char> ok2(two.size(), 0);
                 std::vector<std::vector<cd>> Cm2(two.size());
-                parallel_for((int)two.size(), [&](int t) {
-                    BInst& b = in[iter[two[t]]];
-                    ok2[t] = ortho_coefficients(Gall2[t], m + b.mq, b.ma, Cm2[t], b.mw);
+                parallel_for((int)two.size(), [&](int u) {
+                    BInst& b = in[iter[two[u]]];
+                    ok2[u] = ortho_coefficients(Gall2[u], m + b.mq, b.ma, Cm2[u], b.mw);
                 });
-                std::vector<LinReqR> l2;
+                std::vector<LinQ<Rt>> l2;
                 std::vector<size_t> rest;
-                for (size_t t = 0; t < two.size(); ++t) {
-                    BInst& b = in[iter[two[t]]];
-                    if (ok2[t])
-                        l2.push_back({XPW[two[t]], rvecs(b.c, B_T1, 0, b.mw), &Cm2[t], m + b.mq + b.ma, 0, 0.0, b.c.N});
+                for (size_t u = 0; u < two.size(); ++u) {
+                    BInst& b = in[iter[two[u]]];
+                    if (ok2[u])
+                        l2.push_back({&b.c, XPW[two[u]], V(b, B_T1, 0, b.mw), &Cm2[u], m + b.mq + b.ma, 0.0});
                     else
-                        rest.push_back(two[t]);
+                        rest.push_back(two[u]);
                 }
-                if ((rc = batch_lincomb_real(bo, l2))) return rc;
+                if ((rc = tall_lincombs<Rt>(t, l2))) return rc;
                 two.swap(rest);
             }
             if (!two.empty()) {
+                for (size_t k : two) ++in[iter[k]].reortho;
                 for (int pass = 0; pass < 2; ++pass) {
-                    std::vector<GramReqR> g2;
-                    std::vector<std::vector<RVec>> XP(two.size());
-                    for (size_t t = 0; t < two.size(); ++t) {
-                        BInst& b = in[iter[two[t]]];
-                        XP[t].assign(XPW[two[t]].begin(), XPW[two[t]].begin() + m + b.mq);
-                        g2.push_back({XP[t], Wv[two[t]], b.c.N});
+                    std::vector<std::vector<typename Rt::V>> XP(two.size());
+                    std::vector<GramQ<Rt>> g2;
+                    for (size_t u = 0; u < two.size(); ++u) {
+                        BInst& b = in[iter[two[u]]];
+                        XP[u].assign(XPW[two[u]].begin(), XPW[two[u]].begin() + m + b.mq);
+                        g2.push_back({&b.c, XP[u], V(b, B_W, 0, b.ma)});
                     }
                     std::vector<std::vector<cd>> G;
-                    if ((rc = batch_gram_real(bo, g2, G))) return rc;
-                    std::vector<LinReqR> l2;
-                    for (size_t t = 0; t < two.size(); ++t) {
-                        for (auto& v : G[t]) v = -v;
-                        BInst& b = in[iter[two[t]]];
-                        l2.push_back({XP[t], Wv[two[t]], &G[t], (int)XP[t].size(), 0, 1.0, b.c.N});
+                    if ((rc = tall_grams<Rt>(t, g2, G))) return rc;
+                    std::vector<LinQ<Rt>> l2;
+                    for (size_t u = 0; u < two.size(); ++u) {
+                        for (auto& v : G[u]) v = -v;
+                        BInst& b = in[iter[two[u]]];
+                        l2.push_back({&b.c, XP[u], V(b, B_W, 0, b.ma), &G[u], (int)XP[u].size(), 1.0});
                     }
-                    if ((rc = batch_lincomb_real(bo, l2))) return rc;
+                    if ((rc = tall_lincombs<Rt>(t, l2))) return rc;
                 }
-                std::vector<GramReqR> g2;
-                for (size_t k : two) g2.push_back({Wv[k], Wv[k], in[iter[k]].c.N});
-                std::vector<std::vector<cd>> G;
-                if ((rc = batch_gram_real(bo, g2, G))) return rc;
-                parallel_for((int)two.size(), [&](int t) {
-                    BInst& b = in[iter[two[t]]];
-                    hermitian_part(G[t], b.ma);
-                    b.mw = svqb(G[t], b.ma, b.T, 1e-10);
-                });
-                std::vector<LinReqR> l2;
+                std::vector<GramQ<Rt>> g2;
                 for (size_t k : two) {
                     BInst& b = in[iter[k]];
-                    l2.push_back({Wv[k], rvecs(b.c, B_T1, 0, b.mw), &b.T, b.ma, 0, 0.0, b.c.N});
+                    g2.push_back({&b.c, V(b, B_W, 0, b.ma), V(b, B_W, 0, b.ma)});
                 }
-                if ((rc = batch_lincomb_real(bo, l2))) return rc;
+                std::vector<std::vector<cd>> G;
+                if ((rc = tall_grams<Rt>(t, g2, G))) return rc;
+                parallel_for((int)two.size(), [&](int u) {
+                    BInst& b = in[iter[two[u]]];
+                    if (Rt::real) hermitian_part(G[u], b.ma);
+                    b.mw = svqb(G[u], b.ma, b.T, 1e-10);
+                });
+                std::vector<LinQ<Rt>> l2;
+                for (size_t k : two) {
+                    BInst& b = in[iter[k]];
+                    l2.push_back({&b.c, V(b, B_W, 0, b.ma), V(b, B_T1, 0, b.mw), &b.T, b.ma, 0.0});
+                }
+                if ((rc = tall_lincombs<Rt>(t, l2))) return rc;
             }
             for (int i : iter) std::swap(in[i].s->buf[B_W], in[i].s->buf[B_T1]);
         }
+        // HW = H W
         {
             std::vector<int> cnt(B, 0), pr(B, 0);
             for (int i : iter) {
@@ -3067,42 +2301,45 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
             }
             if ((rc = apply_all(B_W, B_HW, cnt, pr))) return rc;
         }
-        // Rayleigh-Ritz: G = [X W P]^T [HW HP] for all, small problems on host threads
-        std::vector<std::vector<RVec>> S(iter.size()), HS(iter.size());
+        // Rayleigh-Ritz on the orthonormal basis S = [X W P]: with
+        // X^H H X = diag(theta) only S^H [HW HP] is formed; the small problems
+        // on host threads
+        std::vector<std::vector<typename Rt::V>> S(iter.size()), HS(iter.size());
         {
-            std::vector<GramReqR> g;
+            std::vector<GramQ<Rt>> g;
             for (size_t k = 0; k < iter.size(); ++k) {
                 BInst& b = in[iter[k]];
-                S[k] = rvecs(b.c, B_X, 0, m);
-                HS[k] = rvecs(b.c, B_HX, 0, m);
-                auto Wn = rvecs(b.c, B_W, 0, b.mw), HWn = rvecs(b.c, B_HW, 0, b.mw);
-                auto Pn = rvecs(b.c, B_P, 0, b.mq), HPn = rvecs(b.c, B_HP, 0, b.mq);
+                S[k] = V(b, B_X, 0, m);
+                HS[k] = V(b, B_HX, 0, m);
+                auto Wn = V(b, B_W, 0, b.mw), HWn = V(b, B_HW, 0, b.mw);
+                auto Pn = V(b, B_P, 0, b.mq), HPn = V(b, B_HP, 0, b.mq);
                 S[k].insert(S[k].end(), Wn.begin(), Wn.end());
-                S[k].insert(S[k].end(), Pn.begin(), Pn.end());
                 HS[k].insert(HS[k].end(), HWn.begin(), HWn.end());
+                S[k].insert(S[k].end(), Pn.begin(), Pn.end());
                 HS[k].insert(HS[k].end(), HPn.begin(), HPn.end());
                 b.ns = (int)S[k].size();
-                g.push_back({S[k], std::vector<RVec>(HS[k].begin() + m, HS[k].end()), b.c.N});
+                g.push_back({&b.c, S[k], std::vector<typename Rt::V>(HS[k].begin() + m, HS[k].end())});
             }
             std::vector<std::vector<cd>> G;
-            if ((rc = batch_gram_real(bo, g, G))) return rc;
+            if ((rc = tall_grams<Rt>(t, g, G))) return rc;
             parallel_for((int)iter.size(), [&](int k) {
                 BInst& b = in[iter[k]];
                 b.mpn = rr_coefficients(G[k], b.theta, m, b.ns, b.act, b.th, b.U);
             });
         }
+        // [X_new | P_new] = S U, [HX_new | HP_new] = HS U
         {
-            std::vector<LinReqR> l;
+            std::vector<LinQ<Rt>> l;
             for (size_t k = 0; k < iter.size(); ++k) {
                 BInst& b = in[iter[k]];
-                std::vector<RVec> out = rvecs(b.c, B_XN, 0, m), hout = rvecs(b.c, B_HXN, 0, m);
-                auto pn = rvecs(b.c, B_PN, 0, b.mpn), hpn = rvecs(b.c, B_HPN, 0, b.mpn);
+                auto out = V(b, B_XN, 0, m), hout = V(b, B_HXN, 0, m);
+                auto pn = V(b, B_PN, 0, b.mpn), hpn = V(b, B_HPN, 0, b.mpn);
                 out.insert(out.end(), pn.begin(), pn.end());
                 hout.insert(hout.end(), hpn.begin(), hpn.end());
-                l.push_back({S[k], out, &b.U, b.ns, 0, 0.0, b.c.N});
-                l.push_back({HS[k], hout, &b.U, b.ns, 0, 0.0, b.c.N});
+                l.push_back({&b.c, S[k], out, &b.U, b.ns, 0.0});
+                l.push_back({&b.c, HS[k], hout, &b.U, b.ns, 0.0});
             }
-            if ((rc = batch_lincomb_real(bo, l))) return rc;
+            if ((rc = tall_lincombs<Rt>(t, l))) return rc;
             for (int i : iter) {
                 BInst& b = in[i];
                 std::swap(b.s->buf[B_X], b.s->buf[B_XN]);
@@ -3112,6 +2349,19 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
                 b.mp = b.mpn;
                 b.theta.assign(b.th.begin(), b.th.begin() + m);
             }
+        }
+    }
+    if (io.evecs) {
+        BInst& b = in[0];
+        if constexpr (Rt::real) {
+            unsigned long long parts = 0;
+            const ColPtrs src = colptrs(rvecs(b.c, B_X, 0, nev), &parts);
+            ColPtrs dst{};
+            for (int j = 0; j < nev; ++j) dst.p[j] = (double2*)io.evecs + (size_t)j * b.c.N;
+            CHECK_HIP(unpack_real(src, parts, nev, dst, b.c.N, st));
+        } else {
+            CHECK_HIP(hipMemcpyAsync(io.evecs, b.c.col(B_X, 0), (size_t)b.c.N * nev * sizeof(double2),
+                                     hipMemcpyDeviceToDevice, st));
         }
     }
     CHECK_HIP(hipStreamSynchronize(st));
@@ -3125,6 +2375,7 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
         if (stats) {
             iwfpm_stats& s = stats[i];
             s.iterations = b.it;
+            s.restarts = 0;
             s.matvecs = b.matvecs;
             s.polished = b.polished;
             s.fallback = b.fallback;
@@ -3135,6 +2386,33 @@ static int run_batched_real(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_
         if (b.status != IWFPM_OK && worst_status == IWFPM_OK) worst_status = b.status;
     }
     return worst_status;
+}
+
+int eigs_capture(iwfpm_plan_s* p, const iwfpm_eigs_opts& o, Capture* cap, double* evals, void* evecs,
+                 hipStream_t st) {
+    if (o.nev < 1 || o.nev > p->geom.N || !cap || cap->ncol > o.nev) return IWFPM_ERR_ARG;
+    SingleIO io;
+    io.evecs = evecs;
+    io.cap = cap;
+    return lobpcg<CplxRoute>(1, &p, o, io, evals, nullptr, nullptr, st);
+}
+
+}  // namespace iwfpm
+
+using namespace iwfpm;
+
+extern "C" {
+
+void iwfpm_default_eigs_opts(iwfpm_eigs_opts* o) {
+    if (!o) return;
+    o->nev = 8;
+    o->block = 0;
+    o->tol = 1e-8;
+    o->maxit = 1000;
+    o->precond = IWFPM_PRECOND_PLAIN;
+    o->seed = 2404045070ull;
+    o->polish = 1;
+    o->arith = 0;
 }
 
 int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, double* evals, void* evecs, double* eta,
@@ -3150,8 +2428,11 @@ int iwfpm_eigs(iwfpm_plan_t p, const iwfpm_eigs_opts* opts, const void* x0, doub
     if (real && (x0 || !real_symmetric(p))) return IWFPM_ERR_ARG;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     auto t0 = std::chrono::steady_clock::now();
-    int rc = real ? run_real(p, *opts, evals, evecs, eta, stats, (hipStream_t)stream)
-                  : run(p, *opts, x0, evals, evecs, eta, stats, (hipStream_t)stream);
+    SingleIO io;
+    io.x0 = x0;
+    io.evecs = evecs;
+    int rc = real ? lobpcg<RealRoute>(1, &p, *opts, io, evals, eta, stats, (hipStream_t)stream)
+                  : lobpcg<CplxRoute>(1, &p, *opts, io, evals, eta, stats, (hipStream_t)stream);
     if (stats) stats->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
@@ -3179,8 +2460,8 @@ int iwfpm_eigs_batched(int B, const iwfpm_plan_t* plans, const iwfpm_eigs_opts* 
     if (!guard.ok) return IWFPM_ERR_DEVICE;
     if (stats) std::memset(stats, 0, sizeof(iwfpm_stats) * B);
     auto t0 = std::chrono::steady_clock::now();
-    int rc = real ? run_batched_real(B, plans, *opts, evals, eta, stats, (hipStream_t)stream)
-                  : run_batched(B, plans, *opts, evals, eta, stats, (hipStream_t)stream);
+    int rc = real ? lobpcg<RealRoute>(B, plans, *opts, SingleIO{}, evals, eta, stats, (hipStream_t)stream)
+                  : lobpcg<CplxRoute>(B, plans, *opts, SingleIO{}, evals, eta, stats, (hipStream_t)stream);
     double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats)
         for (int i = 0; i < B; ++i) stats[i].t_total = t;
