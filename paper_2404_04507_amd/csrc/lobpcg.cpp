@@ -757,9 +757,8 @@ struct Solver {
     DeviceBuf M;          // preconditioner diagonal
     int Mkind = -1;
     DeviceBuf partial;    // gram / norm partials
-    DeviceBuf small;      // gram results and norms on the device
     DeviceBuf dring;      // coefficient slots on the device
-    double2* hsmall = nullptr;  // pinned host mirror of `small`
+    double2* hsmall = nullptr;  // gram results and norms: pinned host memory the reductions write directly
     double2* hring = nullptr;   // pinned coefficient slots
     int ring_next = 0;
     int ring_since_sync = 0;
@@ -771,7 +770,6 @@ static void solver_free(Solver* s) {
     for (auto& b : s->buf) dev_free(b);
     dev_free(s->M);
     dev_free(s->partial);
-    dev_free(s->small);
     dev_free(s->dring);
     if (s->hsmall) (void)hipHostFree(s->hsmall);
     if (s->hring) (void)hipHostFree(s->hring);
@@ -793,7 +791,6 @@ static int solver_ensure(iwfpm_plan_s* p, int m) {
     size_t need_partial = (size_t)s->max_blocks * kMaxCols * kMaxCols * sizeof(double2);
     if (s->partial.bytes < need_partial && dev_alloc(s->partial, need_partial) != IWFPM_OK) return IWFPM_ERR_ALLOC;
     size_t need_small = (size_t)2 * 96 * 96 * sizeof(double2);
-    if (s->small.bytes < need_small && dev_alloc(s->small, need_small) != IWFPM_OK) return IWFPM_ERR_ALLOC;
     size_t need_ring = (size_t)kRingSlots * kSlot * sizeof(double2);
     if (s->dring.bytes < need_ring && dev_alloc(s->dring, need_ring) != IWFPM_OK) return IWFPM_ERR_ALLOC;
     if (!s->hsmall && hipHostMalloc((void**)&s->hsmall, need_small) != hipSuccess) return IWFPM_ERR_ALLOC;
@@ -857,7 +854,9 @@ static int sync(Ctx& c) {
 static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<double2*>& R, std::vector<cd>& C) {
     const int p = (int)L.size(), q = (int)R.size();
     C.assign((size_t)p * q, 0.0);
-    double2* dC = (double2*)c.s->small.ptr;
+    // the reduction writes straight into the pinned (device-visible) host
+    // mirror: no separate copy and its launch per Gram
+    double2* h = c.s->hsmall;
     for (int i0 = 0; i0 < p; i0 += kMaxCols) {
         int pi = std::min(kMaxCols, p - i0);
         for (int j0 = 0; j0 < q; j0 += kMaxCols) {
@@ -865,12 +864,11 @@ static int host_gram(Ctx& c, const std::vector<double2*>& L, const std::vector<d
             ColPtrs a{}, b{};
             for (int i = 0; i < pi; ++i) a.p[i] = L[i0 + i];
             for (int j = 0; j < qj; ++j) b.p[j] = R[j0 + j];
-            CHECK_HIP(gram(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, dC, c.st));
-            CHECK_HIP(hipMemcpyAsync(c.s->hsmall, dC, (size_t)pi * qj * sizeof(double2), hipMemcpyDeviceToHost, c.st));
+            CHECK_HIP(gram(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, h, c.st));
             if (int rc = sync(c)) return rc;
             for (int j = 0; j < qj; ++j)
                 for (int i = 0; i < pi; ++i) {
-                    double2 v = c.s->hsmall[(size_t)j * pi + i];
+                    double2 v = h[(size_t)j * pi + i];
                     C[(size_t)(i0 + i) + (size_t)(j0 + j) * p] = cd(v.x, v.y);
                 }
         }
@@ -1177,8 +1175,7 @@ static int host_gram_real(Ctx& c, const std::vector<RVec>& L, const std::vector<
     const int P = (int)Lp.cols.size(), Q = (int)Rp.cols.size();
     const size_t ldf = 2 * (size_t)P;
     std::vector<double> Gf(ldf * 2 * (size_t)Q, 0.0);
-    double* dC = (double*)c.s->small.ptr;
-    double* h = (double*)c.s->hsmall;
+    double* h = (double*)c.s->hsmall;  // written by the reduction directly (pinned, device-visible)
     constexpr int kc = kMaxCols / 2;
     for (int i0 = 0; i0 < P; i0 += kc) {
         const int pi = std::min(kc, P - i0);
@@ -1187,8 +1184,7 @@ static int host_gram_real(Ctx& c, const std::vector<RVec>& L, const std::vector<
             ColPtrs a{}, b{};
             for (int i = 0; i < pi; ++i) a.p[i] = Lp.cols[i0 + i];
             for (int j = 0; j < qj; ++j) b.p[j] = Rp.cols[j0 + j];
-            CHECK_HIP(gram_pairs(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, dC, c.st));
-            CHECK_HIP(hipMemcpyAsync(h, dC, (size_t)4 * pi * qj * sizeof(double), hipMemcpyDeviceToHost, c.st));
+            CHECK_HIP(gram_pairs(a, pi, b, qj, c.N, (double2*)c.s->partial.ptr, c.s->max_blocks, h, c.st));
             if (int rc = sync(c)) return rc;
             for (int s2 = 0; s2 < 2 * qj; ++s2)
                 for (int r2 = 0; r2 < 2 * pi; ++r2)
@@ -1732,15 +1728,14 @@ static int tall_residuals(Tall& t, std::vector<BInst>& in, const std::vector<int
                 r.p[j] = b.c.col(B_T1, j);
             }
             for (int v = 0; v < per; ++v) th.v[v] = v < m ? b.theta[v] : 0.0;
-            double* dNorm = (double*)((double2*)b.s->small.ptr + 96 * 96);
-            if constexpr (Rt::real)
-                CHECK_HIP(residual_norm_pairs(hx, x, r, th, mc, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks,
-                                              dNorm, b.c.st));
-            else
-                CHECK_HIP(residual_norm(hx, x, r, th, m, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks, dNorm,
-                                        b.c.st));
+            // the norms land in the pinned host mirror directly
             double* h = (double*)(b.s->hsmall + 96 * 96);
-            CHECK_HIP(hipMemcpyAsync(h, dNorm, per * sizeof(double), hipMemcpyDeviceToHost, b.c.st));
+            if constexpr (Rt::real)
+                CHECK_HIP(residual_norm_pairs(hx, x, r, th, mc, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks, h,
+                                              b.c.st));
+            else
+                CHECK_HIP(residual_norm(hx, x, r, th, m, b.c.N, (double*)b.s->partial.ptr, b.s->max_blocks, h,
+                                        b.c.st));
             if (int rc = sync(b.c)) return rc;
             std::copy(h, h + per, nrm.begin() + (size_t)k * per);
         }
