@@ -241,6 +241,9 @@ def main():
     ap.add_argument("--paper-3d", default="",
                     help="also solve Ex. 4.3 at K = 5, L = 10, 20, 30, 40 (up to 5.12e8 DOF) for the given "
                          "cases: I, II or I,II (several minutes per case)")
+    ap.add_argument("--paper-3d-ef", action="store_true",
+                    help="with --paper-3d: also Table 9's E_f, the ground states on the 3D observation grid "
+                         "[-5, 5]^3 (step 0.1, 101^3 points) against the L = 40 one (about 2.5 more minutes per case)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 20 device copies of 16 x 589,824 complex128 (151 MB read, 151 MB written)")
     a = ap.parse_args()
@@ -302,7 +305,8 @@ def main():
     if not a.no_ef:
         out["eigenfunction"] = run_eigenfunction(lib, W)
     if a.paper_3d:
-        out["paper_3d"] = run_paper_3d(lib, W, tuple(x.strip() for x in a.paper_3d.split(",") if x.strip()))
+        out["paper_3d"] = run_paper_3d(lib, W, tuple(x.strip() for x in a.paper_3d.split(",") if x.strip()),
+                                       with_ef=a.paper_3d_ef)
     if not a.no_sweep:
         out["sweep"] = run_sweep(lib, W, net)
     if not a.no_cpu:
@@ -477,31 +481,61 @@ def run_pm_compare(lib, W):
     return res
 
 
-def run_paper_3d(lib, W, cases=("I", "II")):
+def normalised_at_max(u):
+    """u divided by its value at its first point of largest modulus (fixes the
+    phase and makes the maximal modulus 1; the eigenfunction comparison of
+    Sec. 4)."""
+    import numpy as np
+    flat = u.ravel()
+    return u / flat[int(np.argmax(np.abs(flat)))]
+
+
+def run_paper_3d(lib, W, cases=("I", "II"), with_ef=False):
     """Ex. 4.3 (3D lifted to 6D) at the paper's truncations K = 5, L = 10, 20,
     30 and its reference L = 40 (8e6, 6.4e7, 2.16e8 and 5.12e8 window points;
     L >= 20 runs the five-pass schedule, L = 40 with two-stage 80-point axes),
     ground state to eta <= 1e-9 with the float32 convolution.  E_v(L) is
     measured against this build's own L = 40 solution, as the paper measures
-    Table 9 against its IWFPM L = 40 (Sec. 4.3), and printed beside Table 9."""
+    Table 9 against its IWFPM L = 40 (Sec. 4.3), and printed beside Table 9.
+    with_ef: also E_f(L) = max |u_L - u_40| on the 3D observation grid
+    [-5, 5]^3, step 0.1 (101^3 points), both normalised at their maximum."""
     import math
+    import numpy as np
     printed = {"I": {10: 6.82e-4, 20: 1.58e-4, 30: 4.34e-5}, "II": {10: 4.08e-3, 20: 9.91e-4, 30: 2.71e-4}}
+    printed_ef = {"I": {10: 2.88e-4, 20: 1.94e-4, 30: 9.32e-5}, "II": {10: 3.55e-2, 20: 4.84e-3, 30: 2.21e-3}}
     betas = {"I": math.pi, "II": 0.5 * math.pi}
+    grid = ([-5.0] * 3, [0.1] * 3, [101] * 3)
     res = {}
     for case in cases:
-        rows = {}
+        rows, ufun = {}, {}
         for L in (10, 20, 30, 40):
             prob = W.paper_example_3d(betas[case], 5, L)
             print(f"paper_3d case {case} L={L} N={prob.N}", file=sys.stderr, flush=True)
             with lib.Plan.from_problem(prob, precision="fp32") as plan:
-                r, t = _timed(lambda: plan.eigs(1, tol=1e-9, maxit=6000, want_vectors=False))
+                r, t = _timed(lambda: plan.eigs(1, tol=1e-9, maxit=6000, want_vectors=with_ef))
                 rows[L] = {"N": plan.N, "E0": float(r.evals[0]), "iterations": r.iterations, "seconds": t,
                            "eta": float(r.eta[0])}
-            print(f"  E0={rows[L]['E0']:.12f} its={r.iterations} {t:.1f} s", file=sys.stderr, flush=True)
+                print(f"  E0={rows[L]['E0']:.12f} its={rows[L]['iterations']} {rows[L]['seconds']:.1f} s",
+                      file=sys.stderr, flush=True)
+                if with_ef:
+                    u, te = _timed(lambda: plan.eigenfunction(r.evecs[0].contiguous(), *grid).cpu().numpy())
+                    ufun[L] = normalised_at_max(u)
+                    rho = np.abs(u) ** 2
+                    ufun[(L, "rho")] = rho / rho.max()
+                    rows[L]["eigenfunction_seconds"] = te
+                    print(f"  eigenfunction on 101^3 points: {te:.1f} s", file=sys.stderr, flush=True)
+                del r
         e_star = rows[40]["E0"]
         for L in (10, 20, 30):
             rows[L]["E_v"] = (rows[L]["E0"] - e_star) / e_star
             rows[L]["E_v_printed"] = printed[case][L]
+            if with_ef:
+                rows[L]["E_f"] = float(np.max(np.abs(ufun[L] - ufun[40])))
+                # the same on the densities rho = |u|^2 (each over its maximum)
+                rows[L]["E_f_rho"] = float(np.max(np.abs(ufun[(L, "rho")] - ufun[(40, "rho")])))
+                rows[L]["E_f_printed"] = printed_ef[case][L]
+                print(f"  L={L} E_f={rows[L]['E_f']:.3e} E_f(rho)={rows[L]['E_f_rho']:.3e} "
+                      f"(printed {printed_ef[case][L]:.2e})", file=sys.stderr, flush=True)
         res[case] = rows
     return res
 

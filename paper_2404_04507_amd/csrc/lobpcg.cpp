@@ -1944,7 +1944,9 @@ static int lobpcg(int B, iwfpm_plan_s* const* plans, const iwfpm_eigs_opts& o, c
         BInst& b = in[i];
         b.p = plans[i];
         if (m > b.p->geom.N) return IWFPM_ERR_ARG;
-        if ((rc = solver_ensure(b.p, m))) return rc;
+        // block buffers of m trial vectors: m complex columns, or (m + 1) / 2
+        // columns of real pairs
+        if ((rc = solver_ensure(b.p, Rt::columns(m)))) return rc;
         int pk = o.precond == IWFPM_PRECOND_LEARNED ? IWFPM_PRECOND_PLAIN : o.precond;
         if ((rc = solver_precond(b.p, pk))) return rc;
         b.s = (Solver*)b.p->solver;
