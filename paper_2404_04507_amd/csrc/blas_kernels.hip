@@ -219,7 +219,8 @@ __device__ __forceinline__ void lincomb_rows_body(const ColPtrs& A, int p, const
         // the scalar unit; with many outputs per wave an unrolled input loop
         // holds more of them than there are SGPRs (they spill to VGPR lanes),
         // so it runs one input at a time there and relies on occupancy.
-#pragma unroll ((PAIRS && QG >= 4) ? 1 : 4)
+        constexpr int kInUnroll = (PAIRS && QG >= 4) ? 1 : 4;
+#pragma unroll kInUnroll
         for (int i = 0; i < p; ++i) {
             const double2 a = A.p[i][r];
             const double2 a2 = ok2 ? A.p[i][r2] : make_double2(0.0, 0.0);
