@@ -503,6 +503,7 @@ static bool tridiag_lowest(std::vector<double> d, std::vector<double> e, int n, 
     for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
     Y.assign((size_t)n * nv, 0.0);
     for (int c = 0; c < nv; ++c) Y[(size_t)idx[c] * nv + c] = 1.0;
+    if (nv == 0) return true;  // eigenvalues only (Y is empty: no rows to rotate)
     for (size_t t = rots.size(); t-- > 0;) {
         const Rot& q = rots[t];
         double* __restrict yi = &Y[(size_t)q.i * nv];
