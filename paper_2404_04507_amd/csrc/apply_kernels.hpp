@@ -711,6 +711,74 @@ __global__ void __launch_bounds__(256, sizeof(R) == 8 ? 2 : 1) k_pass1(DevGeom g
     pass1_body<R, MAXS>(g, t, pd, rg, psi, ws, blockIdx.x, gridDim.x, smem);
 }
 
+// The middle pass's outermost axis (axis 0, one register pencil) between
+// global memory and the LDS tile: its inverse DFT runs on values loaded from
+// global memory before they first reach the tile, its forward DFT on values
+// read from the tile for the last time, which go to global memory from the
+// registers.  This takes the place of the tile's copy-in and copy-out sweeps
+// and of their barriers.  A thread takes the pencils of two adjacent columns
+// (16-byte accesses); the pair's element j sits at global offset gofs + j gstep
+// and at tile offset lofs + j lstep.
+template <int S, int SIGN, typename R>
+__device__ __forceinline__ void p2_axis0_pair(cplx<R>* __restrict__ w, cplx<R>* tile, int gofs, int gstep, int lofs,
+                                              int lstep) {
+    cplx<R> a[S], b[S];
+    if constexpr (SIGN > 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const CPair<R> v = *reinterpret_cast<const CPair<R>*>(w + gofs + j * gstep);
+            a[j] = v.a;
+            b[j] = v.b;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const CPair<R> v = *reinterpret_cast<const CPair<R>*>(tile + lofs + j * lstep);
+            a[j] = v.a;
+            b[j] = v.b;
+        }
+    }
+    fft_inplace<S, SIGN>(a);
+    fft_inplace<S, SIGN>(b);
+    if constexpr (SIGN > 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) *reinterpret_cast<CPair<R>*>(tile + lofs + j * lstep) = CPair<R>{a[j], b[j]};
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) *reinterpret_cast<CPair<R>*>(w + gofs + j * gstep) = CPair<R>{a[j], b[j]};
+    }
+}
+
+// longest axis 0 taken this way: two pencils of it in registers take 128 VGPRs
+template <typename R>
+constexpr int kAxis0Max = 256 / (int)sizeof(cplx<R>);
+
+// every pencil pair of axis 0 of the tile: count elements in rows of sl = El T
+// (T even), axis 0 of extent S0 stepping R0 = count / (S0 sl) tile rows
+template <int SIGN, typename R, int MAXS>
+__device__ __forceinline__ void p2_axis0(int S0, cplx<R>* __restrict__ w, cplx<R>* tile, int count, int El, int lgT,
+                                         int sin_, RowGeom rg) {
+    const int np2 = count / S0 / 2;
+    const int R0 = count / (S0 * rg.sl);
+    const int T = 1 << lgT;
+    const Div16 dsl(rg.sl);
+    for (int q = threadIdx.x; q < np2; q += blockDim.x) {
+        const int row0 = dsl.div(2 * q), col = 2 * q - row0 * rg.sl;
+        const int gofs = (row0 * El + (col >> lgT)) * sin_ + (col & (T - 1));
+        const int gstep = R0 * El * sin_;
+        const int lofs = row0 * rg.sp + col, lstep = R0 * rg.sp;
+        switch (S0) {
+#define IWFPM_CASE(s)                                                                  \
+    case s:                                                                           \
+        if constexpr (s <= MAXS && s <= kAxis0Max<R>) p2_axis0_pair<s, SIGN, R>(w, tile, gofs, gstep, lofs, lstep); \
+        break;
+            IWFPM_EXTENTS(IWFPM_CASE)
+#undef IWFPM_CASE
+            default: break;
+        }
+    }
+}
+
 // Per-axis potential tables (vmode 0) in the middle pass: the sum over the
 // axes other than the convolution axis (the last leading one) splits into a
 // part fixed by the tile row (the other leading axes) and a part fixed by the
@@ -786,7 +854,12 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     // memory and in LDS (all extents are even, so the pairs stay aligned):
     // they move as one access each, twice the bytes in flight per load.
     const bool pairs = (T & 1) == 0 && tw == T;
-    if (pairs) {
+    // then axis 0, when it is not the convolution axis and is one register
+    // pencil, moves straight between global memory and the tile (p2_axis0)
+    const bool fuse0 = pairs && split >= 2 && g.nfac[0] == 1 && g.ext[0] <= kAxis0Max<R>;
+    if (fuse0) {
+        p2_axis0<+1, R, MAXS>(g.ext[0], w, tile, count, El, lgT, sin_, rg);
+    } else if (pairs) {
         const int count2 = count >> 1;
         for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < count2;) {
             CPair<R> v[kBatch];
@@ -827,7 +900,7 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
     // the tile, then its forward stages
     const bool long_last = g.nfac[split - 1] > 1;
     const int n_inv = long_last ? split : split - 1;
-    for (int ax = 0; ax < n_inv; ++ax) {
+    for (int ax = fuse0 ? 1 : 0; ax < n_inv; ++ax) {
         int es = (g.stride[ax] / sin_) << lgT;
         run_axis_any<+1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
@@ -865,12 +938,14 @@ __device__ __forceinline__ void pass2_body(const DevGeom& g, const DevTabs& t, c
         }
     }
     __syncthreads();
-    for (int ax = n_inv - 1; ax >= 0; --ax) {
+    for (int ax = n_inv - 1; ax >= (fuse0 ? 1 : 0); --ax) {
         int es = (g.stride[ax] / sin_) << lgT;
         run_axis_any<-1, R, MAXS>(g, t, ax, tile, count / g.ext[ax], es, rg);
         __syncthreads();
     }
-    if (pairs) {
+    if (fuse0) {
+        p2_axis0<-1, R, MAXS>(g.ext[0], w, tile, count, El, lgT, sin_, rg);
+    } else if (pairs) {
         const int count2 = count >> 1;
         for (RowIter it(threadIdx.x, blockDim.x, rg.sl >> 1); it.e < count2; it.next(blockDim.x)) {
             const int col = 2 * it.col;
