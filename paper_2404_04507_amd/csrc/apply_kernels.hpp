@@ -749,6 +749,29 @@ __device__ __forceinline__ void p2_axis0_pair(cplx<R>* __restrict__ w, cplx<R>* 
     }
 }
 
+// the same with one column per thread (8-byte accesses for float32), for
+// tiles with fewer column pairs than the workgroup has threads
+template <int S, int SIGN, typename R>
+__device__ __forceinline__ void p2_axis0_one(cplx<R>* __restrict__ w, cplx<R>* tile, int gofs, int gstep, int lofs,
+                                             int lstep) {
+    cplx<R> a[S];
+    if constexpr (SIGN > 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) a[j] = w[gofs + j * gstep];
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) a[j] = tile[lofs + j * lstep];
+    }
+    fft_inplace<S, SIGN>(a);
+    if constexpr (SIGN > 0) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) tile[lofs + j * lstep] = a[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) w[gofs + j * gstep] = a[j];
+    }
+}
+
 // longest axis 0 taken this way: two pencils of it in registers take 128 VGPRs
 template <typename R>
 constexpr int kAxis0Max = 256 / (int)sizeof(cplx<R>);
@@ -762,6 +785,25 @@ __device__ __forceinline__ void p2_axis0(int S0, cplx<R>* __restrict__ w, cplx<R
     const int R0 = count / (S0 * rg.sl);
     const int T = 1 << lgT;
     const Div16 dsl(rg.sl);
+    if (np2 < (int)blockDim.x) {
+        // fewer pairs than threads: one column per thread keeps them all busy
+        for (int p = threadIdx.x; p < 2 * np2; p += blockDim.x) {
+            const int row0 = dsl.div(p), col = p - row0 * rg.sl;
+            const int gofs = (row0 * El + (col >> lgT)) * sin_ + (col & (T - 1));
+            const int gstep = R0 * El * sin_;
+            const int lofs = row0 * rg.sp + col, lstep = R0 * rg.sp;
+            switch (S0) {
+#define IWFPM_CASE(s)                                                                 \
+    case s:                                                                          \
+        if constexpr (s <= MAXS && s <= kAxis0Max<R>) p2_axis0_one<s, SIGN, R>(w, tile, gofs, gstep, lofs, lstep); \
+        break;
+                IWFPM_EXTENTS(IWFPM_CASE)
+#undef IWFPM_CASE
+                default: break;
+            }
+        }
+        return;
+    }
     for (int q = threadIdx.x; q < np2; q += blockDim.x) {
         const int row0 = dsl.div(2 * q), col = 2 * q - row0 * rg.sl;
         const int gofs = (row0 * El + (col >> lgT)) * sin_ + (col & (T - 1));
